@@ -1,0 +1,146 @@
+"""Restarted GMRES(m) with CGS2 Arnoldi and Givens rotations (oracle).
+
+The Krylov method of the paper's Section 2 (minimal residual over the Krylov
+space K_m = span{r0, J r0, ..., J^{m-1} r0}, restarted) in its classical form:
+
+* initial guess x0 = 0; the tolerance is relative to ||rhs||;
+* each restart cycle starts from the true residual r = rhs - J x and stops the
+  whole solve when ||r|| <= tol ||rhs||; at most ``max_restarts`` cycles (the
+  paper's "maximum Krylov iteration count" counts restart cycles);
+* Arnoldi step: w = J v_j, classical Gram-Schmidt applied twice
+  (h = V^T w, w -= V h, h2 = V^T w, w -= V h2, column = h + h2),
+  H[j+1, j] = ||w||;
+* the Hessenberg column is reduced by the previous Givens rotations, a new
+  rotation zeroes H[j+1, j] (c = a/r, s = b/r, r = hypot(a, b); (1, 0) when
+  b = 0) and g is rotated; |g[j+1]| is the residual estimate;
+* the cycle ends when |g[j+1]| <= tol ||rhs||, on a happy breakdown
+  (||w|| <= breakdown_tol * ||J v_j||) or after m steps; then R y = g is
+  back-substituted and x += V y.
+
+"Krylov iterations" counts Arnoldi steps.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class GmresInfo:
+    converged: bool = False
+    iters: int = 0  # Arnoldi steps over all cycles
+    cycles: int = 0  # restart cycles run
+    nonfinite: bool = False
+    breakdowns: int = 0
+    true_res: list = field(default_factory=list)  # ||rhs - J x|| at the top of each cycle
+    est_res: list = field(default_factory=list)  # |g[j+1]| after every Arnoldi step
+    last_V: list | None = None  # basis of the last cycle (when record=True)
+    last_H: np.ndarray | None = None  # unrotated Hessenberg of the last cycle
+    last_k: int = 0
+
+
+def givens(a: float, b: float) -> tuple[float, float]:
+    """Rotation (c, s) with [c s; -s c] [a; b] = [r; 0]."""
+    if b == 0.0:
+        return 1.0, 0.0
+    r = math.hypot(a, b)
+    return a / r, b / r
+
+
+def back_substitute(R: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """Solve the upper-triangular system R y = g."""
+    k = g.shape[0]
+    y = np.zeros(k)
+    for i in range(k - 1, -1, -1):
+        s = g[i]
+        for l in range(i + 1, k):
+            s -= R[i, l] * y[l]
+        y[i] = s / R[i, i]
+    return y
+
+
+def gmres(matvec, rhs: np.ndarray, m: int = 30, tol: float = 1e-8, max_restarts: int = 100,
+          breakdown_tol: float = 1e-14, record: bool = False):
+    """Solve J x = rhs; returns (x, GmresInfo)."""
+    n = rhs.shape[0]
+    x = np.zeros(n)
+    info = GmresInfo()
+    bnorm = float(np.linalg.norm(rhs))
+    if not math.isfinite(bnorm):
+        info.nonfinite = True
+        return x, info
+    if bnorm == 0.0:
+        info.converged = True
+        info.true_res.append(0.0)
+        return x, info
+    target = tol * bnorm
+    for cycle in range(max_restarts + 1):
+        r = rhs.copy() if cycle == 0 else rhs - matvec(x)
+        beta = float(np.linalg.norm(r))
+        info.true_res.append(beta)
+        if not math.isfinite(beta):
+            info.nonfinite = True
+            return x, info
+        if beta <= target:
+            info.converged = True
+            return x, info
+        if cycle == max_restarts:
+            return x, info
+        info.cycles += 1
+        V = [r / beta]
+        H = np.zeros((m + 1, m))  # rotated in place
+        Hraw = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            w = matvec(V[j])
+            jv_norm = float(np.linalg.norm(w))
+            # classical Gram-Schmidt, twice
+            h = np.array([np.dot(V[i], w) for i in range(j + 1)])
+            for i in range(j + 1):
+                w = w - h[i] * V[i]
+            h2 = np.array([np.dot(V[i], w) for i in range(j + 1)])
+            for i in range(j + 1):
+                w = w - h2[i] * V[i]
+            col = h + h2
+            wnorm = float(np.linalg.norm(w))
+            Hraw[: j + 1, j] = col
+            Hraw[j + 1, j] = wnorm
+            H[: j + 1, j] = col
+            H[j + 1, j] = wnorm
+            if not (np.all(np.isfinite(col)) and math.isfinite(wnorm)):
+                info.nonfinite = True
+                return x, info
+            # previous rotations
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            info.iters += 1
+            info.est_res.append(abs(g[j + 1]))
+            if abs(g[j + 1]) <= target:
+                break
+            if wnorm <= breakdown_tol * jv_norm:
+                info.breakdowns += 1
+                break
+            V.append(w / wnorm)
+        y = back_substitute(H[:k, :k], g[:k])
+        for i in range(k):
+            x = x + y[i] * V[i]
+        if record:
+            info.last_V = [vv.copy() for vv in V]
+            info.last_H = Hraw[: k + 1, :k].copy()
+            info.last_k = k
+    return x, info

@@ -1,0 +1,156 @@
+"""Inexact Newton with backtracking line search (oracle).
+
+Paper, Section 2: linearize F(x^k) at each iterate, solve J(x^k) dx = -F(x^k)
+with the Krylov method (J only through JVPs), stop when
+||F(x^k, x*)|| / ||F(x*, x*)|| < tol_Newton, and damp the update to
+x^{k+1} = x^k + alpha dx with alpha reduced until the residual norm decreases
+sufficiently.  The paper leaves the line-search constants open; the reading
+taken here: Armijo condition ||F(x + alpha dx)|| <= (1 - c alpha) ||F(x)||
+with c = 1e-4, alpha halved at most ``ls_max_backtracks`` times, and if no
+trial passes the last one (alpha = 2^-ls_max_backtracks) is taken and counted
+as a line-search failure.  A non-finite residual at an accepted iterate, or in
+the Krylov solve, fails the solve.
+
+Run-level failure rule (Section 3.4): an implicit step "fails" when its final
+relative residual exceeds 100 tol_Newton; a run of several steps fails when
+more than 20% of its steps fail, or on non-finite values.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gmres as gm
+from .jvp import EPS_MACH, EPS_PAPER, fd_step, jvp_ad, jvp_fd
+from .problems import Problem, residual
+
+OK = "ok"
+NONFINITE = "nonfinite"
+NOT_CONVERGED = "not_converged"
+
+
+@dataclass
+class NewtonOptions:
+    mode: str = "ad"  # 'ad' | 'fd'
+    m: int = 30
+    tol_newton: float = 1e-6
+    tol_krylov: float = 1e-8
+    max_newton: int = 15
+    max_restarts: int = 100
+    ls_c: float = 1e-4
+    ls_max_backtracks: int = 10
+    eps_rule: str = EPS_PAPER
+    eps_mach: float = EPS_MACH["f64"]
+    fd_eps: float = 0.0  # > 0: fixed FD step
+    breakdown_tol: float = 1e-14
+
+    @classmethod
+    def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
+        """Tolerances per precision (paper Section 3.3): FP64 1e-6 / 1e-8, FP32 1e-4 / 1e-6."""
+        if precision == "f64":
+            base = dict(tol_newton=1e-6, tol_krylov=1e-8, eps_mach=EPS_MACH["f64"], breakdown_tol=1e-14)
+        else:
+            base = dict(tol_newton=1e-4, tol_krylov=1e-6, eps_mach=EPS_MACH[precision], breakdown_tol=1e-6)
+        base.update(kw)
+        return cls(**base)
+
+
+@dataclass
+class NewtonInfo:
+    status: str = NOT_CONVERGED
+    converged: bool = False
+    newton_iters: int = 0
+    krylov_iters: int = 0
+    restarts: int = 0
+    ls_backtracks: int = 0
+    ls_failures: int = 0
+    rel_res: list = field(default_factory=list)  # rho_k = ||F(x_k)|| / ||F(x_0)||, k = 0..
+    alphas: list = field(default_factory=list)
+    lin_iters: list = field(default_factory=list)
+    iterates: list = field(default_factory=list)  # x_k (when record=True)
+    f0_norm: float = 0.0
+
+
+def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=None,
+                 x0: np.ndarray | None = None, record: bool = False):
+    """Solve F(x; x*) = 0 starting from x0 (default x* = x_prev); returns (x, NewtonInfo)."""
+    x = (x_prev if x0 is None else x0).astype(np.float64).copy()
+    info = NewtonInfo()
+    F = residual(p, x, x_prev, source)
+    n0 = float(np.linalg.norm(F))
+    info.f0_norm = n0
+    fk = n0
+    if record:
+        info.iterates.append(x.copy())
+    k = 0
+    while True:
+        if not math.isfinite(fk):
+            info.status = NONFINITE
+            return x, info
+        rho = fk / n0 if n0 > 0.0 else 0.0
+        info.rel_res.append(rho)
+        if rho < opts.tol_newton:
+            info.status = OK
+            info.converged = True
+            return x, info
+        if k == opts.max_newton:
+            info.status = NOT_CONVERGED
+            return x, info
+
+        if opts.mode == "ad":
+            def matvec(v, _x=x):
+                return jvp_ad(p, _x, v, x_prev, source)[1]
+        else:
+            Fx = F
+
+            def matvec(v, _x=x, _F=Fx):
+                eps = opts.fd_eps if opts.fd_eps > 0.0 else fd_step(opts.eps_rule, opts.eps_mach, _x, v)
+                return jvp_fd(p, _x, v, eps, x_prev, source, Fx=_F)
+
+        dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
+                             max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol)
+        info.krylov_iters += ginfo.iters
+        info.restarts += ginfo.cycles
+        info.lin_iters.append(ginfo.iters)
+        if ginfo.nonfinite:
+            info.status = NONFINITE
+            return x, info
+
+        alpha = 1.0
+        accepted = False
+        for t in range(opts.ls_max_backtracks + 1):
+            xt = x + alpha * dx
+            Ft = residual(p, xt, x_prev, source)
+            ft = float(np.linalg.norm(Ft))
+            if math.isfinite(ft) and ft <= (1.0 - opts.ls_c * alpha) * fk:
+                accepted = True
+                break
+            if t < opts.ls_max_backtracks:
+                alpha *= 0.5
+                info.ls_backtracks += 1
+        if not accepted:
+            info.ls_failures += 1
+        info.alphas.append(alpha)
+        x, F, fk = xt, Ft, ft
+        k += 1
+        info.newton_iters = k
+        if record:
+            info.iterates.append(x.copy())
+
+
+def step_failed(info: NewtonInfo, tol_newton: float) -> bool:
+    """A time step fails if its final relative residual is above 100 tol_Newton or non-finite."""
+    if info.status == NONFINITE or not info.rel_res:
+        return True
+    return not (info.rel_res[-1] <= 100.0 * tol_newton)
+
+
+def run_failed(step_infos: list, tol_newton: float) -> bool:
+    """A multi-step run fails when more than 20% of its steps fail, or on a non-finite step."""
+    if any(i.status == NONFINITE for i in step_infos):
+        return True
+    bad = sum(step_failed(i, tol_newton) for i in step_infos)
+    return bad > 0.2 * len(step_infos)

@@ -1,0 +1,118 @@
+"""Planted mistakes in the oracle must fail its pins.
+
+Each case patches one plausible mistake into the oracle (a sign, a dropped
+term, a transposed operand, a wrong index) and runs the pin that should catch
+it; the pin must raise.  This shows the pins constrain every part they claim.
+"""
+
+import numpy as np
+import pytest
+
+import oracle.dual as odual
+import oracle.gmres as ogm
+import oracle.jvp as ojvp
+import oracle.problems as oprob
+import test_oracle_gmres as tg
+import test_oracle_jvp as tj
+import test_oracle_newton as tn
+import test_oracle_residual as tr
+
+
+def _expect_failure(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_sign_of_first_difference(monkeypatch):
+    monkeypatch.setattr(oprob, "d1", lambda f, h, axis: (oprob.roll(f, 1, axis) - oprob.roll(f, -1, axis)) / (2 * h))
+    _expect_failure(tr.test_burgers1d_fourier_mode, 1.0)
+    _expect_failure(tr.test_burgers2d_taylor_green_crank_nicolson)
+
+
+def test_dropped_factor_in_second_difference(monkeypatch):
+    monkeypatch.setattr(oprob, "d2", lambda f, h, axis: (oprob.roll(f, -1, axis) - f + oprob.roll(f, 1, axis)) / (h * h))
+    _expect_failure(tr.test_grayscott_mode_and_pointwise_terms)
+    _expect_failure(tj.test_ad_columns_equal_analytic_jacobian, tj.tiny_cases()[2])
+
+
+def test_laplacian_missing_a_direction(monkeypatch):
+    monkeypatch.setattr(oprob, "lap", lambda f, p: oprob.d2(f, p.hx, 1) + oprob.d2(f, p.hx, 0))  # hy -> hx
+    spec = tj.tiny_cases()[2]  # hx != hy? make it so
+    spec = dict(spec, hy=spec["hx"] * 1.7)
+    _expect_failure(tj.test_ad_columns_equal_analytic_jacobian, spec)
+
+
+def test_product_rule_missing_a_term(monkeypatch):
+    def bad_mul(self, o):
+        if isinstance(o, odual.Dual):
+            return odual.Dual(self.val * o.val, self.tan * o.val)
+        return odual.Dual(self.val * o, self.tan * o)
+    monkeypatch.setattr(odual.Dual, "__mul__", bad_mul)
+    for spec in tj.tiny_cases():
+        _expect_failure(tj.test_ad_equals_complex_step, spec)
+
+
+def test_fd_quotient_scaled_wrong(monkeypatch):
+    orig = ojvp.jvp_fd
+    monkeypatch.setattr(ojvp, "jvp_fd", lambda *a, **k: 0.5 * orig(*a, **k))
+    monkeypatch.setattr(tj, "jvp_fd", ojvp.jvp_fd)
+    _expect_failure(tj.test_fd_minus_ad_truncation_closed_form, tj.tiny_cases()[0])
+
+
+def test_givens_sign(monkeypatch):
+    orig = ogm.givens
+    monkeypatch.setattr(ogm, "givens", lambda a, b: (orig(a, b)[0], -orig(a, b)[1]))
+    # restarts from the true residual still reach the answer; the estimate pin catches it
+    _expect_failure(tg.test_givens_estimate_equals_true_residual)
+    _expect_failure(tg.test_exact_termination_with_few_distinct_eigenvalues)
+
+
+def test_back_substitution_transposed(monkeypatch):
+    orig = ogm.back_substitute
+    monkeypatch.setattr(ogm, "back_substitute", lambda R, g: orig(np.ascontiguousarray(R.T), g))
+    _expect_failure(tg.test_givens_estimate_equals_true_residual)
+    _expect_failure(tg.test_exact_termination_with_few_distinct_eigenvalues)
+
+
+def test_single_gram_schmidt_pass_loses_orthogonality(monkeypatch):
+    # replace the second CGS pass by nothing: dot products against a perturbed basis
+    calls = {"n": 0}
+    orig_dot = np.dot
+
+    def noisy_dot(a, b):
+        calls["n"] += 1
+        return orig_dot(a, b) * (1 + 1e-6)
+    monkeypatch.setattr(ogm.np, "dot", noisy_dot)
+    _expect_failure(tg.test_orthonormal_basis_and_arnoldi_relation)
+
+
+def test_kerr_boundary_mask_wrong(monkeypatch):
+    def bad_mask(p):
+        m = np.zeros((p.ny, p.nx))
+        m[1:, 1:-1] = 1.0  # forgets the top boundary row
+        return m
+    monkeypatch.setattr(oprob, "interior_mask", bad_mask)
+    _expect_failure(tr.test_kerr_boundary_rows_hold_the_field)
+
+
+def test_wrong_time_level_in_theta_scheme(monkeypatch):
+    orig = oprob.N_apply
+    # evaluate the old-level operator at the new level: x_prev ignored
+    monkeypatch.setattr(oprob, "N_apply", lambda p, x: orig(p, x) * 1.0 if x is not None else None)
+    orig_res = oprob.residual
+
+    def bad_residual(p, x, x_prev, source=None):
+        return orig_res(p, x, x, source) + (x - x_prev) * 0 + (x - x_prev)
+    monkeypatch.setattr(tr, "residual", bad_residual)
+    _expect_failure(tr.test_burgers2d_taylor_green_crank_nicolson)
+
+
+def test_line_search_that_accepts_every_step(monkeypatch):
+    # a sufficient-decrease constant that accepts any step never backtracks
+    import dataclasses
+    from oracle import newton as onewton
+
+    def opts(**kw):
+        return dataclasses.replace(onewton.NewtonOptions(**kw), ls_c=-1e30)
+    monkeypatch.setattr(tn, "NewtonOptions", opts)
+    _expect_failure(tn.test_line_search_armijo_and_halving)

@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only draws random numbers and lays out grids.  It holds none of the
+method's arithmetic (no residual, no derivative, no Krylov or Newton step), so
+the CPU oracle and the HIP path can both take their inputs from here without
+sharing any code that computes the method.
+
+Every generator takes an explicit seed and uses ``numpy.random.default_rng``.
+State vectors are flat float64 arrays in the layout both sides use:
+
+* 1D Burgers: ``u[i]``, ``i = 0..nx-1``.
+* 2D two-field problems (Burgers, Gray-Scott): two planes, each row-major,
+  ``x[f*nx*ny + j*nx + i]`` for field ``f``, row ``j`` (y), column ``i`` (x).
+* Helmholtz-Kerr: complex field, real and imaginary parts interleaved,
+  ``x[2*(j*nx + i) + c]`` with ``c = 0`` (real) or ``1`` (imaginary).
+
+The parameter sets follow the paper's benchmark problems (its Section 3.2 and
+Appendix A) where the paper fixes them, and the workload definitions of this
+project otherwise; every choice the paper leaves open is listed with its
+reading in the design notes.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Problem specifications (plain numbers; both sides build their own objects)
+# ---------------------------------------------------------------------------
+
+
+def burgers1d_spec(nx: int = 256, nu: float = 0.01, dt: float = 1e-3, theta: float = 1.0) -> dict:
+    """1D viscous Burgers on [0,1) periodic, h = 1/nx (backward Euler by default)."""
+    return dict(kind="burgers1d", nx=nx, ny=1, hx=1.0 / nx, hy=1.0, dt=dt, theta=theta, nu=nu)
+
+
+def burgers2d_spec(n: int = 2048, nu: float = 1e-3, dt: float = 5e-4, theta: float = 0.5) -> dict:
+    """2D viscous Burgers on [0,2pi)^2 periodic (Crank-Nicolson by default, Appendix A.1)."""
+    h = 2.0 * math.pi / n
+    return dict(kind="burgers2d", nx=n, ny=n, hx=h, hy=h, dt=dt, theta=theta, nu=nu)
+
+
+def grayscott_spec(n: int = 1024, D: float = 2e-5, Dv: float = 1e-5, F: float = 0.04, k: float = 0.06,
+                   dt: float = 1.0, theta: float = 1.0, h: float | None = None) -> dict:
+    """Gray-Scott two-species reaction-diffusion, periodic.
+
+    The grid spacing defaults to h = sqrt(D*dt), i.e. a diffusion Courant number
+    of one in the paper's reaction-diffusion rule dt = C h^2 / D with C = 1.
+    """
+    if h is None:
+        h = math.sqrt(D * dt)
+    return dict(kind="grayscott", nx=n, ny=n, hx=h, hy=h, dt=dt, theta=theta, D=D, Dv=Dv, F=F, k=k)
+
+
+def kerr_spec(n: int = 1024, chi3: float = 0.1, eps_re: float = 1.0, eps_im: float = 0.0,
+              cells_per_wavelength: float = 64.0) -> dict:
+    """Scalar Helmholtz-Kerr on an n x n node grid, PEC boundary nodes, h = 1 (grid units)."""
+    return dict(kind="kerr", nx=n, ny=n, hx=1.0, hy=1.0, dt=0.0, theta=1.0,
+                k0=2.0 * math.pi / cells_per_wavelength, eps_re=eps_re, eps_im=eps_im, chi3=chi3)
+
+
+def n_unknowns(spec: dict) -> int:
+    """Number of real unknowns of a problem spec."""
+    cells = spec["nx"] * spec["ny"]
+    return cells if spec["kind"] == "burgers1d" else 2 * cells
+
+
+# ---------------------------------------------------------------------------
+# Initial data and sources
+# ---------------------------------------------------------------------------
+
+
+def burgers1d_initial(nx: int = 256, seed: int = 0, noise: float = 1e-3) -> np.ndarray:
+    """u0 = sin(2 pi x_i) + noise * N(0,1), x_i = i/nx."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx, dtype=np.float64) / nx
+    return np.sin(2.0 * np.pi * x) + noise * rng.standard_normal(nx)
+
+
+def grayscott_initial(n: int = 1024, seed: int = 0, patches: int = 16, side_frac: float = 1.0 / 32,
+                      noise: float = 0.01, ny: int | None = None) -> np.ndarray:
+    """Background (u, v) = (0, 1) with square patches (0.25, 0.5) plus Gaussian noise.
+
+    ``patches`` squares of side ``max(1, round(n*side_frac))`` cells are placed
+    at seeded positions (periodic wrap); both fields then get ``noise*N(0,1)``.
+    """
+    ny = n if ny is None else ny
+    nx = n
+    rng = np.random.default_rng(seed)
+    u = np.zeros((ny, nx))
+    v = np.ones((ny, nx))
+    side = max(1, int(round(min(nx, ny) * side_frac)))
+    for _ in range(patches):
+        j0 = int(rng.integers(0, ny))
+        i0 = int(rng.integers(0, nx))
+        rows = (j0 + np.arange(side)) % ny
+        cols = (i0 + np.arange(side)) % nx
+        u[np.ix_(rows, cols)] = 0.25
+        v[np.ix_(rows, cols)] = 0.5
+    u += noise * rng.standard_normal((ny, nx))
+    v += noise * rng.standard_normal((ny, nx))
+    return np.concatenate([u.ravel(), v.ravel()])
+
+
+def burgers2d_initial(n: int = 2048, seed: int = 0, modes: int = 32, kmax: int = 8,
+                      energy: float = 0.5) -> np.ndarray:
+    """Random-Fourier velocity field on [0,2pi)^2 with mean kinetic energy ``energy``.
+
+    Each component is a sum of ``modes`` waves a_m cos(k_m . x + phi_m) with
+    integer wavevectors k_m drawn from {-kmax..kmax}^2 without the origin,
+    a_m ~ N(0,1)/|k_m| and phi_m ~ U[0, 2pi).  The pair is then scaled so that
+    0.5 * mean(u^2 + v^2) equals ``energy``.
+    """
+    rng = np.random.default_rng(seed)
+    h = 2.0 * np.pi / n
+    coord = np.arange(n) * h
+    X = coord[None, :]
+    Y = coord[:, None]
+    comps = []
+    for _ in range(2):
+        f = np.zeros((n, n))
+        for _m in range(modes):
+            while True:
+                kx, ky = (int(t) for t in rng.integers(-kmax, kmax + 1, size=2))
+                if kx != 0 or ky != 0:
+                    break
+            amp = rng.standard_normal() / math.hypot(kx, ky)
+            phi = rng.uniform(0.0, 2.0 * np.pi)
+            f += amp * np.cos(kx * X + ky * Y + phi)
+        comps.append(f)
+    u, v = comps
+    ke = 0.5 * np.mean(u * u + v * v)
+    s = math.sqrt(energy / ke)
+    return np.concatenate([(s * u).ravel(), (s * v).ravel()])
+
+
+def taylor_green(n: int) -> np.ndarray:
+    """Taylor-Green vortex u = sin x cos y, v = -cos x sin y on [0,2pi)^2 (Appendix A.1)."""
+    h = 2.0 * np.pi / n
+    c = np.arange(n) * h
+    X = c[None, :]
+    Y = c[:, None]
+    u = np.sin(X) * np.cos(Y)
+    v = -np.cos(X) * np.sin(Y)
+    return np.concatenate([u.ravel(), v.ravel()])
+
+
+def kerr_gaussian_source(n: int = 1024, amp: float = 0.1, sigma: float = 4.0,
+                         center: tuple[float, float] | None = None, ny: int | None = None) -> np.ndarray:
+    """Real Gaussian source f on the node grid, zero on the PEC boundary, interleaved complex."""
+    ny = n if ny is None else ny
+    nx = n
+    cx = (nx - 1) / 2.0 if center is None else center[0]
+    cy = (ny - 1) / 2.0 if center is None else center[1]
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    g = amp * np.exp(-((i - cx) ** 2 + (j - cy) ** 2) / (2.0 * sigma * sigma))
+    g[0, :] = 0.0
+    g[-1, :] = 0.0
+    g[:, 0] = 0.0
+    g[:, -1] = 0.0
+    out = np.zeros((ny, nx, 2))
+    out[..., 0] = g
+    return out.ravel()
+
+
+def random_vector(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """A seeded N(0, scale^2) vector (Krylov directions and generic test data)."""
+    return scale * np.random.default_rng(seed).standard_normal(n)
+
+
+# ---------------------------------------------------------------------------
+# Named configurations
+# ---------------------------------------------------------------------------
+
+
+def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.ndarray, np.ndarray | None]:
+    """Return (spec, x_prev, source) for a named workload, optionally at another size.
+
+    Names: ``burgers1d`` (N=256 by default), ``grayscott`` (1024^2),
+    ``burgers2d`` (2048^2), ``kerr`` (1024^2, chi3 = 0.1).
+    """
+    if name == "burgers1d":
+        nx = 256 if n is None else n
+        spec = burgers1d_spec(nx)
+        return spec, burgers1d_initial(nx, seed), None
+    if name == "grayscott":
+        nn = 1024 if n is None else n
+        spec = grayscott_spec(nn)
+        return spec, grayscott_initial(nn, seed), None
+    if name == "burgers2d":
+        nn = 2048 if n is None else n
+        spec = burgers2d_spec(nn)
+        return spec, burgers2d_initial(nn, seed), None
+    if name == "kerr":
+        nn = 1024 if n is None else n
+        spec = kerr_spec(nn)
+        return spec, np.zeros(2 * nn * nn), kerr_gaussian_source(nn)
+    raise KeyError(name)
+
+
+def serving_stream(count: int = 2000, seed: int = 0, rate: float = 1.0) -> list[dict]:
+    """Poisson stream of implicit-step requests mixing 1D Burgers and 2D Gray-Scott.
+
+    Each request: type Bernoulli(1/2); 1D Burgers N = 2^e, e ~ U{8..16}, with
+    dt(N) = 1e-3 (256/N)^2 (keeping the N=256 diffusion number); Gray-Scott side
+    2^e, e ~ U{6..10}.  Arrival gaps are exponential with mean 1/rate seconds.
+    Initial data come from the per-request seed.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        kind = "burgers1d" if rng.random() < 0.5 else "grayscott"
+        if kind == "burgers1d":
+            e = int(rng.integers(8, 17))
+            size = 2 ** e
+        else:
+            e = int(rng.integers(6, 11))
+            size = 2 ** e
+        out.append(dict(id=r, arrival=t, kind=kind, size=size, seed=int(rng.integers(0, 2**31 - 1))))
+    return out
+
+
+def serving_request_inputs(req: dict) -> tuple[dict, np.ndarray]:
+    """(spec, x_prev) of one serving request."""
+    if req["kind"] == "burgers1d":
+        nx = req["size"]
+        spec = burgers1d_spec(nx, dt=1e-3 * (256.0 / nx) ** 2)
+        return spec, burgers1d_initial(nx, req["seed"])
+    n = req["size"]
+    spec = grayscott_spec(n)
+    return spec, grayscott_initial(n, req["seed"])
