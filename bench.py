@@ -1,0 +1,254 @@
+"""Benchmark of the JFNK hot path on one MI355X.
+
+Workload: implicit (backward-Euler) step of the two-species Gray-Scott
+reaction-diffusion system on a 1024 x 1024 periodic grid (D = 2e-5,
+Dv = 1e-5, F = 0.04, k = 0.06, dt = 1, h = sqrt(D dt)), seeded random square
+patches, solved by Newton with line search around GMRES(30) with CGS2 Arnoldi
+and FP64 Givens.  One step = one whole Newton solve of that implicit step
+(residuals, JVPs, every Arnoldi pass, Givens, V y updates, line search), with
+the inputs resident in HBM before the timed region starts.
+
+The headline line is the AD JVP in FP32 working precision (FP64 Givens,
+Newton update and merit norm); FP64 and FD variants, the JVP bandwidth of
+the AD and FD kernels, per-solve latency percentiles, the roofline of the
+kernel that takes most of the time, and the CPU oracle timed on the host
+are reported on the same JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+CONFIG_NAME = "grayscott-1024x1024-backward-euler"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    s = sorted(xs)
+    if not s:
+        return float("nan")
+    k = (len(s) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def make_solver(spec, prec, xp, torch):
+    from paper_2605_13378_amd import Solver
+
+    s = Solver(spec, prec, m=30)
+    s.set_previous(torch.tensor(xp, dtype=torch.float64, device="cuda"))
+    return s
+
+
+def options_for(prec: str, mode: str) -> dict:
+    # the Gray-Scott workload takes the normalized FD step rule
+    return dict(mode=mode, eps_rule="normalized")
+
+
+def run_solves(s, x0, torch, count, opts, sync_each=True):
+    """Run `count` Newton solves; returns (elapsed seconds, per-solve latencies, last info)."""
+    lat = []
+    info = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(count):
+        t1 = time.perf_counter()
+        _, info = s.newton_solve(x0, **opts)
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, info
+
+
+def jvp_bandwidth(s, torch, n, prec, mode, reps=200):
+    """Average duration (HIP events on the solver stream) and algorithmic GB/s of one JVP kind."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = 1.0 + 0.1 * torch.randn(n, device="cuda", dtype=dt, generator=g)
+    v = torch.randn(n, device="cuda", dtype=dt, generator=g)
+    for _ in range(5):
+        s.jvp(x, v, mode=mode)
+    s.profile_reset()
+    s.profile(True)
+    for _ in range(reps):
+        s.jvp(x, v, mode=mode)
+    torch.cuda.synchronize()
+    st = s.profile_read()["jvp_ad" if mode == "ad" else "jvp_fd"]
+    s.profile(False)
+    s.profile_reset()
+    avg_us = st["ms"] * 1e3 / max(1, st["launches"])
+    gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9 if st["ms"] > 0 else 0.0
+    return dict(avg_us=round(avg_us, 3), gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4),
+                bytes_per_launch=st["bytes"] / max(1, st["launches"]), launches=st["launches"])
+
+
+def cpu_baseline(spec, xp, prec):
+    """The oracle, single-threaded, on one full Newton solve of the same workload."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import NewtonOptions, Problem, newton_solve
+
+    p = Problem.from_spec(spec)
+    o = NewtonOptions.for_precision(prec, mode="ad", eps_rule="normalized")
+    import contextlib
+
+    with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
+        t0 = time.perf_counter()
+        _, info = newton_solve(p, xp, o)
+        el = time.perf_counter() - t0
+    return dict(value=round(1.0 / el, 5), unit="Newton solves/s", cores=1, kind="oracle",
+                sample=f"1 full Newton solve (AD, {prec.upper()} tolerances, FP64 arithmetic) of the "
+                       f"Gray-Scott 1024^2 implicit step; {info.newton_iters} Newton / "
+                       f"{info.krylov_iters} GMRES iterations in {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the JFNK hot path of this "
+              f"package is single-GPU by design", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    spec, xp, _ = W.config("grayscott", seed=0)
+    n = W.n_unknowns(spec)
+    prec = args.precision
+    x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
+
+    # ---- headline: AD JVP, working precision `prec` ------------------------
+    s = make_solver(spec, prec, xp, torch)
+    opts = options_for(prec, "ad")
+    log(f"[bench] warmup {args.warmup} solves ({prec}, AD)")
+    run_solves(s, x0, torch, args.warmup, opts)
+    log(f"[bench] timed {args.steps} solves")
+    elapsed, lat, info = run_solves(s, x0, torch, args.steps, opts)
+    value = args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    log(f"[bench] {value:.2f} solves/s, {ms_per_step:.3f} ms/solve, newton {info['newton_iters']}, "
+        f"krylov {info['krylov_iters']}, converged {info['converged']}")
+
+    # ---- the same timed region again with HIP events around every kernel ----
+    log("[bench] profiled pass (HIP events)")
+    s.profile_reset()
+    s.profile(True)
+    p_el, _, _ = run_solves(s, x0, torch, args.steps, opts)
+    stats = s.profile_read()
+    s.profile(False)
+    total_ms = sum(v["ms"] for v in stats.values())
+    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    dom_avg_us = dom["ms"] * 1e3 / max(1, dom["launches"])
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    kernels = {k: dict(launches=v["launches"], ms=round(v["ms"], 3),
+                       avg_us=round(v["ms"] * 1e3 / max(1, v["launches"]), 3),
+                       gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0.0,
+                       share=round(v["ms"] / total_ms, 4) if total_ms > 0 else 0.0)
+               for k, v in stats.items() if v["launches"]}
+    roofline = dict(bound="hbm", kernel=dom_name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None, avg_us=round(dom_avg_us, 3),
+                    launches=dom["launches"], bytes_per_launch_avg=dom["bytes"] / max(1, dom["launches"]))
+
+    # ---- JVP bandwidth: AD vs FD -------------------------------------------
+    jvp = {}
+    for pr in ("f32", "f64"):
+        sj = s if pr == prec else make_solver(spec, pr, xp, torch)
+        for mode in ("ad", "fd"):
+            jvp[f"{pr}-{mode}"] = jvp_bandwidth(sj, torch, n, pr, mode)
+            log(f"[bench] jvp {pr}-{mode}: {jvp[f'{pr}-{mode}']}")
+        if sj is not s:
+            sj.close()
+
+    # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
+    variants = {}
+    if not args.no_variants:
+        for pr in ("f32", "f64"):
+            sv = s if pr == prec else make_solver(spec, pr, xp, torch)
+            for mode in ("ad", "fd"):
+                o = options_for(pr, mode)
+                run_solves(sv, x0, torch, 1, o)
+                budget = 8.0
+                cnt = 0
+                t_all = 0.0
+                lat_v = []
+                inf = None
+                while t_all < budget and cnt < args.steps:
+                    el, l1, inf = run_solves(sv, x0, torch, 1, o)
+                    t_all += el
+                    lat_v += l1
+                    cnt += 1
+                variants[f"{pr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
+                                                p50_ms=round(1e3 * percentile(lat_v, 0.5), 3),
+                                                p99_ms=round(1e3 * percentile(lat_v, 0.99), 3),
+                                                newton_iters=inf["newton_iters"], krylov_iters=inf["krylov_iters"],
+                                                converged=inf["converged"], final_rel_res=inf["rel_res"][-1])
+                log(f"[bench] variant {pr}-{mode}: {variants[f'{pr}-{mode}']}")
+            if sv is not s:
+                sv.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (1 solve)")
+        cpu = cpu_baseline(spec, xp, prec)
+        log(f"[bench] cpu: {cpu}")
+
+    out = {
+        "metric": "Newton solves/sec and JVP HBM GB/s, AD vs FD, FP64/FP32/FP16; p99 latency",
+        "value": round(value, 3),
+        "unit": "Newton solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": CONFIG_NAME, "grid": [1024, 1024], "unknowns": n, "jvp": "ad",
+                   "krylov": "GMRES(30) CGS2, FP64 Givens", "tol_newton": 1e-4 if prec == "f32" else 1e-6,
+                   "tol_krylov": 1e-6 if prec == "f32" else 1e-8, "seed": 0},
+        "latency_ms": {"p50": round(1e3 * percentile(lat, 0.5), 3), "p99": round(1e3 * percentile(lat, 0.99), 3)},
+        "newton_iters": info["newton_iters"],
+        "krylov_iters": info["krylov_iters"],
+        "roofline": roofline,
+        "kernels": kernels,
+        "profiled_pass_ms_per_step": round(1e3 * p_el / args.steps, 4),
+        "jvp": jvp,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * jfnk.h — C ABI of the MI355X (gfx950) Jacobian-free Newton-Krylov hot path.
+ *
+ * Method (Pasquale & Markidis, "Robust Matrix-Free Newton-Krylov Solvers via
+ * Automatic Differentiation"):
+ *   - the discrete residual F(x^k, x*) of a PDE after space and time
+ *     discretization (paper, Section 2; Appendix A);
+ *   - the Newton step J(x^k) dx = -F(x^k), solved by restarted GMRES that sees
+ *     J only through Jacobian-vector products (Section 2; Section 3.1);
+ *   - the JVP either by forward-mode AD (value + tangent carried together
+ *     through the residual, the paper's AD jvp pair) or by finite differences
+ *     (F(x + eps v) - F(x)) / eps with eps from the paper's step-size rule;
+ *   - the stopping test ||F(x^k)|| / ||F(x*)|| < tol_Newton and a backtracking
+ *     line search x^{k+1} = x^k + alpha dx (Section 2).
+ *
+ * Everything runs on one GPU in hand-written HIP kernels; this header is the
+ * whole boundary.  Conventions for every call:
+ *   - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *     with the length n implied by the problem (see jfnk_problem) and the
+ *     element type implied by the solver's precision:
+ *        working vectors (x, v, F, Jv, rhs, dx):  double for JFNK_F64,
+ *                                                 float  for JFNK_F32 / JFNK_F16S;
+ *        state arrays (x_prev, source, Newton x): always double.
+ *     Any alignment is accepted (16-byte alignment takes the vectorized path).
+ *   - Layout of a state vector: 1D Burgers u[i]; two-field 2D problems as two
+ *     row-major planes (field f, row j, column i at f*nx*ny + j*nx + i);
+ *     Helmholtz-Kerr as interleaved complex (re, im) pairs at 2*(j*nx+i)+c.
+ *   - No call retains a caller pointer after it returns.  The solver handle
+ *     owns its workspace (Krylov basis, Hessenberg, scratch).
+ *   - jfnk_residual and jfnk_jvp are asynchronous on the solver's HIP stream:
+ *     the caller keeps the buffers alive until that stream is synchronized.
+ *     jfnk_gmres and jfnk_newton_solve synchronize before returning.
+ *   - Errors are status codes; nothing aborts and no exception crosses the
+ *     ABI.  jfnk_last_error() describes the last failure of a handle.
+ *   - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JFNK_OK = 0,
+  JFNK_ERR_ARG = 1,           /* invalid argument or unsupported combination */
+  JFNK_ERR_OOM = 2,           /* device or pinned-host allocation failed */
+  JFNK_ERR_HIP = 3,           /* a HIP runtime call failed */
+  JFNK_ERR_NONFINITE = 4,     /* NaN/Inf in a residual, Krylov quantity or update */
+  JFNK_ERR_BREAKDOWN = 5,     /* Krylov breakdown that left no usable direction */
+  JFNK_ERR_NOT_CONVERGED = 6  /* Newton iteration cap reached above tolerance */
+} jfnk_status;
+
+typedef enum { JFNK_JVP_AD = 0, JFNK_JVP_FD = 1 } jfnk_jvp_mode;
+
+/* Working precision.  F16S: FP32 arithmetic, Krylov basis and JVP tangent
+ * stored in FP16 with a per-vector power-of-two scale.  Givens rotations,
+ * the Hessenberg least squares, dot-product accumulation, the Newton update
+ * and the line-search merit norm are FP64 in every precision. */
+typedef enum { JFNK_F64 = 0, JFNK_F32 = 1, JFNK_F16S = 2 } jfnk_precision;
+
+/* FD step (paper, Section 2, step-size equation):
+ *   PAPER:      eps = sqrt(eps_mach) * max(1, ||x||)
+ *   NORMALIZED: eps = sqrt(eps_mach) * (1 + ||x||) / ||v||
+ * eps_mach is that of the working arithmetic (2^-52 or 2^-23). */
+typedef enum { JFNK_EPS_PAPER = 0, JFNK_EPS_NORMALIZED = 1 } jfnk_eps_rule;
+
+typedef enum {
+  JFNK_BURGERS1D = 0,   /* u_t + u u_x = nu u_xx, periodic; n = nx (ny = 1) */
+  JFNK_BURGERS2D = 1,   /* (U.grad)U = nu Lap U (Appendix A.1), periodic; n = 2 nx ny */
+  JFNK_GRAYSCOTT2D = 2, /* two-species reaction-diffusion, periodic; n = 2 nx ny */
+  JFNK_KERR2D = 3       /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
+} jfnk_problem_id;
+
+/* Problem description.  Time-dependent problems use the theta scheme
+ *   F(x; x^n) = x - x^n + dt [theta N(x) + (1 - theta) N(x^n)] - dt s
+ * (theta = 1/2 is the paper's Crank-Nicolson, 1 is backward Euler) with
+ * N(u) = u D_x u - nu D_xx u (1D Burgers), Adv(U) - nu Lap(U) (2D Burgers),
+ * (-D Lap u - u^2 v + (F+k) u, -Dv Lap v + u^2 v - F (1 - v)) (Gray-Scott),
+ * second-order central differences.  Kerr: F = -Lap E - k0^2 (eps_L +
+ * chi3 |E|^2) E - f on interior nodes and F = E on the boundary nodes.
+ *   p[]: Burgers {nu}; Gray-Scott {D, Dv, F, k}; Kerr {k0, eps_re, eps_im, chi3}.
+ * Grid: nx columns (contiguous) by ny rows, spacings hx, hy; nx >= 3, and
+ * ny >= 3 for 2D problems (ny = 1 for 1D Burgers). */
+typedef struct {
+  int id;
+  int nx, ny;
+  double hx, hy;
+  double dt, theta;
+  double p[8];
+} jfnk_problem;
+
+/* Newton / GMRES options; jfnk_default_options() fills the paper's settings
+ * (Section 3.3: FP64 tol_Newton 1e-6, tol_Krylov 1e-8; FP32 1e-4 / 1e-6;
+ * at most 15 Newton iterations and 100 restart cycles; m = 30). */
+typedef struct {
+  int m;                 /* GMRES restart length, 1..32 (<= the m of jfnk_create) */
+  int max_restarts;      /* restart cycles per Newton step */
+  int max_newton;        /* Newton iterations, <= JFNK_MAX_ITERS */
+  int ls_max_backtracks; /* line-search halvings (alpha down to 2^-ls_max_backtracks) */
+  double tol_krylov;     /* relative to ||rhs|| = ||F(x^k)|| */
+  double tol_newton;     /* on ||F(x^k)|| / ||F(x^0)|| */
+  double ls_c;           /* Armijo constant: accept ||F(x+a dx)|| <= (1 - c a) ||F(x)|| */
+  double fd_eps;         /* > 0: fixed FD step; otherwise eps_rule */
+  double breakdown_tol;  /* happy breakdown when ||w|| <= breakdown_tol ||J v_j|| */
+  int mode;              /* jfnk_jvp_mode */
+  int eps_rule;          /* jfnk_eps_rule */
+  double* history;       /* nullable DEVICE array of (max_newton + 1) * n doubles:
+                            receives every Newton iterate x_k (k = 0, 1, ...) */
+} jfnk_options;
+
+#define JFNK_MAX_ITERS 64
+
+/* Per-solve record (paper, Section 3.4 metrics). */
+typedef struct {
+  int status;                      /* jfnk_status of the solve */
+  int converged;                   /* Newton: rel. residual < tol; GMRES: ||r|| <= tol ||rhs|| */
+  int newton_iters;
+  int krylov_iters;                /* Arnoldi steps, all cycles and Newton steps */
+  int restarts;                    /* restart cycles run */
+  int ls_backtracks;
+  int ls_failures;                 /* steps where no alpha passed the Armijo test */
+  int lin_iters[JFNK_MAX_ITERS];   /* Arnoldi steps of each Newton step */
+  double rel_res[JFNK_MAX_ITERS + 1]; /* ||F(x_k)|| / ||F(x_0)||, k = 0..newton_iters */
+  double alpha[JFNK_MAX_ITERS];    /* accepted line-search step of each Newton step */
+  double f0_norm;                  /* ||F(x_0)|| (FP64 merit norm) */
+  double final_res;                /* GMRES: last true residual ||rhs - J dx|| */
+  double seconds;                  /* wall time of the call */
+} jfnk_info;
+
+typedef struct jfnk_solver jfnk_solver;
+
+/* Create a solver for one problem shape and precision on `hip_stream`
+ * (a hipStream_t; NULL = the default stream) with workspace for GMRES(m),
+ * 1 <= m <= 32.  Allocates jfnk_footprint_bytes() of device memory. */
+jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void* hip_stream,
+                        jfnk_solver** out);
+jfnk_status jfnk_destroy(jfnk_solver* s);
+
+/* Device bytes a solver of this shape allocates (for admission control). */
+size_t jfnk_footprint_bytes(const jfnk_problem* problem, int precision, int m);
+
+/* Number of real unknowns n of a problem (0 if the description is invalid). */
+size_t jfnk_problem_size(const jfnk_problem* problem);
+
+/* Fix x* for the next calls: the previous time level x^n (time-dependent
+ * problems) and the optional source s / f (nullable; required for Kerr).
+ * Both FP64 device arrays of length n.  Computes the constant part
+ * x^n - (1 - theta) dt N(x^n) + dt s once (stream-ordered). */
+jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double* source);
+
+/* F = F(x; x*) in the working precision (paper, Section 2). */
+jfnk_status jfnk_residual(jfnk_solver* s, const void* x, void* F);
+
+/* Jv = J(x) v.  mode AD: fused dual-number pass; if F_or_null is given it
+ * also receives F(x).  mode FD: (F(x + eps v) - F(x)) / eps with both
+ * residuals evaluated in one pass; eps > 0 is used as given, eps <= 0 takes
+ * eps_rule (jfnk_eps_rule) with norms computed on the device. */
+jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, void* F_or_null,
+                     int mode, double eps, int eps_rule);
+
+/* Solve J(x) dx = rhs by restarted GMRES(m) from dx = 0 with CGS2 Arnoldi and
+ * FP64 Givens least squares; tolerance relative to ||rhs||.  Reaching the
+ * cycle cap returns JFNK_OK with info->converged = 0. */
+jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx, int m, double tol,
+                       int max_restarts, int mode, double eps, int eps_rule, jfnk_info* info);
+
+/* Newton with line search from x_inout (FP64 device array, overwritten with
+ * the last iterate).  Returns JFNK_OK when converged, JFNK_ERR_NOT_CONVERGED
+ * at the iteration cap, JFNK_ERR_NONFINITE on NaN/Inf; info is filled in all
+ * three cases. */
+jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts,
+                              jfnk_info* info);
+
+/* The paper's defaults for a precision (see jfnk_options). */
+void jfnk_default_options(int precision, jfnk_options* out);
+
+const char* jfnk_status_string(int status);
+const char* jfnk_last_error(const jfnk_solver* s);
+
+/* Kernel timing with HIP events on the solver's stream (off by default).
+ * kernel: 0 residual, 1 AD JVP, 2 FD JVP, 3 CGS pass A (V^T w), 4 CGS pass B
+ * (update + dot), 5 CGS pass C (update + norm + Givens), 6 V y update,
+ * 7 cycle start, 8 Newton trial update.  Reports the launches timed since
+ * the last reset, their summed duration (ms) and their algorithmic HBM bytes. */
+jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);
+jfnk_status jfnk_profile_read(jfnk_solver* s, int kernel, long long* launches, double* total_ms,
+                              double* bytes);
+jfnk_status jfnk_profile_reset(jfnk_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JFNK_H */

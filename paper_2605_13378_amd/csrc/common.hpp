@@ -1,0 +1,198 @@
+// Device-side building blocks shared by the JFNK kernels (gfx950, wave64).
+//
+//  * dual<T>: value + tangent pair; arithmetic applies the sum and product
+//    rules, so a residual written once over a scalar type S yields F(x) for
+//    S = T and (F(x), J(x) v) for S = dual<T> (forward-mode AD JVP).
+//  * vec<T, N>: aligned vector of N elements for 8/16-byte global accesses.
+//  * wave_sum / block_partials / reduce_partials: deterministic reductions in
+//    FP64.  A block sums its wavefronts in fixed order and writes one row of
+//    partials; the next kernel adds the rows in fixed order.
+//  * Ctl: the GMRES control block that lives in device memory, so Arnoldi
+//    kernels read their coefficients and flags without any host round trip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace jfnk {
+
+constexpr int kMaxM = 32;     // largest GMRES restart length
+constexpr int kWave = 64;     // CDNA wavefront width
+
+// ---------------------------------------------------------------------------
+// dual numbers
+// ---------------------------------------------------------------------------
+template <class T>
+struct dual {
+  T v, t;
+};
+
+template <class T> __device__ __forceinline__ dual<T> operator+(dual<T> a, dual<T> b) { return {a.v + b.v, a.t + b.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator-(dual<T> a, dual<T> b) { return {a.v - b.v, a.t - b.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator-(dual<T> a) { return {-a.v, -a.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator*(dual<T> a, dual<T> b) { return {a.v * b.v, a.v * b.t + a.t * b.v}; }
+template <class T> __device__ __forceinline__ dual<T> operator*(T c, dual<T> a) { return {c * a.v, c * a.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator*(dual<T> a, T c) { return {a.v * c, a.t * c}; }
+template <class T> __device__ __forceinline__ dual<T> operator+(dual<T> a, T c) { return {a.v + c, a.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator+(T c, dual<T> a) { return {c + a.v, a.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator-(dual<T> a, T c) { return {a.v - c, a.t}; }
+template <class T> __device__ __forceinline__ dual<T> operator-(T c, dual<T> a) { return {c - a.v, -a.t}; }
+
+// ---------------------------------------------------------------------------
+// vector memory access
+// ---------------------------------------------------------------------------
+template <class T, int N>
+struct alignas(sizeof(T) * N) vec {
+  T a[N];
+};
+
+template <class T, int N>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&out)[N]) {
+  const vec<T, N> t = *reinterpret_cast<const vec<T, N>*>(p);
+#pragma unroll
+  for (int e = 0; e < N; ++e) out[e] = t.a[e];
+}
+
+template <class T, int N>
+__device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&in)[N]) {
+  vec<T, N> t;
+#pragma unroll
+  for (int e = 0; e < N; ++e) t.a[e] = in[e];
+  *reinterpret_cast<vec<T, N>*>(p) = t;
+}
+
+// storage <-> compute conversions (FP16 storage carries a power-of-two scale
+// applied by the caller)
+template <class C, class S> __device__ __forceinline__ C to_c(S x) { return static_cast<C>(x); }
+template <> __device__ __forceinline__ float to_c<float, __half>(__half x) { return __half2float(x); }
+template <class S, class C> __device__ __forceinline__ S to_s(C x) { return static_cast<S>(x); }
+template <> __device__ __forceinline__ __half to_s<__half, float>(float x) { return __float2half_rn(x); }
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block partial sums.  A reducing kernel writes one row of FP64 partial sums
+// per block (row-major [block][kPartStride]); the next kernel in stream order
+// adds the rows in its prologue (reduce_partials), every block alike and in
+// the same order.  The kernel boundary makes the rows visible, so no kernel
+// needs a grid-wide fence or atomic (on gfx950 a device-scope fence writes
+// back and invalidates the whole L2), and results depend only on the launch
+// shape, never on timing.
+constexpr int kPartStride = kMaxM + 2;
+
+// Write this block's sums of acc[k], k < nr, to row blockIdx of `part`.
+// `lds` must hold NR * (threads / 64) doubles.  All threads must call it.
+template <int NR>
+__device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double* __restrict__ part, double* lds) {
+  const int nthreads = blockDim.x * blockDim.y;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wid = tid / kWave;
+  const int nw = nthreads / kWave;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k < nr) {
+      const double s = wave_sum(acc[k]);
+      if (lane == 0) lds[k * nw + wid] = s;
+    }
+  }
+  __syncthreads();
+  if (tid < nr) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[tid * nw + w];
+    part[(size_t)bid * kPartStride + tid] = s;
+  }
+}
+
+// Column sums of `nb` partial rows for k < nr into `tot` (LDS), visible to the
+// whole block on return.  Every block computes bit-identical totals.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, int nr, double* tot) {
+  const int nthreads = blockDim.x * blockDim.y;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  int G = kWave;
+  while (G > 1 && G * nr > nthreads) G >>= 1;
+  const int col = tid / G;
+  const int g = tid % G;
+  double s = 0.0;
+  if (col < nr)
+    for (int b = g; b < nb; b += G) s += part[(size_t)b * kPartStride + col];
+  for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  if (col < nr && g == 0) tot[col] = s;
+  __syncthreads();
+}
+
+// A set of partial rows produced by an earlier kernel.
+struct Partials {
+  const double* part;
+  int nb;  // rows (blocks of the producer); 0 = none
+};
+
+// ---------------------------------------------------------------------------
+// GMRES / Newton control block (device resident)
+// ---------------------------------------------------------------------------
+enum : int {
+  kRunning = 0,
+  kConverged = 1,   // residual (true or estimated) below tolerance
+  kBreakdown = 2,   // happy breakdown: ||w|| tiny against ||J v_j||
+  kNonfinite = 3,   // NaN/Inf met
+};
+
+// Every field is written by exactly one kind of kernel and only read by
+// later kernels in stream order: no kernel reads a field that another block
+// of the same kernel may write.  done_col[0] is the state after the cycle
+// start, done_col[c + 1] the state after the Givens rotation of column c.
+struct Ctl {
+  int k;             // Arnoldi columns completed in the current cycle (written by the V y kernel)
+  int m;             // restart length of the current solve
+  int first;         // 1 until the first cycle start has fixed ||rhs||
+  int pad0;
+  int done_col[kMaxM + 2];
+  double bnorm;      // ||rhs||
+  double tol;        // relative Krylov tolerance
+  double tol_abs;    // tol * bnorm
+  double brk_tol;    // happy-breakdown threshold (relative to ||J v_j||)
+  double beta;       // ||r|| at the start of the current cycle
+  double res_est;    // latest Givens residual estimate |g_{k}|
+  double jvn2;       // ||J v_j||^2 of the current step (pass A, written by pass B)
+  double fnorm2;     // ||F||^2 of the latest residual evaluation
+  double xnorm2;     // ||x||^2 of the latest residual evaluation (must follow fnorm2)
+  double dxnorm2;    // spare norm slot
+  double aux2;       // ||v||^2 for standalone FD JVP calls
+  double gp[kMaxM + 1];              // g entry j before rotation j (gp[0] = beta)
+  double gr[kMaxM];                  // g entry j after rotation j
+  double cs[kMaxM];
+  double sn[kMaxM];
+  double hA[kMaxM + 1];              // first CGS projection of the current column
+  double hB[kMaxM + 1];              // second CGS projection of the current column
+  double scale[kMaxM + 1];           // stored V_i = v_i / scale_i  (true v_i = scale_i * V_i)
+  double H[(kMaxM + 1) * kMaxM];     // rotated Hessenberg, column-major, ld = kMaxM + 1
+};
+
+// FD step parameters (evaluated on the device from device-resident norms).
+struct EpsSpec {
+  double fixed;              // > 0: use as eps
+  double root_eps;           // sqrt(eps_mach)
+  int rule;                  // 0 paper, 1 normalized
+  const double* xnorm2;      // ||x||^2 (device)
+  const double* vnorm2;      // ||v_true||^2 (device); null: ||v|| = 1 (or vparts)
+  Partials vparts;           // ||v_true||^2 as partial rows of an earlier kernel (nb > 0)
+};
+
+// `vn2` is ||v||^2 when the caller already reduced it (negative: not known).
+__device__ __forceinline__ double fd_eps(const EpsSpec& e, double vn2) {
+  if (e.fixed > 0.0) return e.fixed;
+  const double xn = sqrt(*e.xnorm2);
+  if (e.rule == 0) return e.root_eps * fmax(1.0, xn);
+  const double vn = vn2 >= 0.0 ? sqrt(vn2) : (e.vnorm2 ? sqrt(*e.vnorm2) : 1.0);
+  return e.root_eps * (1.0 + xn) / vn;
+}
+
+}  // namespace jfnk

@@ -1,0 +1,442 @@
+// Krylov kernels of restarted GMRES(m) with CGS2 Arnoldi (paper, Section 2:
+// GMRES minimizes the residual over the Krylov space and is restarted).
+//
+// One Arnoldi step j (K = j + 1 basis vectors V_0..V_j, w = J v_j) is three
+// streaming passes, each a single read of the basis:
+//   pass A:  h  = V^T w,  ||w||^2                        (CGS, first projection)
+//   pass B:  w -= V h;   h2 = V^T w                      (update fused with the second projection)
+//   pass C:  w -= V h2;  ||w||^2;  V_{j+1} <- w          (update fused with the norm)
+// Each pass writes one row of FP64 partial sums per block; the next kernel
+// adds them in its prologue (pass B the h of pass A, pass C the h2 of pass B,
+// and the JVP of step j+1 -- or the V y kernel at the end of a cycle -- the
+// ||w||^2 of pass C, after which it applies the previous Givens rotations to
+// the new Hessenberg column, forms the new rotation and updates g, in FP64).
+// The basis is stored unnormalized: V_i holds a multiple of v_i and
+// Ctl::scale[i] = 1 / ||V_i|| is folded into the coefficients instead of a
+// separate normalization pass.  Coefficients and stop flags live in the
+// device control block, so a cycle runs without host round trips.
+//
+// Threads hold VEC consecutive elements of w and of every basis vector in
+// registers, so each element of V is loaded once per pass and the update and
+// the dot products share that load.  All vectors here are solver-internal,
+// padded with zeros to a multiple of 256 elements and 256-byte aligned.
+#pragma once
+
+#include "common.hpp"
+
+namespace jfnk {
+
+enum { PASS_A = 0, PASS_B = 1, PASS_C = 2 };
+
+// ---------------------------------------------------------------------------
+// Givens update of Hessenberg column j (one thread, FP64).
+// Reads hA, hB, jvn2, cs/sn[0..j-1], gp[j], tol_abs, brk_tol; the results go
+// to a GivensOut and `col`, and are committed to Ctl by block 0 only.
+// ---------------------------------------------------------------------------
+struct GivensOut {
+  double c, s, gr, gp1, est, wn;
+  int done;
+};
+
+__device__ inline GivensOut givens_column(const Ctl* __restrict__ ctl, int j, double wn2, double* col) {
+  GivensOut o;
+  o.wn = sqrt(wn2);
+  for (int i = 0; i <= j; ++i) col[i] = ctl->hA[i] + ctl->hB[i];
+  col[j + 1] = o.wn;
+  bool finite = isfinite(o.wn);
+  for (int i = 0; i <= j; ++i) finite = finite && isfinite(col[i]);
+  for (int i = 0; i < j; ++i) {
+    const double t = ctl->cs[i] * col[i] + ctl->sn[i] * col[i + 1];
+    col[i + 1] = -ctl->sn[i] * col[i] + ctl->cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  o.c = 1.0;
+  o.s = 0.0;
+  if (col[j + 1] != 0.0) {
+    const double r = hypot(col[j], col[j + 1]);
+    o.c = col[j] / r;
+    o.s = col[j + 1] / r;
+  }
+  col[j] = o.c * col[j] + o.s * col[j + 1];
+  col[j + 1] = 0.0;
+  const double g = ctl->gp[j];
+  o.gr = o.c * g;
+  o.gp1 = -o.s * g;
+  o.est = fabs(o.gp1);
+  finite = finite && isfinite(o.est);
+  o.done = kRunning;
+  if (!finite)
+    o.done = kNonfinite;
+  else if (o.est <= ctl->tol_abs)
+    o.done = kConverged;
+  else if (o.wn <= ctl->brk_tol * sqrt(ctl->jvn2))
+    o.done = kBreakdown;
+  return o;
+}
+
+__device__ inline void givens_commit(Ctl* __restrict__ ctl, int j, const GivensOut& o, const double* col,
+                                     int* host_flags) {
+  const int ld = kMaxM + 1;
+  for (int i = 0; i <= j + 1; ++i) ctl->H[j * ld + i] = col[i];
+  ctl->cs[j] = o.c;
+  ctl->sn[j] = o.s;
+  ctl->gr[j] = o.gr;
+  ctl->gp[j + 1] = o.gp1;
+  ctl->res_est = o.est;
+  ctl->scale[j + 1] = 1.0 / o.wn;
+  ctl->done_col[j + 1] = o.done;
+  if (host_flags) host_flags[j] = o.done;
+}
+
+// Prologue of the kernel that follows pass C of step j (the JVP of step j+1
+// or the V y update): reduce ||w||^2 and update column j.  Every thread of
+// every block gets the same outcome; `col` (LDS, kMaxM + 1 doubles) receives
+// the rotated column.
+__device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, Partials pc, int* host_flags, double* col) {
+  __shared__ double tot[1];
+  __shared__ GivensOut out;
+  reduce_partials(pc.part, pc.nb, 1, tot);
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if (tid == 0) {
+    out = givens_column(ctl, j, tot[0], col);
+    if (blockIdx.x == 0 && blockIdx.y == 0) givens_commit(ctl, j, out, col, host_flags);
+  }
+  __syncthreads();
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// CGS passes
+// ---------------------------------------------------------------------------
+template <class T, class VT>
+struct KArgs {
+  long long n;        // padded length
+  const VT* V;        // basis, vector i at V + i * vstride
+  long long vstride;
+  T* w;               // working vector
+  VT* wout;           // pass C destination (V_{j+1})
+  int K;              // basis vectors in use (j + 1)
+  Ctl* ctl;
+  Partials in;        // partials of the previous pass (B: pass A's, C: pass B's)
+  double* out;        // this pass's partial rows
+};
+
+template <class T, class VT, int KMAX, int VEC, int MODE>
+__global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
+  Ctl* ctl = a.ctl;
+  const int K = a.K;
+  if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
+  __shared__ double tot[KMAX + 1];
+  T coef[KMAX];
+  if constexpr (MODE != PASS_A) {
+    // projections of the previous pass on the stored vectors (+ ||J v_j||^2 from pass A)
+    reduce_partials(a.in.part, a.in.nb, MODE == PASS_B ? K + 1 : K, tot);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) coef[k] = k < K ? T(tot[k] * ctl->scale[k] * ctl->scale[k]) : T(0);
+    if (blockIdx.x == 0 && threadIdx.x < K) {
+      const double h = tot[threadIdx.x] * ctl->scale[threadIdx.x];
+      if (MODE == PASS_B)
+        ctl->hA[threadIdx.x] = h;
+      else
+        ctl->hB[threadIdx.x] = h;
+    }
+    if (MODE == PASS_B && blockIdx.x == 0 && threadIdx.x == 0) ctl->jvn2 = tot[K];
+  }
+  double acc[KMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
+
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < a.n; i += step) {
+    T w[VEC];
+    load_vec<T, VEC>(a.w + i, w);
+    T vv[KMAX][VEC];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < K) {
+        VT t[VEC];
+        load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vv[k][e] = to_c<T>(t[e]);
+      }
+    }
+    if constexpr (MODE == PASS_A) {
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < K)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[k] += (double)vv[k][e] * (double)w[e];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)w[e] * (double)w[e];
+    } else {
+      T wn[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        T x = w[e];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) x = x - coef[k] * vv[k][e];
+        wn[e] = x;
+      }
+      if constexpr (MODE == PASS_B) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[k] += (double)vv[k][e] * (double)wn[e];
+        store_vec<T, VEC>(a.w + i, wn);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[0] += (double)wn[e] * (double)wn[e];
+        VT o[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = to_s<VT>(wn[e]);
+        store_vec<VT, VEC>(a.wout + i, o);
+      }
+    }
+  }
+
+  int nr = MODE == PASS_C ? 1 : K;
+  if constexpr (MODE == PASS_A) {
+    // move ||w||^2 next to the K dot products (static indices keep acc in registers)
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k == K) acc[k] = acc[KMAX];
+    nr = K + 1;
+  }
+  __shared__ double lds[(KMAX + 1) * 8];
+  block_partials<KMAX + 1>(acc, nr, a.out, lds);
+}
+
+// Start of a restart cycle: V_0 = sign * R - w (w nullable) and its partial
+// norms; cycle_begin_kernel then fixes beta, g, scale[0] and the flags.
+template <class T, class VT>
+struct InitArgs {
+  long long n;
+  const T* R;
+  double sign;
+  const T* w;   // nullable
+  VT* V0;
+  double* out;  // partial rows
+};
+
+template <class T, class VT, int VEC>
+__global__ void __launch_bounds__(256) init_cycle_kernel(const InitArgs<T, VT> a) {
+  double acc[1] = {0.0};
+  const T sg = T(a.sign);
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < a.n; i += step) {
+    T r[VEC];
+    load_vec<T, VEC>(a.R + i, r);
+    if (a.w != nullptr) {
+      T w[VEC];
+      load_vec<T, VEC>(a.w + i, w);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) r[e] = sg * r[e] - w[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) r[e] = sg * r[e];
+    }
+    VT o[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      o[e] = to_s<VT>(r[e]);
+      acc[0] += (double)r[e] * (double)r[e];
+    }
+    store_vec<VT, VEC>(a.V0 + i, o);
+  }
+  __shared__ double lds[4];
+  block_partials<1>(acc, 1, a.out, lds);
+}
+
+// One block: beta = ||V_0||; the first cycle of a solve also fixes ||rhs||.
+template <int kUnused = 0>
+__global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in, int m) {
+  __shared__ double tot[1];
+  reduce_partials(in.part, in.nb, 1, tot);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(tot[0]);
+    if (ctl->first) {
+      ctl->bnorm = beta;
+      ctl->tol_abs = ctl->tol * beta;
+      ctl->first = 0;
+    }
+    ctl->beta = beta;
+    ctl->res_est = beta;
+    ctl->gp[0] = beta;
+    ctl->scale[0] = 1.0 / beta;
+    ctl->k = 0;
+    ctl->done_col[0] = !isfinite(beta) ? kNonfinite : (beta <= ctl->tol_abs ? kConverged : kRunning);
+  }
+  if (threadIdx.x >= 1 && threadIdx.x <= m) ctl->done_col[threadIdx.x] = kRunning;
+}
+
+// End of a cycle: finish the pending Givens column (if the last enqueued step
+// ran), y = R^{-1} g by back substitution (FP64, every block alike), then
+// dx = [dx] + sum_i y_i scale_i V_i with its partial norms.
+template <class T, class VT>
+struct VyArgs {
+  long long n;
+  const VT* V;
+  long long vstride;
+  T* dx;
+  int first;    // 1: dx = V y (dx not read)
+  int jmax;     // last Arnoldi step enqueued in this cycle (-1: none)
+  Ctl* ctl;
+  Partials pc;  // partial norms of the last pass C
+  double* out;  // partial rows of ||dx||^2
+  int* host_flags;
+};
+
+template <class T, class VT, int KMAX, int VEC>
+__global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
+  Ctl* ctl = a.ctl;
+  __shared__ double y[kMaxM];
+  __shared__ double lastcol[kMaxM + 1];
+  __shared__ double lastgr;
+  // columns completed: stop at the first column whose Givens update ended the cycle
+  int k = 0;
+  bool pending = false;
+  if (a.jmax >= 0 && ctl->done_col[0] == kRunning) {
+    k = a.jmax + 1;
+    for (int c = 0; c < a.jmax; ++c)
+      if (ctl->done_col[c + 1] != kRunning) {
+        k = c + 1;
+        break;
+      }
+    pending = (k == a.jmax + 1);
+  }
+  if (pending) {
+    const GivensOut g = finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
+    if (threadIdx.x == 0) lastgr = g.gr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // block 0 may just have written column k-1 of H: every block uses the
+    // column it computed itself for that one
+    const int ld = kMaxM + 1;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = (pending && i == k - 1) ? lastgr : ctl->gr[i];
+      for (int l = i + 1; l < k; ++l) {
+        const double r = (pending && l == k - 1) ? lastcol[i] : ctl->H[l * ld + i];
+        s -= r * y[l];
+      }
+      const double d = (pending && i == k - 1) ? lastcol[i] : ctl->H[i * ld + i];
+      y[i] = s / d;
+    }
+    if (blockIdx.x == 0) ctl->k = k;
+  }
+  __syncthreads();
+  T coef[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) coef[c] = c < k ? T(y[c] * ctl->scale[c]) : T(0);
+  double acc[1] = {0.0};
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < a.n; i += step) {
+    T d[VEC];
+    if (a.first) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) d[e] = T(0);
+    } else {
+      load_vec<T, VEC>(a.dx + i, d);
+    }
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+      if (c < k) {
+        VT t[VEC];
+        load_vec<VT, VEC>(a.V + c * a.vstride + i, t);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d[e] = d[e] + coef[c] * to_c<T>(t[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[0] += (double)d[e] * (double)d[e];
+    store_vec<T, VEC>(a.dx + i, d);
+  }
+  __shared__ double lds[8];
+  block_partials<1>(acc, 1, a.out, lds);
+}
+
+// One block: write column sums of earlier partial rows to device scalars.
+template <int kUnused = 0>
+__global__ void __launch_bounds__(256) finish_sums_kernel(Partials in, int nr, double* out0, double* out1) {
+  __shared__ double tot[2];
+  reduce_partials(in.part, in.nb, nr, tot);
+  if (threadIdx.x == 0) {
+    *out0 = tot[0];
+    if (nr > 1 && out1) *out1 = tot[1];
+  }
+}
+
+// Newton trial point: x64t = x64 + alpha dx (FP64 accumulation of the update),
+// xw = working-precision copy (nullable when the working precision is FP64).
+template <class T, int VEC>
+__global__ void __launch_bounds__(256) newton_trial_kernel(long long n, const double* __restrict__ x64,
+                                                           const T* __restrict__ dx, double alpha,
+                                                           double* __restrict__ x64t, T* __restrict__ xw) {
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < n; i += step) {
+    double x[VEC];
+    T d[VEC];
+    load_vec<double, VEC>(x64 + i, x);
+    load_vec<T, VEC>(dx + i, d);
+    T o[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      x[e] = x[e] + alpha * (double)d[e];
+      o[e] = T(x[e]);
+    }
+    store_vec<double, VEC>(x64t + i, x);
+    if (xw != nullptr) store_vec<T, VEC>(xw + i, o);
+  }
+}
+
+// Working-precision copy of an FP64 vector.
+template <class T, int VEC>
+__global__ void __launch_bounds__(256) cast_kernel(long long n, const double* __restrict__ src, T* __restrict__ dst) {
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < n; i += step) {
+    double x[VEC];
+    load_vec<double, VEC>(src + i, x);
+    T o[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) o[e] = T(x[e]);
+    store_vec<T, VEC>(dst + i, o);
+  }
+}
+
+// Partial sums of p^2 over an arbitrary (possibly unaligned) vector.
+template <class T>
+__global__ void __launch_bounds__(256) norm2_kernel(long long n, const T* __restrict__ p, double* out) {
+  double acc[1] = {0.0};
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const double v = (double)p[i];
+    acc[0] += v * v;
+  }
+  __shared__ double lds[4];
+  block_partials<1>(acc, 1, out, lds);
+}
+
+// Zero fill (used instead of memset so every step is a plain kernel).
+template <class T>
+__global__ void __launch_bounds__(256) fill_zero_kernel(long long n, T* __restrict__ p) {
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) p[i] = T(0);
+}
+
+// Begin a GMRES solve: reset the control flags on the device.
+template <int kUnused = 0>
+__global__ void ctl_begin_kernel(Ctl* c, double tol, double brk_tol, int m) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->k = 0;
+    c->m = m;
+    c->first = 1;
+    c->tol = tol;
+    c->brk_tol = brk_tol;
+    c->tol_abs = 0.0;
+    c->bnorm = 0.0;
+  }
+}
+
+}  // namespace jfnk

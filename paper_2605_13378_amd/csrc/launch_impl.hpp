@@ -1,0 +1,139 @@
+// Definitions of the launchers declared in launch.hpp (included by the
+// per-precision translation units only).
+#pragma once
+
+#include "launch.hpp"
+
+namespace jfnk {
+
+template <class P, class T, class VT, int VEC>
+static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid,
+                                dim3 block, hipStream_t s) {
+  constexpr int RY = kStencilRY;
+  if (op == OP_RES) {
+    if constexpr (std::is_same<T, VT>::value) {
+      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false>), grid, block, 0, s, a, c);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (op == OP_AD) {
+    if (withf) {
+      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true>), grid, block, 0, s, a, c);
+    } else {
+      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, false>), grid, block, 0, s, a, c);
+    }
+  } else {
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_FD, false>), grid, block, 0, s, a, c);
+  }
+  return hipGetLastError();
+}
+
+template <class P, class T, class VT>
+static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
+                                      const Coefs& c, hipStream_t s, int* nblocks) {
+  constexpr int V = P::kInterleaved ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
+  dim3 grid, block;
+  stencil_shape(pid, a.nx, a.ny, vectorized ? V : 1, grid, block);
+  if (nblocks) *nblocks = (int)(grid.x * grid.y);
+  if (vectorized) return stencil_by_op<P, T, VT, V>(op, withf, a, c, grid, block, s);
+  return stencil_by_op<P, T, VT, 1>(op, withf, a, c, grid, block, s);
+}
+
+template <class T, class VT>
+hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
+                          const Coefs& c, hipStream_t s, int* nblocks) {
+  switch (pid) {
+    case kBurgers1D:
+      return stencil_for_problem<Burgers1DOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+    case kBurgers2D:
+      return stencil_for_problem<Burgers2DOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+    case kGrayScott:
+      return stencil_for_problem<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+    case kKerr:
+      return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <class T, class VT, int KMAX>
+static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  const dim3 g(grid), b(kKrylovThreads);
+  if (mode == PASS_A)
+    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_A>), g, b, 0, s, a);
+  else if (mode == PASS_B)
+    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_B>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_C>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, class VT>
+hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
+  if (a.K <= 4) return cgs_by_mode<T, VT, 4>(mode, a, grid, s);
+  if (a.K <= 8) return cgs_by_mode<T, VT, 8>(mode, a, grid, s);
+  if (a.K <= 16) return cgs_by_mode<T, VT, 16>(mode, a, grid, s);
+  return cgs_by_mode<T, VT, 32>(mode, a, grid, s);
+}
+
+template <class T, class VT>
+hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  hipLaunchKernelGGL((init_cycle_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, class VT>
+hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  const dim3 g(grid), b(kKrylovThreads);
+  if (m <= 8)
+    hipLaunchKernelGGL((vy_kernel<T, VT, 8, VEC>), g, b, 0, s, a);
+  else if (m <= 16)
+    hipLaunchKernelGGL((vy_kernel<T, VT, 16, VEC>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((vy_kernel<T, VT, 32, VEC>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_trial(long long n, const double* x64, const T* dx, double alpha, double* x64t, T* xw, int grid,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((newton_trial_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), 0, s, n, x64, dx, alpha, x64t,
+                     xw);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_cast(long long n, const double* src, T* dst, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((cast_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_norm2(long long n, const T* p, double* part, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((norm2_kernel<T>), dim3(grid), dim3(kStreamThreads), 0, s, n, p, part);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((fill_zero_kernel<T>), dim3(grid), dim3(kStreamThreads), 0, s, n, p);
+  return hipGetLastError();
+}
+
+#define JFNK_INSTANTIATE(T, VT)                                                                                  \
+  template hipError_t launch_stencil<T, VT>(int, int, bool, bool, const StencilArgs<T, VT>&, const Coefs&,      \
+                                            hipStream_t, int*);                                                 \
+  template hipError_t launch_cgs<T, VT>(int, const KArgs<T, VT>&, int, hipStream_t);                            \
+  template hipError_t launch_init<T, VT>(const InitArgs<T, VT>&, int, hipStream_t);                             \
+  template hipError_t launch_vy<T, VT>(const VyArgs<T, VT>&, int, int, hipStream_t);
+
+#define JFNK_INSTANTIATE_SCALAR(T)                                                                               \
+  template hipError_t launch_trial<T>(long long, const double*, const T*, double, double*, T*, int, hipStream_t);\
+  template hipError_t launch_cast<T>(long long, const double*, T*, int, hipStream_t);                           \
+  template hipError_t launch_norm2<T>(long long, const T*, double*, int, hipStream_t);                          \
+  template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);
+
+}  // namespace jfnk

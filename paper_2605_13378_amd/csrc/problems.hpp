@@ -1,0 +1,142 @@
+// Pointwise spatial operators N of the benchmark problems, written once over
+// a scalar type S (T for the residual and FD, dual<T> for the AD JVP).
+//
+// Discretization (paper, Section 3.2 and Appendix A): second-order central
+// differences on a 5-point stencil, D_x f = (f_{i+1} - f_{i-1}) / (2 hx),
+// D_xx f = (f_{i+1} - 2 f_i + f_{i-1}) / hx^2.  Each operator receives the
+// centre value and its four neighbours of every field (Nbr) and returns N per
+// field; the kernel forms alpha x + cN N(x) + beta b around it.
+//
+//   Burgers 1D:   N = u D_x u - nu D_xx u
+//   Burgers 2D:   N = (u D_x + v D_y) U - nu Lap U            (Appendix A.1)
+//   Gray-Scott:   N = (-D Lap u - u^2 v + (F+k) u, -Dv Lap v + u^2 v - F (1-v))
+//   Kerr:         N = -Lap E - k0^2 (eps_L + chi3 |E|^2) E on (re, im),
+//                 |E|^2 = re^2 + im^2; PEC boundary nodes are identity rows.
+#pragma once
+
+#include "common.hpp"
+
+namespace jfnk {
+
+template <class S>
+struct Nbr {
+  S c, l, r, d, u;  // centre, x-1, x+1, y-1, y+1
+};
+
+// Host-filled coefficient block (double); kernels convert to T.
+struct Coefs {
+  double c[12];
+};
+
+struct Burgers1DOp {
+  static constexpr int NF = 1;
+  static constexpr bool kDim2 = false;
+  static constexpr bool kPeriodic = true;
+  static constexpr bool kInterleaved = false;
+  // c: 0 = 1/(2h), 1 = nu/h^2
+  template <class T>
+  struct K {
+    T i2h, nuh2;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[1], S (&out)[1]) {
+    const Nbr<S>& q = f[0];
+    const S dx = (q.r - q.l) * k.i2h;
+    const S dxx = (q.r - T(2) * q.c) + q.l;
+    out[0] = q.c * dx - k.nuh2 * dxx;
+  }
+  __device__ __forceinline__ static bool boundary(int, int, int, int) { return false; }
+};
+
+struct Burgers2DOp {
+  static constexpr int NF = 2;
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = true;
+  static constexpr bool kInterleaved = false;
+  // c: 0 = 1/(2hx), 1 = 1/(2hy), 2 = nu/hx^2, 3 = nu/hy^2
+  template <class T>
+  struct K {
+    T i2hx, i2hy, nux, nuy;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1]), T(c.c[2]), T(c.c[3])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[2], S (&out)[2]) {
+    const S u = f[0].c;
+    const S v = f[1].c;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const Nbr<S>& a = f[q];
+      const S dx = (a.r - a.l) * k.i2hx;
+      const S dy = (a.u - a.d) * k.i2hy;
+      const S lx = (a.r - T(2) * a.c) + a.l;
+      const S ly = (a.u - T(2) * a.c) + a.d;
+      out[q] = (u * dx + v * dy) - (k.nux * lx + k.nuy * ly);
+    }
+  }
+  __device__ __forceinline__ static bool boundary(int, int, int, int) { return false; }
+};
+
+struct GrayScottOp {
+  static constexpr int NF = 2;
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = true;
+  static constexpr bool kInterleaved = false;
+  // c: 0 = D/hx^2, 1 = D/hy^2, 2 = Dv/hx^2, 3 = Dv/hy^2, 4 = F + k, 5 = F
+  template <class T>
+  struct K {
+    T dux, duy, dvx, dvy, fk, feed;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1]), T(c.c[2]), T(c.c[3]), T(c.c[4]), T(c.c[5])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[2], S (&out)[2]) {
+    const Nbr<S>& u = f[0];
+    const Nbr<S>& v = f[1];
+    const S lu = k.dux * ((u.r - T(2) * u.c) + u.l) + k.duy * ((u.u - T(2) * u.c) + u.d);
+    const S lv = k.dvx * ((v.r - T(2) * v.c) + v.l) + k.dvy * ((v.u - T(2) * v.c) + v.d);
+    const S uuv = (u.c * u.c) * v.c;
+    out[0] = (k.fk * u.c - uuv) - lu;
+    out[1] = (uuv - k.feed * (T(1) - v.c)) - lv;
+  }
+  __device__ __forceinline__ static bool boundary(int, int, int, int) { return false; }
+};
+
+struct KerrOp {
+  static constexpr int NF = 2;  // real and imaginary parts, interleaved in memory
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = false;
+  static constexpr bool kInterleaved = true;
+  // c: 0 = 1/hx^2, 1 = 1/hy^2, 2 = k0^2, 3 = eps_re, 4 = eps_im, 5 = chi3
+  template <class T>
+  struct K {
+    T ihx2, ihy2, k2, er, ei, chi;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1]), T(c.c[2]), T(c.c[3]), T(c.c[4]), T(c.c[5])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[2], S (&out)[2]) {
+    const Nbr<S>& re = f[0];
+    const Nbr<S>& im = f[1];
+    const S lre = k.ihx2 * ((re.r - T(2) * re.c) + re.l) + k.ihy2 * ((re.u - T(2) * re.c) + re.d);
+    const S lim = k.ihx2 * ((im.r - T(2) * im.c) + im.l) + k.ihy2 * ((im.u - T(2) * im.c) + im.d);
+    const S a = k.er + k.chi * (re.c * re.c + im.c * im.c);
+    out[0] = -lre - k.k2 * (a * re.c - k.ei * im.c);
+    out[1] = -lim - k.k2 * (a * im.c + k.ei * re.c);
+  }
+  __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
+    return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+  }
+};
+
+}  // namespace jfnk

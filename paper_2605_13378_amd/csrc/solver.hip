@@ -1,0 +1,950 @@
+// Host side of the JFNK library: solver handle, workspace, the GMRES and
+// Newton drivers and the C ABI of include/jfnk.h.
+//
+// The drivers only enqueue kernels and read back a few scalars:
+//  * GMRES: one synchronization per restart cycle (true residual at the cycle
+//    start, Arnoldi step count at its end).  Inside a cycle the Arnoldi steps
+//    are enqueued back to back; every kernel reads its coefficients and the
+//    stop flag from the device control block, and the host looks at the flag
+//    of step j-1 (written by that step's last block into mapped host memory)
+//    while step j is already queued, so the GPU never waits for the host.
+//  * Newton: one synchronization per residual evaluation (the FP64 merit norm
+//    decides the line search on the host).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "jfnk.h"
+#include "launch.hpp"
+
+using namespace jfnk;
+
+namespace {
+
+constexpr int kNumProf = 9;
+enum ProfKernel { PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8 };
+
+struct ProfRec {
+  int kid;
+  double bytes;
+  hipEvent_t a, b;
+  int step;  // Arnoldi step index (-1 outside a cycle)
+};
+
+double eps_mach(int prec) { return prec == JFNK_F64 ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23); }
+
+long long round_up(long long v, long long q) { return (v + q - 1) / q * q; }
+
+}  // namespace
+
+struct jfnk_solver {
+  jfnk_problem prob{};
+  int prec = 0;
+  int m = 0;
+  hipStream_t stream = nullptr;
+  int pid = 0;
+  long long n = 0;
+  long long npad = 0;
+  Coefs coefs{};
+  double alpha = 1.0, cN = 0.0, beta = -1.0;
+  int cu = 256;
+  size_t tsize = 8;
+  size_t vsize = 8;
+  void* V = nullptr;
+  void* w = nullptr;
+  void* R = nullptr;
+  void* dx = nullptr;
+  void* F = nullptr;
+  void* Ft = nullptr;
+  void* xw = nullptr;
+  void* xwt = nullptr;
+  void* b = nullptr;
+  double* x64 = nullptr;
+  double* x64t = nullptr;
+  double* tmp64 = nullptr;
+  // partial-sum rows: 0 pass A, 1 pass B, 2 pass C, 3 cycle start, 4 V y, 5 residual / norms
+  double* parts = nullptr;
+  size_t part_rows = 0;
+  Ctl* ctl = nullptr;
+  Ctl* hctl = nullptr;     // pinned host mirror of the control block header
+  int* hflags = nullptr;   // pinned, mapped: per-step stop flags written by the device
+  int* dflags = nullptr;   // device view of hflags
+  std::vector<hipEvent_t> step_ev;
+  bool has_prev = false;
+  std::string err;
+  bool prof = false;
+  int cur_step = -1;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  long long p_count[kNumProf] = {};
+  double p_ms[kNumProf] = {};
+  double p_bytes[kNumProf] = {};
+};
+
+#define JFNK_HIP(s, ...)                                                   \
+  do {                                                                     \
+    hipError_t e_ = (__VA_ARGS__);                                         \
+    if (e_ != hipSuccess) {                                                \
+      (s)->err = std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_); \
+      return JFNK_ERR_HIP;                                                 \
+    }                                                                      \
+  } while (0)
+
+#define JFNK_TRY(...)                   \
+  do {                                  \
+    jfnk_status st_ = (__VA_ARGS__);    \
+    if (st_ != JFNK_OK) return st_;     \
+  } while (0)
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// profiling with HIP events on the solver's stream
+// ---------------------------------------------------------------------------
+hipEvent_t pool_get(jfnk_solver* s) {
+  if (!s->pool.empty()) {
+    hipEvent_t e = s->pool.back();
+    s->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  jfnk_solver* s;
+  int kid;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(jfnk_solver* s_, int kid_, double bytes_) : s(s_), kid(kid_), bytes(bytes_) {
+    if (s->prof) {
+      a = pool_get(s);
+      if (a) (void)hipEventRecord(a, s->stream);
+    }
+  }
+  ~ProfScope() {
+    if (s->prof && a) {
+      hipEvent_t b = pool_get(s);
+      if (b) {
+        (void)hipEventRecord(b, s->stream);
+        s->recs.push_back({kid, bytes, a, b, s->cur_step});
+      } else {
+        s->pool.push_back(a);
+      }
+    }
+  }
+};
+
+// Fold completed event pairs into the per-kernel totals.  Launches of Arnoldi
+// steps at or beyond `steps_done` early-exited (the cycle had already stopped)
+// and are not counted.
+void prof_harvest(jfnk_solver* s, int steps_done) {
+  for (const ProfRec& r : s->recs) {
+    float ms = 0.f;
+    const bool skipped = r.step >= 0 && r.step >= steps_done;
+    if (!skipped && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      s->p_count[r.kid] += 1;
+      s->p_ms[r.kid] += ms;
+      s->p_bytes[r.kid] += r.bytes;
+    }
+    s->pool.push_back(r.a);
+    s->pool.push_back(r.b);
+  }
+  s->recs.clear();
+}
+
+jfnk_status sync_read_ctl(jfnk_solver* s) {
+  JFNK_HIP(s, hipMemcpyAsync(s->hctl, s->ctl, offsetof(Ctl, gp), hipMemcpyDeviceToHost, s->stream));
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  return JFNK_OK;
+}
+
+int krylov_grid(const jfnk_solver* s, int vec) {
+  const long long need = (s->npad + (long long)kKrylovThreads * vec - 1) / ((long long)kKrylovThreads * vec);
+  return (int)std::max<long long>(1, std::min<long long>(need, s->cu));
+}
+
+int stream_grid(const jfnk_solver* s, int vec) {
+  const long long need = (s->npad + (long long)kStreamThreads * vec - 1) / ((long long)kStreamThreads * vec);
+  return (int)std::max<long long>(1, std::min<long long>(need, 4LL * s->cu));
+}
+
+bool aligned(const void* p, size_t a) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+EpsSpec eps_spec(const jfnk_solver* s, double fixed, int rule, const double* vnorm2) {
+  EpsSpec e{};
+  e.fixed = fixed;
+  e.root_eps = std::sqrt(eps_mach(s->prec));
+  e.rule = rule;
+  e.xnorm2 = &s->ctl->xnorm2;
+  e.vnorm2 = rule == JFNK_EPS_NORMALIZED ? vnorm2 : nullptr;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// precision-generic drivers
+// ---------------------------------------------------------------------------
+template <class T, class VT>
+struct Impl {
+  static constexpr int KVEC = krylov_vec<T>();
+
+  static double* part(jfnk_solver* s, int region) { return s->parts + (size_t)region * s->part_rows * kPartStride; }
+
+  // Residual F = alpha x + cN N(x) + beta b; optional norms into ctl.
+  static jfnk_status residual(jfnk_solver* s, const T* x, T* F, bool norms) {
+    StencilArgs<T, T> a{};
+    a.nx = s->prob.nx;
+    a.ny = s->prob.ny;
+    a.plane = (long long)s->prob.nx * s->prob.ny;
+    a.x = x;
+    a.b = static_cast<const T*>(s->b);
+    a.out = F;
+    a.alpha = s->alpha;
+    a.cN = s->cN;
+    a.beta = s->beta;
+    a.part_out = part(s, 5);
+    a.nred = norms ? 2 : 0;
+    const int vec = stencil_vec<T>(s->pid);
+    const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(F, 16) && aligned(s->b, 16);
+    int nb = 0;
+    {
+      ProfScope ps(s, PK_RES, 3.0 * s->n * sizeof(T));
+      JFNK_HIP(s, launch_stencil<T, T>(s->pid, OP_RES, false, vz, a, s->coefs, s->stream, &nb));
+    }
+    if (norms) JFNK_HIP(s, launch_finish_sums(Partials{part(s, 5), nb}, 2, &s->ctl->fnorm2, &s->ctl->xnorm2, s->stream));
+    return JFNK_OK;
+  }
+
+  // Jv = J(x) v (AD or FD), optional F(x) for AD; v is of type W (T or VT).
+  // Arnoldi mode (arn_j >= 0): v is basis vector arn_j, its scale and the
+  // pending Givens column come from the device control block.
+  template <class W>
+  static jfnk_status jvp(jfnk_solver* s, const T* x, const W* v, const double* vscale, T* Jv, T* Fout, int mode,
+                         const EpsSpec& eps, int arn_j = -1) {
+    StencilArgs<T, W> a{};
+    a.nx = s->prob.nx;
+    a.ny = s->prob.ny;
+    a.plane = (long long)s->prob.nx * s->prob.ny;
+    a.x = x;
+    a.v = v;
+    // the AD tangent does not involve b; F(x) and the FD difference do
+    a.b = (mode == JFNK_JVP_AD && Fout == nullptr) ? nullptr : static_cast<const T*>(s->b);
+    a.out = Jv;
+    a.out2 = Fout;
+    a.alpha = s->alpha;
+    a.cN = s->cN;
+    a.beta = s->beta;
+    a.vscale = vscale;
+    a.eps = eps;
+    if (arn_j >= 0) {
+      a.ctl = s->ctl;
+      a.arn_j = arn_j;
+      a.pc = Partials{part(s, 2), krylov_grid(s, KVEC)};
+      a.host_flags = s->dflags;
+    }
+    const int vec = stencil_vec<T>(s->pid);
+    const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(v, vec * sizeof(W)) && aligned(Jv, 16) &&
+                    aligned(Fout, 16) && aligned(a.b, 16);
+    const int op = mode == JFNK_JVP_AD ? OP_AD : OP_FD;
+    const double nvec = mode == JFNK_JVP_AD ? 2.0 + (Fout ? 2.0 : 0.0) : 3.0;
+    ProfScope ps(s, mode == JFNK_JVP_AD ? PK_AD : PK_FD,
+                 nvec * s->n * sizeof(T) + (double)s->n * sizeof(W));
+    JFNK_HIP(s, launch_stencil<T, W>(s->pid, op, Fout != nullptr, vz, a, s->coefs, s->stream));
+    return JFNK_OK;
+  }
+
+  struct GOut {
+    bool converged = false, nonfinite = false;
+    int iters = 0, cycles = 0;
+    double bnorm = 0.0, true_res = 0.0;
+  };
+
+  static VT* basis(jfnk_solver* s, int i) { return static_cast<VT*>(s->V) + (long long)i * s->npad; }
+
+  // Restarted GMRES(m) on J(x) dx = sign * R (R internal, padded), dx internal.
+  static jfnk_status gmres(jfnk_solver* s, const T* x, const T* R, double sign, int m, double tol, int max_restarts,
+                           int mode, double fixed_eps, int eps_rule, double brk, GOut& go) {
+    go = GOut{};
+    T* dxi = static_cast<T*>(s->dx);
+    T* w = static_cast<T*>(s->w);
+    const int kgrid = krylov_grid(s, KVEC);
+    const int sgrid = stream_grid(s, KVEC);
+    const EpsSpec eps_arnoldi = eps_spec(s, fixed_eps, eps_rule, nullptr);  // ||v_j|| = 1
+    EpsSpec eps_restart = eps_spec(s, fixed_eps, eps_rule, nullptr);        // v = dx
+    if (eps_rule == JFNK_EPS_NORMALIZED) eps_restart.vparts = Partials{part(s, 4), kgrid};
+    volatile int* flags = reinterpret_cast<volatile int*>(s->hflags);
+    JFNK_HIP(s, launch_ctl_begin(s->ctl, tol, brk, m, s->stream));
+    bool updated = false;
+    for (int cycle = 0;; ++cycle) {
+      const T* wr = nullptr;
+      s->cur_step = -1;
+      if (cycle > 0) {
+        JFNK_TRY(jvp<T>(s, x, dxi, nullptr, w, nullptr, mode, eps_restart));
+        wr = w;
+      }
+      {
+        InitArgs<T, VT> ia{s->npad, R, sign, wr, basis(s, 0), part(s, 3)};
+        ProfScope ps(s, PK_INIT, (double)s->n * ((wr ? 2.0 : 1.0) * sizeof(T) + sizeof(VT)));
+        JFNK_HIP(s, launch_init<T, VT>(ia, sgrid, s->stream));
+      }
+      JFNK_HIP(s, launch_cycle_begin(s->ctl, Partials{part(s, 3), sgrid}, m, s->stream));
+      JFNK_TRY(sync_read_ctl(s));
+      if (s->prof) prof_harvest(s, 0);
+      if (cycle == 0) go.bnorm = s->hctl->bnorm;
+      go.true_res = s->hctl->beta;
+      const int d0 = s->hctl->done_col[0];
+      if (d0 == kNonfinite) {
+        go.nonfinite = true;
+        break;
+      }
+      if (d0 == kConverged) {
+        go.converged = true;
+        break;
+      }
+      if (cycle == max_restarts) break;
+      go.cycles += 1;
+      // Arnoldi steps back to back; the Givens update of column j runs in the
+      // prologue of step j+1's JVP and reports its stop flag to mapped host
+      // memory.  After enqueueing step j the host waits for step j-1, whose
+      // JVP settled column j-2: at most two enqueued steps are skipped.
+      int jmax = -1;
+      for (int j = 0; j < m; ++j) {
+        s->cur_step = j;
+        const int K = j + 1;
+        if (j >= 1) flags[j - 1] = -1;
+        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j));
+        KArgs<T, VT> ka{s->npad, basis(s, 0), s->npad, w, basis(s, K), K, s->ctl, Partials{nullptr, 0}, part(s, 0)};
+        {
+          ProfScope ps(s, PK_A, (double)s->n * (K * sizeof(VT) + sizeof(T)));
+          JFNK_HIP(s, launch_cgs<T, VT>(PASS_A, ka, kgrid, s->stream));
+        }
+        ka.in = Partials{part(s, 0), kgrid};
+        ka.out = part(s, 1);
+        {
+          ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
+          JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, kgrid, s->stream));
+        }
+        ka.in = Partials{part(s, 1), kgrid};
+        ka.out = part(s, 2);
+        {
+          ProfScope ps(s, PK_C, (double)s->n * (K * sizeof(VT) + sizeof(T) + sizeof(VT)));
+          JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, kgrid, s->stream));
+        }
+        jmax = j;
+        JFNK_HIP(s, hipEventRecord(s->step_ev[j], s->stream));
+        if (j >= 2) {
+          JFNK_HIP(s, hipEventSynchronize(s->step_ev[j - 1]));
+          if (flags[j - 2] != kRunning) break;
+        }
+      }
+      s->cur_step = -1;
+      flags[jmax] = -1;
+      {
+        VyArgs<T, VT> va{s->npad, basis(s, 0), s->npad, dxi, updated ? 0 : 1, jmax, s->ctl,
+                         Partials{part(s, 2), kgrid}, part(s, 4), s->dflags};
+        ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
+        JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
+      }
+      updated = true;
+      JFNK_TRY(sync_read_ctl(s));
+      const int k = s->hctl->k;
+      if (s->prof) {
+        for (ProfRec& r : s->recs)
+          if (r.kid == PK_VY) r.bytes = (double)s->n * (k * sizeof(VT) + (cycle == 0 ? 1.0 : 2.0) * sizeof(T));
+        prof_harvest(s, k);
+      }
+      go.iters += k;
+      if (k > 0 && s->hctl->done_col[k] == kNonfinite) {
+        go.nonfinite = true;
+        break;
+      }
+    }
+    if (!updated) JFNK_HIP(s, launch_fill_zero<T>(s->npad, dxi, sgrid, s->stream));
+    return JFNK_OK;
+  }
+
+  static jfnk_status newton(jfnk_solver* s, double* x_user, const jfnk_options& o, jfnk_info* info) {
+    const long long n = s->n;
+    const bool f64 = std::is_same<T, double>::value;
+    const int sgrid = stream_grid(s, 2);
+    JFNK_HIP(s, hipMemcpyAsync(s->x64, x_user, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    auto cur_x = [&]() -> T* { return f64 ? reinterpret_cast<T*>(s->x64) : static_cast<T*>(s->xw); };
+    if (!f64) JFNK_HIP(s, launch_cast<T>(s->npad, s->x64, static_cast<T*>(s->xw), sgrid, s->stream));
+    if (o.history) JFNK_HIP(s, hipMemcpyAsync(o.history, s->x64, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    JFNK_TRY(residual(s, cur_x(), static_cast<T*>(s->F), true));
+    JFNK_TRY(sync_read_ctl(s));
+    if (s->prof) prof_harvest(s, 0);
+    const double n0 = std::sqrt(s->hctl->fnorm2);
+    double fk = n0;
+    info->f0_norm = n0;
+    int k = 0;
+    jfnk_status result = JFNK_ERR_NOT_CONVERGED;
+    while (true) {
+      if (!std::isfinite(fk)) {
+        result = JFNK_ERR_NONFINITE;
+        break;
+      }
+      const double rho = n0 > 0.0 ? fk / n0 : 0.0;
+      info->rel_res[k] = rho;
+      if (rho < o.tol_newton) {
+        result = JFNK_OK;
+        info->converged = 1;
+        break;
+      }
+      if (k == o.max_newton) {
+        result = JFNK_ERR_NOT_CONVERGED;
+        break;
+      }
+      GOut go;
+      JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
+                     o.fd_eps, o.eps_rule, o.breakdown_tol, go));
+      info->krylov_iters += go.iters;
+      info->restarts += go.cycles;
+      info->lin_iters[k] = go.iters;
+      if (go.nonfinite) {
+        result = JFNK_ERR_NONFINITE;
+        break;
+      }
+      double alpha = 1.0;
+      double ft = 0.0;
+      bool accepted = false;
+      for (int t = 0; t <= o.ls_max_backtracks; ++t) {
+        {
+          ProfScope ps(s, PK_TRIAL, (double)n * (16.0 + sizeof(T) + (f64 ? 0.0 : sizeof(T))));
+          JFNK_HIP(s, launch_trial<T>(s->npad, s->x64, static_cast<const T*>(s->dx), alpha, s->x64t,
+                                      f64 ? nullptr : static_cast<T*>(s->xwt), sgrid, s->stream));
+        }
+        const T* xt = f64 ? reinterpret_cast<const T*>(s->x64t) : static_cast<const T*>(s->xwt);
+        JFNK_TRY(residual(s, xt, static_cast<T*>(s->Ft), true));
+        JFNK_TRY(sync_read_ctl(s));
+        if (s->prof) prof_harvest(s, 0);
+        ft = std::sqrt(s->hctl->fnorm2);
+        if (std::isfinite(ft) && ft <= (1.0 - o.ls_c * alpha) * fk) {
+          accepted = true;
+          break;
+        }
+        if (t < o.ls_max_backtracks) {
+          alpha *= 0.5;
+          info->ls_backtracks += 1;
+        }
+      }
+      if (!accepted) info->ls_failures += 1;
+      info->alpha[k] = alpha;
+      std::swap(s->x64, s->x64t);
+      std::swap(s->xw, s->xwt);
+      std::swap(s->F, s->Ft);
+      fk = ft;
+      k += 1;
+      info->newton_iters = k;
+      if (o.history)
+        JFNK_HIP(s, hipMemcpyAsync(o.history + (long long)k * n, s->x64, n * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s->stream));
+    }
+    JFNK_HIP(s, hipMemcpyAsync(x_user, s->x64, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    JFNK_HIP(s, hipStreamSynchronize(s->stream));
+    return result;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// problem set-up
+// ---------------------------------------------------------------------------
+jfnk_status fill_problem(jfnk_solver* s) {
+  const jfnk_problem& p = s->prob;
+  Coefs& c = s->coefs;
+  std::memset(&c, 0, sizeof(c));
+  switch (p.id) {
+    case JFNK_BURGERS1D:
+      c.c[0] = 1.0 / (2.0 * p.hx);
+      c.c[1] = p.p[0] / (p.hx * p.hx);
+      break;
+    case JFNK_BURGERS2D:
+      c.c[0] = 1.0 / (2.0 * p.hx);
+      c.c[1] = 1.0 / (2.0 * p.hy);
+      c.c[2] = p.p[0] / (p.hx * p.hx);
+      c.c[3] = p.p[0] / (p.hy * p.hy);
+      break;
+    case JFNK_GRAYSCOTT2D:
+      c.c[0] = p.p[0] / (p.hx * p.hx);
+      c.c[1] = p.p[0] / (p.hy * p.hy);
+      c.c[2] = p.p[1] / (p.hx * p.hx);
+      c.c[3] = p.p[1] / (p.hy * p.hy);
+      c.c[4] = p.p[2] + p.p[3];
+      c.c[5] = p.p[2];
+      break;
+    case JFNK_KERR2D:
+      c.c[0] = 1.0 / (p.hx * p.hx);
+      c.c[1] = 1.0 / (p.hy * p.hy);
+      c.c[2] = p.p[0] * p.p[0];
+      c.c[3] = p.p[1];
+      c.c[4] = p.p[2];
+      c.c[5] = p.p[3];
+      break;
+    default:
+      s->err = "unknown problem id";
+      return JFNK_ERR_ARG;
+  }
+  if (p.id == JFNK_KERR2D) {
+    s->alpha = 0.0;
+    s->cN = 1.0;
+    s->beta = -1.0;
+  } else {
+    s->alpha = 1.0;
+    s->cN = p.theta * p.dt;
+    s->beta = -1.0;
+  }
+  return JFNK_OK;
+}
+
+bool problem_valid(const jfnk_problem* p, std::string* why) {
+  if (p == nullptr) {
+    if (why) *why = "null problem";
+    return false;
+  }
+  if (p->id < JFNK_BURGERS1D || p->id > JFNK_KERR2D) {
+    if (why) *why = "unknown problem id";
+    return false;
+  }
+  if (p->nx < 3 || (p->id == JFNK_BURGERS1D ? p->ny != 1 : p->ny < 3)) {
+    if (why) *why = "grid too small (nx >= 3; ny = 1 for 1D, ny >= 3 for 2D)";
+    return false;
+  }
+  if ((long long)p->nx * p->ny > (1LL << 30)) {
+    if (why) *why = "grid too large";
+    return false;
+  }
+  if (!(p->hx > 0.0) || (p->id != JFNK_BURGERS1D && !(p->hy > 0.0))) {
+    if (why) *why = "grid spacing must be positive";
+    return false;
+  }
+  if (p->id != JFNK_KERR2D && (!(p->dt > 0.0) || !(p->theta > 0.0) || p->theta > 1.0)) {
+    if (why) *why = "time-dependent problems need dt > 0 and 0 < theta <= 1";
+    return false;
+  }
+  return true;
+}
+
+long long problem_n(const jfnk_problem* p) {
+  const long long cells = (long long)p->nx * p->ny;
+  return p->id == JFNK_BURGERS1D ? cells : 2 * cells;
+}
+
+size_t max_blocks(const jfnk_problem* p, int cu) {
+  dim3 g, b;
+  stencil_shape(p->id, p->nx, p->ny, 1, g, b);
+  const size_t st = (size_t)g.x * g.y;
+  return std::max<size_t>({st, (size_t)4 * cu, (size_t)cu}) + 1;
+}
+
+size_t elem_size(int prec) { return prec == JFNK_F64 ? 8 : 4; }
+size_t basis_elem_size(int prec) { return prec == JFNK_F64 ? 8 : (prec == JFNK_F32 ? 4 : 2); }
+
+size_t footprint(const jfnk_problem* p, int prec, int m, int cu) {
+  const long long npad = round_up(problem_n(p), 256);
+  const size_t t = elem_size(prec);
+  size_t bytes = 0;
+  bytes += (size_t)(m + 1) * npad * basis_elem_size(prec);  // basis
+  bytes += 8 * (size_t)npad * t;                            // w R dx F Ft xw xwt b
+  bytes += 3 * (size_t)npad * 8;                            // x64 x64t tmp64
+  bytes += 6 * max_blocks(p, cu) * kPartStride * 8;         // partial-sum rows
+  bytes += sizeof(Ctl);
+  return bytes;
+}
+
+template <class T>
+jfnk_status malloc_dev(jfnk_solver* s, T** p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    s->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+    return JFNK_ERR_OOM;
+  }
+  *p = static_cast<T*>(q);
+  if (hipMemset(q, 0, bytes) != hipSuccess) {
+    s->err = "hipMemset failed";
+    return JFNK_ERR_HIP;
+  }
+  return JFNK_OK;
+}
+
+void release(jfnk_solver* s) {
+  void* bufs[] = {s->V, s->w, s->R, s->dx, s->F, s->Ft, s->xw, s->xwt, s->b, s->x64, s->x64t, s->tmp64,
+                  s->parts, s->ctl};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (s->hctl) (void)hipHostFree(s->hctl);
+  if (s->hflags) (void)hipHostFree(s->hflags);
+  for (hipEvent_t e : s->step_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->pool)
+    if (e) (void)hipEventDestroy(e);
+  for (ProfRec& r : s->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+namespace {
+// ||p||^2 of a caller vector into a device scalar (stream-ordered).
+template <class T>
+jfnk_status device_norm2(jfnk_solver* s, const T* p, double* out) {
+  double* part = s->parts + 5 * s->part_rows * kPartStride;
+  const int g = stream_grid(s, 1);
+  JFNK_HIP(s, launch_norm2<T>(s->n, p, part, g, s->stream));
+  JFNK_HIP(s, launch_finish_sums(Partials{part, g}, 1, out, nullptr, s->stream));
+  return JFNK_OK;
+}
+
+template <class T>
+jfnk_status jvp_api(jfnk_solver* s, const T* x, const T* v, T* Jv, T* F, int mode, double eps, int rule) {
+  EpsSpec e = eps_spec(s, eps, rule, &s->ctl->aux2);
+  if (mode == JFNK_JVP_FD && !(eps > 0.0)) {
+    JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
+    if (rule == JFNK_EPS_NORMALIZED) JFNK_TRY(device_norm2<T>(s, v, &s->ctl->aux2));
+  }
+  return Impl<T, T>::template jvp<T>(s, x, v, nullptr, Jv, mode == JFNK_JVP_AD ? F : nullptr, mode, e);
+}
+
+template <class T>
+jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, double tol, int max_restarts, int mode,
+                      double eps, int rule, jfnk_info* info) {
+  const long long n = s->n;
+  JFNK_HIP(s, hipMemcpyAsync(s->R, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
+  if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
+  const double brk = s->prec == JFNK_F64 ? 1e-14 : 1e-6;
+  typename Impl<T, T>::GOut go;
+  JFNK_TRY(Impl<T, T>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go));
+  JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  if (info) {
+    info->converged = go.converged ? 1 : 0;
+    info->krylov_iters = go.iters;
+    info->restarts = go.cycles;
+    info->final_res = go.true_res;
+    info->f0_norm = go.bnorm;
+    info->status = go.nonfinite ? JFNK_ERR_NONFINITE : JFNK_OK;
+  }
+  return go.nonfinite ? JFNK_ERR_NONFINITE : JFNK_OK;
+}
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t jfnk_problem_size(const jfnk_problem* problem) {
+  if (!problem_valid(problem, nullptr)) return 0;
+  return (size_t)problem_n(problem);
+}
+
+size_t jfnk_footprint_bytes(const jfnk_problem* problem, int precision, int m) {
+  if (!problem_valid(problem, nullptr) || m < 1 || m > kMaxM) return 0;
+  if (precision < JFNK_F64 || precision > JFNK_F16S) return 0;
+  return footprint(problem, precision, m, 256);
+}
+
+void jfnk_default_options(int precision, jfnk_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->m = 30;
+  o->max_restarts = 100;
+  o->max_newton = 15;
+  o->ls_max_backtracks = 10;
+  o->ls_c = 1e-4;
+  o->mode = JFNK_JVP_AD;
+  o->eps_rule = JFNK_EPS_PAPER;
+  if (precision == JFNK_F64) {
+    o->tol_newton = 1e-6;
+    o->tol_krylov = 1e-8;
+    o->breakdown_tol = 1e-14;
+  } else {
+    o->tol_newton = 1e-4;
+    o->tol_krylov = 1e-6;
+    o->breakdown_tol = 1e-6;
+  }
+}
+
+const char* jfnk_status_string(int status) {
+  switch (status) {
+    case JFNK_OK: return "ok";
+    case JFNK_ERR_ARG: return "invalid argument";
+    case JFNK_ERR_OOM: return "out of device memory";
+    case JFNK_ERR_HIP: return "HIP runtime error";
+    case JFNK_ERR_NONFINITE: return "non-finite value";
+    case JFNK_ERR_BREAKDOWN: return "Krylov breakdown";
+    case JFNK_ERR_NOT_CONVERGED: return "not converged";
+    default: return "unknown status";
+  }
+}
+
+const char* jfnk_last_error(const jfnk_solver* s) {
+  if (!s) return g_create_error.c_str();
+  return s->err.c_str();
+}
+
+jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void* hip_stream, jfnk_solver** out) {
+  if (!out) return JFNK_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  if (!problem_valid(problem, &why)) {
+    g_create_error = why;
+    return JFNK_ERR_ARG;
+  }
+  if (precision != JFNK_F64 && precision != JFNK_F32) {
+    g_create_error = "precision not supported by this build (F64 and F32 are)";
+    return JFNK_ERR_ARG;
+  }
+  if (m < 1 || m > kMaxM) {
+    g_create_error = "m must be in 1..32";
+    return JFNK_ERR_ARG;
+  }
+  jfnk_solver* s = new jfnk_solver();
+  s->prob = *problem;
+  s->prec = precision;
+  s->m = m;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->pid = problem->id;
+  s->n = problem_n(problem);
+  s->npad = round_up(s->n, 256);
+  s->tsize = elem_size(precision);
+  s->vsize = basis_elem_size(precision);
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      prop.multiProcessorCount > 0)
+    s->cu = prop.multiProcessorCount;
+  jfnk_status st = fill_problem(s);
+  const size_t vec_bytes = (size_t)s->npad * s->tsize;
+  if (st == JFNK_OK) st = malloc_dev(s, &s->V, (size_t)(m + 1) * s->npad * s->vsize);
+  void** tv[] = {&s->w, &s->R, &s->dx, &s->F, &s->Ft, &s->xw, &s->xwt, &s->b};
+  for (void** p : tv)
+    if (st == JFNK_OK) st = malloc_dev(s, p, vec_bytes);
+  if (st == JFNK_OK) st = malloc_dev(s, &s->x64, (size_t)s->npad * 8);
+  if (st == JFNK_OK) st = malloc_dev(s, &s->x64t, (size_t)s->npad * 8);
+  if (st == JFNK_OK) st = malloc_dev(s, &s->tmp64, (size_t)s->npad * 8);
+  s->part_rows = max_blocks(problem, s->cu);
+  if (st == JFNK_OK) st = malloc_dev(s, &s->parts, 6 * s->part_rows * kPartStride * sizeof(double));
+  if (st == JFNK_OK) st = malloc_dev(s, &s->ctl, sizeof(Ctl));
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+      s->err = "hipHostMalloc failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hctl = static_cast<Ctl*>(h);
+      std::memset(s->hctl, 0, sizeof(Ctl));
+    }
+  }
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(int) * (kMaxM + 1), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      s->err = "hipHostMalloc (flags) failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hflags = static_cast<int*>(h);
+      void* d = nullptr;
+      if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        s->err = "hipHostGetDevicePointer failed";
+        st = JFNK_ERR_HIP;
+      }
+      s->dflags = static_cast<int*>(d);
+    }
+  }
+  if (st == JFNK_OK) {
+    s->step_ev.assign(kMaxM, nullptr);
+    for (auto& e : s->step_ev)
+      if (st == JFNK_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        s->err = "hipEventCreate failed";
+        st = JFNK_ERR_HIP;
+      }
+  }
+  if (st == JFNK_OK && hipDeviceSynchronize() != hipSuccess) {
+    s->err = "device synchronize after set-up failed";
+    st = JFNK_ERR_HIP;
+  }
+  if (st != JFNK_OK) {
+    g_create_error = s->err;
+    release(s);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_destroy(jfnk_solver* s) {
+  if (!s) return JFNK_ERR_ARG;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  release(s);
+  delete s;
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double* source) {
+  if (!s) return JFNK_ERR_ARG;
+  const jfnk_problem& p = s->prob;
+  const long long n = s->n;
+  const int sgrid = stream_grid(s, 2);
+  if (p.id == JFNK_KERR2D) {
+    // b = f (the source), cast to the working precision
+    if (source == nullptr) {
+      if (s->prec == JFNK_F64)
+        JFNK_HIP(s, launch_fill_zero<double>(s->npad, static_cast<double*>(s->b), sgrid, s->stream));
+      else
+        JFNK_HIP(s, launch_fill_zero<float>(s->npad, static_cast<float*>(s->b), sgrid, s->stream));
+    } else if (s->prec == JFNK_F64) {
+      JFNK_HIP(s, hipMemcpyAsync(s->b, source, n * 8, hipMemcpyDeviceToDevice, s->stream));
+    } else {
+      JFNK_HIP(s, hipMemcpyAsync(s->tmp64, source, n * 8, hipMemcpyDeviceToDevice, s->stream));
+      JFNK_HIP(s, launch_cast<float>(s->npad, s->tmp64, static_cast<float*>(s->b), sgrid, s->stream));
+    }
+    s->has_prev = true;
+    return JFNK_OK;
+  }
+  if (x_prev == nullptr) {
+    s->err = "x_prev is required for time-dependent problems";
+    return JFNK_ERR_ARG;
+  }
+  // b = x^n - (1 - theta) dt N(x^n) + dt s, evaluated in FP64
+  StencilArgs<double, double> a{};
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.plane = (long long)p.nx * p.ny;
+  a.x = x_prev;
+  a.b = source;
+  a.alpha = 1.0;
+  a.cN = -(1.0 - p.theta) * p.dt;
+  a.beta = p.dt;
+  a.nred = 0;
+  double* dst = s->prec == JFNK_F64 ? static_cast<double*>(s->b) : s->tmp64;
+  a.out = dst;
+  const int vec = stencil_vec<double>(s->pid);
+  const bool vz = (p.nx % vec == 0) && aligned(x_prev, 16) && aligned(source, 16);
+  JFNK_HIP(s, launch_stencil<double, double>(s->pid, OP_RES, false, vz, a, s->coefs, s->stream));
+  if (s->prec != JFNK_F64)
+    JFNK_HIP(s, launch_cast<float>(s->npad, s->tmp64, static_cast<float*>(s->b), sgrid, s->stream));
+  s->has_prev = true;
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_residual(jfnk_solver* s, const void* x, void* F) {
+  if (!s || !x || !F) return JFNK_ERR_ARG;
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  if (s->prec == JFNK_F64) return Impl<double, double>::residual(s, (const double*)x, (double*)F, false);
+  return Impl<float, float>::residual(s, (const float*)x, (float*)F, false);
+}
+
+
+jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, void* F_or_null, int mode, double eps,
+                     int eps_rule) {
+  if (!s || !x || !v || !Jv) return JFNK_ERR_ARG;
+  if (mode != JFNK_JVP_AD && mode != JFNK_JVP_FD) return JFNK_ERR_ARG;
+  if (eps_rule != JFNK_EPS_PAPER && eps_rule != JFNK_EPS_NORMALIZED) return JFNK_ERR_ARG;
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  if (s->prec == JFNK_F64)
+    return jvp_api<double>(s, (const double*)x, (const double*)v, (double*)Jv, (double*)F_or_null, mode, eps,
+                           eps_rule);
+  return jvp_api<float>(s, (const float*)x, (const float*)v, (float*)Jv, (float*)F_or_null, mode, eps, eps_rule);
+}
+
+jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx, int m, double tol, int max_restarts,
+                       int mode, double eps, int eps_rule, jfnk_info* info) {
+  if (!s || !x || !rhs || !dx) return JFNK_ERR_ARG;
+  if (m < 1 || m > s->m || max_restarts < 0 || !(tol >= 0.0)) {
+    s->err = "m must be in 1..(solver m), max_restarts >= 0, tol >= 0";
+    return JFNK_ERR_ARG;
+  }
+  if (mode != JFNK_JVP_AD && mode != JFNK_JVP_FD) return JFNK_ERR_ARG;
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  const auto t0 = std::chrono::steady_clock::now();
+  jfnk_status st;
+  if (s->prec == JFNK_F64)
+    st = gmres_api<double>(s, (const double*)x, (const double*)rhs, (double*)dx, m, tol, max_restarts, mode, eps,
+                           eps_rule, info);
+  else
+    st = gmres_api<float>(s, (const float*)x, (const float*)rhs, (float*)dx, m, tol, max_restarts, mode, eps,
+                          eps_rule, info);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts, jfnk_info* info) {
+  if (!s || !x_inout || !opts || !info) return JFNK_ERR_ARG;
+  const jfnk_options& o = *opts;
+  if (o.m < 1 || o.m > s->m || o.max_newton < 0 || o.max_newton > JFNK_MAX_ITERS || o.max_restarts < 0 ||
+      o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
+      (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0)) {
+    s->err = "invalid options";
+    return JFNK_ERR_ARG;
+  }
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  const auto t0 = std::chrono::steady_clock::now();
+  jfnk_status st;
+  if (s->prec == JFNK_F64)
+    st = Impl<double, double>::newton(s, x_inout, o, info);
+  else
+    st = Impl<float, float>::newton(s, x_inout, o, info);
+  info->status = st;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+jfnk_status jfnk_profile_enable(jfnk_solver* s, int on) {
+  if (!s) return JFNK_ERR_ARG;
+  if (!on && s->prof) {
+    JFNK_HIP(s, hipStreamSynchronize(s->stream));
+    prof_harvest(s, 1 << 30);
+  }
+  s->prof = on != 0;
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_profile_read(jfnk_solver* s, int kernel, long long* launches, double* total_ms, double* bytes) {
+  if (!s || kernel < 0 || kernel >= kNumProf) return JFNK_ERR_ARG;
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  prof_harvest(s, 1 << 30);
+  if (launches) *launches = s->p_count[kernel];
+  if (total_ms) *total_ms = s->p_ms[kernel];
+  if (bytes) *bytes = s->p_bytes[kernel];
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_profile_reset(jfnk_solver* s) {
+  if (!s) return JFNK_ERR_ARG;
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  prof_harvest(s, 1 << 30);
+  for (int i = 0; i < kNumProf; ++i) {
+    s->p_count[i] = 0;
+    s->p_ms[i] = 0.0;
+    s->p_bytes[i] = 0.0;
+  }
+  return JFNK_OK;
+}
+
+}  // extern "C"

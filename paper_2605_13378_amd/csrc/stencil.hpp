@@ -1,0 +1,317 @@
+// Fused stencil kernel: residual, AD JVP and FD JVP in one template.
+//
+//   OP_RES: out = alpha x + cN N(x) + beta b                 (residual F(x))
+//   OP_AD : out = alpha v + cN [N'(x) v]   (+ out2 = F(x))   (AD JVP, dual numbers)
+//   OP_FD : out = (F(x + eps v) - F(x)) / eps                (FD JVP, both in registers)
+//
+// Paper, Section 2: the AD JVP returns F(x) and J(x) v from one evaluation of
+// the residual on dual numbers; the FD JVP evaluates the same residual twice
+// and differences.  Here both live in a single pass over HBM: each thread
+// owns VEC consecutive columns of RY consecutive rows, loads rows
+// r0-1 .. r0+RY (periodic wrap, or clamp for PEC) of x (and v) once with
+// 8/16-byte accesses, gets its left/right neighbours from the adjacent lane
+// by cross-lane shuffle (global load only at wavefront and grid edges), and
+// writes out with vector stores.  The tangent is carried in the same
+// registers as the value (dual<T>), so the AD JVP costs one read of x and v
+// and one write of Jv: three vectors of HBM traffic.
+//
+// Layout: SoA planes (field f at f * plane), row-major rows of nx elements;
+// Kerr: interleaved (re, im) pairs.  Any nx, ny; the vector path needs nx a
+// multiple of VEC and 16-byte aligned pointers (the host picks VEC = 1
+// otherwise).  Optional FP64 reductions of sum(out^2) and sum(x^2) (residual
+// norm and state norm for the FD step) go through grid_reduce.
+#pragma once
+
+#include "common.hpp"
+#include "krylov.hpp"
+#include "problems.hpp"
+
+namespace jfnk {
+
+enum { OP_RES = 0, OP_AD = 1, OP_FD = 2 };
+
+template <class T, class VT>
+struct StencilArgs {
+  int nx, ny;
+  long long plane;     // nx * ny
+  const T* x;          // linearization point / state
+  const VT* v;         // direction (stored; true v = vscale * v)
+  const T* b;          // pointwise term multiplied by beta (nullable -> 0)
+  T* out;              // F (RES) or Jv
+  T* out2;             // F (AD with F output), nullable
+  double alpha, cN, beta;
+  const double* vscale;  // device scalar, nullable -> 1
+  EpsSpec eps;
+  // Arnoldi JVP of step arn_j (ctl non-null): finishes the Givens update of
+  // column arn_j - 1 from pass C's partials `pc`, stops early once the cycle
+  // is done, and takes the basis scale from that update.
+  Ctl* ctl;
+  int arn_j;
+  Partials pc;
+  int* host_flags;
+  double* part_out;      // RES: partial rows of sum(out^2) and sum(x^2)
+  int nred;              // 0, 1 or 2 reductions
+};
+
+template <bool PERIODIC>
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+  if (PERIODIC) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <class P, class S, int VEC>
+__device__ __forceinline__ void load_nodes(const S* __restrict__ base, long long plane, int nx, int r, int c,
+                                           S (&out)[P::NF][VEC]) {
+  if constexpr (P::kInterleaved) {
+    S tmp[2 * VEC];
+    load_vec<S, 2 * VEC>(base + 2 * ((long long)r * nx + c), tmp);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      out[0][e] = tmp[2 * e];
+      out[1][e] = tmp[2 * e + 1];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) load_vec<S, VEC>(base + f * plane + (long long)r * nx + c, out[f]);
+  }
+}
+
+template <class P, class S>
+__device__ __forceinline__ S load_node(const S* __restrict__ base, long long plane, int nx, int r, int c, int f) {
+  if constexpr (P::kInterleaved) return base[2 * ((long long)r * nx + c) + f];
+  return base[f * plane + (long long)r * nx + c];
+}
+
+template <class P, class S, int VEC>
+__device__ __forceinline__ void store_nodes(S* __restrict__ base, long long plane, int nx, int r, int c,
+                                            const S (&in)[P::NF][VEC]) {
+  if constexpr (P::kInterleaved) {
+    S tmp[2 * VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      tmp[2 * e] = in[0][e];
+      tmp[2 * e + 1] = in[1][e];
+    }
+    store_vec<S, 2 * VEC>(base + 2 * ((long long)r * nx + c), tmp);
+  } else {
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) store_vec<S, VEC>(base + f * plane + (long long)r * nx + c, in[f]);
+  }
+}
+
+// Rows [r0-1, r0+RY] (2D) or the single row (1D) of one array for one thread,
+// plus the left/right halo of every centre row.
+template <class P, class T, int VEC, int RY>
+struct Tile {
+  static constexpr int NR = P::kDim2 ? RY + 2 : 1;
+  static constexpr int RC = P::kDim2 ? RY : 1;
+  T a[P::NF][NR][VEC];
+  T lh[P::NF][RC];
+  T rh[P::NF][RC];
+
+  template <class S>
+  __device__ __forceinline__ void load(const S* __restrict__ base, long long plane, int nx, int ny, int r0,
+                                       int col0, int cc, int lane, T scale) {
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + t, ny) : 0;
+      S tmp[P::NF][VEC];
+      load_nodes<P, S, VEC>(base, plane, nx, r, cc, tmp);
+#pragma unroll
+      for (int f = 0; f < P::NF; ++f)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) a[f][t][e] = to_c<T>(tmp[f][e]) * scale;
+    }
+    const int cl = wrap_idx<P::kPeriodic>(col0 - 1, nx);
+    const int cr = wrap_idx<P::kPeriodic>(col0 + VEC, nx);
+    const bool need_l = (lane == 0) || (col0 == 0);
+    const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
+#pragma unroll
+    for (int tt = 0; tt < RC; ++tt) {
+      const int t = P::kDim2 ? tt + 1 : 0;
+      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 + tt, ny) : 0;
+#pragma unroll
+      for (int f = 0; f < P::NF; ++f) {
+        T lv = __shfl_up(a[f][t][VEC - 1], 1, kWave);
+        T rv = __shfl_down(a[f][t][0], 1, kWave);
+        if (need_l) lv = to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) * scale;
+        if (need_r) rv = to_c<T>(load_node<P, S>(base, plane, nx, r, cr, f)) * scale;
+        lh[f][tt] = lv;
+        rh[f][tt] = rv;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void nbr(int tt, int e, Nbr<T> (&o)[P::NF]) const {
+    const int t = P::kDim2 ? tt + 1 : 0;
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) {
+      o[f].c = a[f][t][e];
+      o[f].l = e > 0 ? a[f][t][e - 1] : lh[f][tt];
+      o[f].r = e < VEC - 1 ? a[f][t][e + 1] : rh[f][tt];
+      o[f].d = P::kDim2 ? a[f][t - 1][e] : a[f][t][e];
+      o[f].u = P::kDim2 ? a[f][t + 1][e] : a[f][t][e];
+    }
+  }
+};
+
+template <class P, class T, class VT, int VEC, int RY, int OP, bool WITHF>
+__global__ void __launch_bounds__(256)
+stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
+  double vscale = 1.0;
+  if constexpr (OP != OP_RES) {
+    if (a.ctl != nullptr) {
+      const int j = a.arn_j;
+      if (j == 0) {
+        if (a.ctl->done_col[0] != kRunning) return;
+        vscale = a.ctl->scale[0];
+      } else {
+        const int prev = a.ctl->done_col[j - 1];
+        if (prev != kRunning) {
+          // the cycle stopped earlier: carry the state forward so that the
+          // flags stay monotone (later kernels only look at their own column)
+          if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+            a.ctl->done_col[j] = prev;
+            if (a.host_flags) a.host_flags[j - 1] = prev;
+          }
+          return;
+        }
+        __shared__ double col[kMaxM + 1];
+        const GivensOut g = finish_column(a.ctl, j - 1, a.pc, a.host_flags, col);
+        if (g.done != kRunning) return;
+        vscale = 1.0 / g.wn;
+      }
+    } else if (a.vscale != nullptr) {
+      vscale = *a.vscale;
+    }
+  }
+  constexpr int NF = P::NF;
+  constexpr int RC = P::kDim2 ? RY : 1;
+  const auto k = P::template make<T>(coefs);
+  const int nx = a.nx, ny = a.ny;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int col0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int r0 = P::kDim2 ? (blockIdx.y * blockDim.y + threadIdx.y) * RY : 0;
+  const bool colok = col0 < nx;
+  const int cc = colok ? col0 : 0;
+  const T alpha = T(a.alpha), cN = T(a.cN), beta = T(a.beta);
+
+  Tile<P, T, VEC, RY> X;
+  X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane, T(1));
+
+  double eps = 0.0;
+  T eps_s = T(0);
+  Tile<P, T, VEC, RY> Vt;
+  if constexpr (OP == OP_AD) {
+    Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane, T(vscale));
+  } else if constexpr (OP == OP_FD) {
+    double vn2 = -1.0;
+    if (a.eps.vparts.nb > 0) {
+      __shared__ double tot[1];
+      reduce_partials(a.eps.vparts.part, a.eps.vparts.nb, 1, tot);
+      vn2 = tot[0];
+    }
+    eps = fd_eps(a.eps, vn2);
+    eps_s = T(eps * vscale);
+    Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane, T(1));
+  }
+  const T eps_t = T(eps);
+
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int tt = 0; tt < RC; ++tt) {
+    const int r = r0 + tt;
+    const bool ok = colok && (!P::kDim2 || r < ny);
+    const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
+    T bval[NF][VEC];
+    if (a.b != nullptr) {
+      load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval);
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) bval[f][e] = T(0);
+    }
+    T o[NF][VEC];
+    T o2[NF][VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      Nbr<T> xn[NF];
+      X.nbr(tt, e, xn);
+      const bool bnd = P::boundary(col0 + e, rr, nx, ny);
+      if constexpr (OP == OP_RES) {
+        T n[NF];
+        P::template N<T, T>(k, xn, n);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[f][e];
+      } else if constexpr (OP == OP_AD) {
+        Nbr<T> vn[NF];
+        Vt.nbr(tt, e, vn);
+        Nbr<dual<T>> dn[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          dn[f].c = {xn[f].c, vn[f].c};
+          dn[f].l = {xn[f].l, vn[f].l};
+          dn[f].r = {xn[f].r, vn[f].r};
+          dn[f].d = {xn[f].d, vn[f].d};
+          dn[f].u = {xn[f].u, vn[f].u};
+        }
+        dual<T> n[NF];
+        P::template N<T, dual<T>>(k, dn, n);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          o[f][e] = bnd ? vn[f].c : alpha * vn[f].c + cN * n[f].t;
+          o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[f][e];
+        }
+      } else {
+        Nbr<T> vn[NF];
+        Vt.nbr(tt, e, vn);
+        Nbr<T> yn[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          yn[f].c = xn[f].c + eps_s * vn[f].c;
+          yn[f].l = xn[f].l + eps_s * vn[f].l;
+          yn[f].r = xn[f].r + eps_s * vn[f].r;
+          yn[f].d = xn[f].d + eps_s * vn[f].d;
+          yn[f].u = xn[f].u + eps_s * vn[f].u;
+        }
+        T n0[NF], n1[NF];
+        P::template N<T, T>(k, xn, n0);
+        P::template N<T, T>(k, yn, n1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[f][e];
+          const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[f][e];
+          o[f][e] = (f1 - f0) / eps_t;
+        }
+      }
+    }
+    if (ok) {
+      store_nodes<P, T, VEC>(a.out, a.plane, nx, rr, cc, o);
+      if constexpr (OP == OP_AD && WITHF) store_nodes<P, T, VEC>(a.out2, a.plane, nx, rr, cc, o2);
+      if constexpr (OP == OP_RES) {
+        const int t = P::kDim2 ? tt + 1 : 0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            acc[0] += (double)o[f][e] * (double)o[f][e];
+            acc[1] += (double)X.a[f][t][e] * (double)X.a[f][t][e];
+          }
+      }
+    }
+  }
+
+  if constexpr (OP == OP_RES) {
+    if (a.nred > 0) {
+      __shared__ double lds[2 * 4];
+      block_partials<2>(acc, a.nred, a.part_out, lds);
+    }
+  }
+}
+
+}  // namespace jfnk

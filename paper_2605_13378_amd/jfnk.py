@@ -1,0 +1,287 @@
+"""ctypes binding of libjfnk.so (include/jfnk.h).
+
+Argument marshalling only: tensors are checked (device, dtype, length,
+contiguity) and their device pointers handed to the C ABI; every step of the
+method runs in the library's HIP kernels.  PyTorch provides device memory and
+the current HIP stream.  There is no fallback: if the library is not built or
+cannot be loaded, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjfnk.so")
+
+MAX_ITERS = 64
+
+PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3}
+PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
+MODES = {"ad": 0, "fd": 1}
+EPS_RULES = {"paper": 0, "normalized": 1}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
+          5: "breakdown", 6: "not_converged"}
+PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
+                   "cycle_start": 7, "newton_trial": 8}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("dt", ctypes.c_double), ("theta", ctypes.c_double),
+                ("p", ctypes.c_double * 8)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("max_restarts", ctypes.c_int), ("max_newton", ctypes.c_int),
+                ("ls_max_backtracks", ctypes.c_int),
+                ("tol_krylov", ctypes.c_double), ("tol_newton", ctypes.c_double), ("ls_c", ctypes.c_double),
+                ("fd_eps", ctypes.c_double), ("breakdown_tol", ctypes.c_double),
+                ("mode", ctypes.c_int), ("eps_rule", ctypes.c_int),
+                ("history", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("newton_iters", ctypes.c_int),
+                ("krylov_iters", ctypes.c_int), ("restarts", ctypes.c_int), ("ls_backtracks", ctypes.c_int),
+                ("ls_failures", ctypes.c_int), ("lin_iters", ctypes.c_int * MAX_ITERS),
+                ("rel_res", ctypes.c_double * (MAX_ITERS + 1)), ("alpha", ctypes.c_double * MAX_ITERS),
+                ("f0_norm", ctypes.c_double), ("final_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        k = self.newton_iters
+        return dict(status=STATUS.get(self.status, str(self.status)), converged=bool(self.converged),
+                    newton_iters=k, krylov_iters=self.krylov_iters, restarts=self.restarts,
+                    ls_backtracks=self.ls_backtracks, ls_failures=self.ls_failures,
+                    lin_iters=list(self.lin_iters[:k]), rel_res=list(self.rel_res[: k + 1]),
+                    alphas=list(self.alpha[:k]), f0_norm=self.f0_norm, final_res=self.final_res,
+                    seconds=self.seconds)
+
+
+class JfnkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGNATURES = [
+    ("jfnk_create", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_void_p)]),
+    ("jfnk_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("jfnk_footprint_bytes", ctypes.c_size_t, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int]),
+    ("jfnk_problem_size", ctypes.c_size_t, [ctypes.POINTER(Problem)]),
+    ("jfnk_set_previous", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("jfnk_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("jfnk_jvp", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int]),
+    ("jfnk_gmres", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, ctypes.POINTER(Info)]),
+    ("jfnk_newton_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
+                                         ctypes.POINTER(Info)]),
+    ("jfnk_default_options", None, [ctypes.c_int, ctypes.POINTER(Options)]),
+    ("jfnk_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("jfnk_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
+    ("jfnk_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("jfnk_profile_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    ("jfnk_profile_reset", ctypes.c_int, [ctypes.c_void_p]),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libjfnk.so (built in place); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2605_13378_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return [name for name, _, _ in _SIGNATURES]
+
+
+def make_problem(spec: dict) -> Problem:
+    """Problem struct from a workload spec dict (see the workloads module)."""
+    kind = spec["kind"]
+    p = Problem()
+    p.id = PROBLEM_IDS[kind]
+    p.nx = int(spec["nx"])
+    p.ny = int(spec.get("ny", 1))
+    p.hx = float(spec["hx"])
+    p.hy = float(spec.get("hy", 1.0))
+    p.dt = float(spec.get("dt", 0.0))
+    p.theta = float(spec.get("theta", 1.0))
+    if kind in ("burgers1d", "burgers2d"):
+        vals = [spec["nu"]]
+    elif kind == "grayscott":
+        vals = [spec["D"], spec["Dv"], spec["F"], spec["k"]]
+    else:
+        vals = [spec["k0"], spec.get("eps_re", 1.0), spec.get("eps_im", 0.0), spec["chi3"]]
+    for i, v in enumerate(vals):
+        p.p[i] = float(v)
+    return p
+
+
+def default_options(precision: str = "f64", **kw) -> Options:
+    o = Options()
+    lib().jfnk_default_options(PRECISIONS[precision], ctypes.byref(o))
+    for key, val in kw.items():
+        if key == "mode":
+            val = MODES[val]
+        elif key == "eps_rule":
+            val = EPS_RULES[val]
+        elif key == "history":
+            val = None if val is None else val.data_ptr()
+        setattr(o, key, val)
+    return o
+
+
+def footprint_bytes(spec: dict, precision: str = "f64", m: int = 30) -> int:
+    p = make_problem(spec)
+    return int(lib().jfnk_footprint_bytes(ctypes.byref(p), PRECISIONS[precision], m))
+
+
+def problem_size(spec: dict) -> int:
+    p = make_problem(spec)
+    return int(lib().jfnk_problem_size(ctypes.byref(p)))
+
+
+class Solver:
+    """One problem shape and precision on the current HIP stream."""
+
+    def __init__(self, spec: dict, precision: str = "f64", m: int = 30, stream=None):
+        import torch
+
+        self._torch = torch
+        self.spec = dict(spec)
+        self.precision = precision
+        self.m = m
+        self.n = problem_size(spec)
+        self.wdtype = torch.float64 if precision == "f64" else torch.float32
+        st = torch.cuda.current_stream() if stream is None else stream
+        self.stream = st
+        prob = make_problem(spec)
+        h = ctypes.c_void_p()
+        rc = lib().jfnk_create(ctypes.byref(prob), PRECISIONS[precision], m, ctypes.c_void_p(st.cuda_stream),
+                               ctypes.byref(h))
+        if rc != 0:
+            raise JfnkError(rc, lib().jfnk_last_error(None).decode())
+        self._h = h
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc: int, allowed=(0,)):
+        if rc not in allowed:
+            raise JfnkError(rc, lib().jfnk_last_error(self._h).decode())
+        return rc
+
+    def _vec(self, t, dtype, name):
+        torch = self._torch
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+        if t.numel() != self.n or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {self.n} elements")
+        return t
+
+    def _new(self, dtype=None):
+        return self._torch.empty(self.n, dtype=dtype or self.wdtype, device="cuda")
+
+    # -- the C ABI calls -------------------------------------------------------
+    def set_previous(self, x_prev, source=None):
+        torch = self._torch
+        self._prev = self._vec(x_prev, torch.float64, "x_prev") if x_prev is not None else None
+        self._src = self._vec(source, torch.float64, "source")
+        self._check(lib().jfnk_set_previous(self._h, None if self._prev is None else self._prev.data_ptr(),
+                                            None if self._src is None else self._src.data_ptr()))
+
+    def residual(self, x, out=None):
+        x = self._vec(x, self.wdtype, "x")
+        out = self._new() if out is None else self._vec(out, self.wdtype, "out")
+        self._check(lib().jfnk_residual(self._h, x.data_ptr(), out.data_ptr()))
+        return out
+
+    def jvp(self, x, v, mode="ad", eps=0.0, eps_rule="paper", want_F=False):
+        x = self._vec(x, self.wdtype, "x")
+        v = self._vec(v, self.wdtype, "v")
+        jv = self._new()
+        F = self._new() if (want_F and mode == "ad") else None
+        self._check(lib().jfnk_jvp(self._h, x.data_ptr(), v.data_ptr(), jv.data_ptr(),
+                                   None if F is None else F.data_ptr(), MODES[mode], float(eps),
+                                   EPS_RULES[eps_rule]))
+        return (jv, F) if want_F else jv
+
+    def gmres(self, x, rhs, m=None, tol=1e-8, max_restarts=100, mode="ad", eps=0.0, eps_rule="paper"):
+        x = self._vec(x, self.wdtype, "x")
+        rhs = self._vec(rhs, self.wdtype, "rhs")
+        dx = self._new()
+        info = Info()
+        self._check(lib().jfnk_gmres(self._h, x.data_ptr(), rhs.data_ptr(), dx.data_ptr(),
+                                     self.m if m is None else m, tol, max_restarts, MODES[mode], float(eps),
+                                     EPS_RULES[eps_rule], ctypes.byref(info)), allowed=(0, 4))
+        d = info.as_dict()
+        d["converged"] = bool(info.converged)
+        return dx, d
+
+    def newton_solve(self, x0, history: bool = False, **opts):
+        torch = self._torch
+        x = self._vec(x0, torch.float64, "x0").clone()
+        hist = None
+        if history:
+            mn = opts.get("max_newton", 15)
+            hist = torch.zeros((mn + 1) * self.n, dtype=torch.float64, device="cuda")
+            opts["history"] = hist
+        o = default_options(self.precision, **opts)
+        if o.m > self.m:
+            raise ValueError("options.m exceeds the solver's m")
+        info = Info()
+        # converged, non-finite and not-converged solves all report through info
+        self._check(lib().jfnk_newton_solve(self._h, x.data_ptr(), ctypes.byref(o), ctypes.byref(info)),
+                    allowed=(0, 4, 6))
+        d = info.as_dict()
+        if history:
+            d["history"] = hist.view(-1, self.n)[: info.newton_iters + 1]
+        return x, d
+
+    # -- profiling ------------------------------------------------------------
+    def profile(self, on: bool = True):
+        self._check(lib().jfnk_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        self._check(lib().jfnk_profile_reset(self._h))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for name, kid in PROFILE_KERNELS.items():
+            n = ctypes.c_longlong()
+            ms = ctypes.c_double()
+            by = ctypes.c_double()
+            self._check(lib().jfnk_profile_read(self._h, kid, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+            out[name] = dict(launches=n.value, ms=ms.value, bytes=by.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().jfnk_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,66 @@
+"""Shared helpers of the GPU parity tests: seeded cases and tensor plumbing.
+
+Inputs come from the ``workloads`` generators only; expected values come from
+the oracle only.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+import workloads as W
+
+
+def torch_mod():
+    import torch
+
+    return torch
+
+
+def gpu_available() -> bool:
+    try:
+        torch = torch_mod()
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def dev(a, dtype):
+    torch = torch_mod()
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def wdtype(prec):
+    torch = torch_mod()
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def case(kind: str, nx: int, ny: int | None = None, seed: int = 0):
+    """(spec, x_prev, source) of a small problem of the given kind and grid."""
+    if kind == "burgers1d":
+        spec = W.burgers1d_spec(nx)
+        return spec, W.burgers1d_initial(nx, seed), None
+    ny = nx if ny is None else ny
+    if kind == "grayscott":
+        spec = dict(W.grayscott_spec(nx), ny=ny)
+        return spec, W.grayscott_initial(nx, seed, ny=ny, side_frac=1 / 8, patches=6), None
+    if kind == "burgers2d":
+        spec = dict(W.burgers2d_spec(nx, nu=0.02, dt=0.01), ny=ny, hy=2 * np.pi / ny)
+        u = W.random_vector(2 * nx * ny, seed, 0.5)
+        return spec, u, None
+    if kind == "kerr":
+        spec = dict(W.kerr_spec(nx, chi3=0.3, cells_per_wavelength=8.0, eps_im=0.05), ny=ny)
+        src = W.kerr_gaussian_source(nx, amp=1.0, sigma=max(1.0, nx / 8), ny=ny)
+        return spec, np.zeros(2 * nx * ny), src
+    raise KeyError(kind)
+
+
+def rel_err(got, ref, x=None):
+    scale = max(1.0, float(np.abs(ref).max()))
+    if x is not None:
+        scale = max(scale, float(np.abs(x).max()))
+    return float(np.abs(got - ref).max()) / scale
