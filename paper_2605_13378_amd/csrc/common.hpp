@@ -69,6 +69,18 @@ template <> __device__ __forceinline__ float to_c<float, __half>(__half x) { ret
 template <class S, class C> __device__ __forceinline__ S to_s(C x) { return static_cast<S>(x); }
 template <> __device__ __forceinline__ __half to_s<__half, float>(float x) { return __float2half_rn(x); }
 
+// Wave-uniform values moved to scalar registers (the coefficients of the
+// Krylov updates), freeing vector registers for the register-resident basis.
+__device__ __forceinline__ float uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
@@ -78,19 +90,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block partial sums.  A reducing kernel writes one row of FP64 partial sums
-// per block (row-major [block][kPartStride]); the next kernel in stream order
-// adds the rows in its prologue (reduce_partials), every block alike and in
-// the same order.  The kernel boundary makes the rows visible, so no kernel
-// needs a grid-wide fence or atomic (on gfx950 a device-scope fence writes
-// back and invalidates the whole L2), and results depend only on the launch
-// shape, never on timing.
-constexpr int kPartStride = kMaxM + 2;
+// Block partial sums.  A reducing kernel writes one FP64 partial sum per
+// block and column; the next kernel in stream order adds them in its
+// prologue (reduce_partials), every block alike and in the same order.  The
+// kernel boundary makes the sums visible, so no kernel needs a grid-wide
+// fence or atomic (on gfx950 a device-scope fence writes back and
+// invalidates the whole L2), and results depend only on the launch shape,
+// never on timing.  Storage is column-major: column c of block b at
+// part[c * ld + b], so the lanes summing one column read consecutive words.
+constexpr int kMaxCols = kMaxM + 1;
 
-// Write this block's sums of acc[k], k < nr, to row blockIdx of `part`.
+struct Partials {
+  const double* part;
+  int nb;  // rows (blocks of the producer); 0 = none
+  int ld;  // column stride
+};
+
+// Destination of a producer's partial sums.
+struct PartSink {
+  double* part;
+  int ld;
+};
+
+// Write this block's sums of acc[k], k < nr, to column k, row blockIdx.
 // `lds` must hold NR * (threads / 64) doubles.  All threads must call it.
 template <int NR>
-__device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double* __restrict__ part, double* lds) {
+__device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double* __restrict__ part, int ld,
+                                               double* lds) {
   const int nthreads = blockDim.x * blockDim.y;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -108,13 +134,15 @@ __device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double
   if (tid < nr) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += lds[tid * nw + w];
-    part[(size_t)bid * kPartStride + tid] = s;
+    part[(size_t)tid * ld + bid] = s;
   }
 }
 
-// Column sums of `nb` partial rows for k < nr into `tot` (LDS), visible to the
-// whole block on return.  Every block computes bit-identical totals.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, int nr, double* tot) {
+// Column sums of the first nb rows for columns k < nr into `tot` (LDS),
+// visible to the whole block on return.  Each lane issues up to 16 loads
+// before adding, so the prologue costs about one memory round trip.
+__device__ __forceinline__ void reduce_partials(const Partials& p, int nr, double* tot) {
+  constexpr int CH = 16;
   const int nthreads = blockDim.x * blockDim.y;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   int G = kWave;
@@ -122,18 +150,23 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
   const int col = tid / G;
   const int g = tid % G;
   double s = 0.0;
-  if (col < nr)
-    for (int b = g; b < nb; b += G) s += part[(size_t)b * kPartStride + col];
+  if (col < nr) {
+    const double* __restrict__ q = p.part + (size_t)col * p.ld;
+    for (int b0 = g; b0 < p.nb; b0 += G * CH) {
+      double v[CH];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        const int b = b0 + r * G;
+        v[r] = b < p.nb ? q[b] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < CH; ++r) s += v[r];
+    }
+  }
   for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
   if (col < nr && g == 0) tot[col] = s;
   __syncthreads();
 }
-
-// A set of partial rows produced by an earlier kernel.
-struct Partials {
-  const double* part;
-  int nb;  // rows (blocks of the producer); 0 = none
-};
 
 // ---------------------------------------------------------------------------
 // GMRES / Newton control block (device resident)

@@ -38,16 +38,39 @@ struct GivensOut {
   int done;
 };
 
-__device__ inline GivensOut givens_column(const Ctl* __restrict__ ctl, int j, double wn2, double* col) {
+// Inputs of one column update, gathered into LDS by all threads at once.
+struct GivensIn {
+  double h[kMaxM + 1];  // hA + hB
+  double cs[kMaxM];
+  double sn[kMaxM];
+  double gp, tol_abs, brk_tol, jvn2;
+};
+
+__device__ inline void givens_gather(const Ctl* __restrict__ ctl, int j, GivensIn& in) {
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if (tid <= j) in.h[tid] = ctl->hA[tid] + ctl->hB[tid];
+  if (tid < j) {
+    in.cs[tid] = ctl->cs[tid];
+    in.sn[tid] = ctl->sn[tid];
+  }
+  if (tid == 0) {
+    in.gp = ctl->gp[j];
+    in.tol_abs = ctl->tol_abs;
+    in.brk_tol = ctl->brk_tol;
+    in.jvn2 = ctl->jvn2;
+  }
+}
+
+__device__ inline GivensOut givens_column(const GivensIn& in, int j, double wn2, double* col) {
   GivensOut o;
   o.wn = sqrt(wn2);
-  for (int i = 0; i <= j; ++i) col[i] = ctl->hA[i] + ctl->hB[i];
+  for (int i = 0; i <= j; ++i) col[i] = in.h[i];
   col[j + 1] = o.wn;
   bool finite = isfinite(o.wn);
   for (int i = 0; i <= j; ++i) finite = finite && isfinite(col[i]);
   for (int i = 0; i < j; ++i) {
-    const double t = ctl->cs[i] * col[i] + ctl->sn[i] * col[i + 1];
-    col[i + 1] = -ctl->sn[i] * col[i] + ctl->cs[i] * col[i + 1];
+    const double t = in.cs[i] * col[i] + in.sn[i] * col[i + 1];
+    col[i + 1] = -in.sn[i] * col[i] + in.cs[i] * col[i + 1];
     col[i] = t;
   }
   o.c = 1.0;
@@ -59,17 +82,16 @@ __device__ inline GivensOut givens_column(const Ctl* __restrict__ ctl, int j, do
   }
   col[j] = o.c * col[j] + o.s * col[j + 1];
   col[j + 1] = 0.0;
-  const double g = ctl->gp[j];
-  o.gr = o.c * g;
-  o.gp1 = -o.s * g;
+  o.gr = o.c * in.gp;
+  o.gp1 = -o.s * in.gp;
   o.est = fabs(o.gp1);
   finite = finite && isfinite(o.est);
   o.done = kRunning;
   if (!finite)
     o.done = kNonfinite;
-  else if (o.est <= ctl->tol_abs)
+  else if (o.est <= in.tol_abs)
     o.done = kConverged;
-  else if (o.wn <= ctl->brk_tol * sqrt(ctl->jvn2))
+  else if (o.wn <= in.brk_tol * sqrt(in.jvn2))
     o.done = kBreakdown;
   return o;
 }
@@ -92,13 +114,16 @@ __device__ inline void givens_commit(Ctl* __restrict__ ctl, int j, const GivensO
 // or the V y update): reduce ||w||^2 and update column j.  Every thread of
 // every block gets the same outcome; `col` (LDS, kMaxM + 1 doubles) receives
 // the rotated column.
-__device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, Partials pc, int* host_flags, double* col) {
+__device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Partials& pc, int* host_flags,
+                                          double* col) {
   __shared__ double tot[1];
+  __shared__ GivensIn in;
   __shared__ GivensOut out;
-  reduce_partials(pc.part, pc.nb, 1, tot);
+  givens_gather(ctl, j, in);
+  reduce_partials(pc, 1, tot);  // ends with a barrier: `in` is complete too
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   if (tid == 0) {
-    out = givens_column(ctl, j, tot[0], col);
+    out = givens_column(in, j, tot[0], col);
     if (blockIdx.x == 0 && blockIdx.y == 0) givens_commit(ctl, j, out, col, host_flags);
   }
   __syncthreads();
@@ -118,21 +143,42 @@ struct KArgs {
   int K;              // basis vectors in use (j + 1)
   Ctl* ctl;
   Partials in;        // partials of the previous pass (B: pass A's, C: pass B's)
-  double* out;        // this pass's partial rows
+  PartSink out;       // this pass's partial sums
 };
+
+template <class T, class VT, int KMAX, int VEC>
+__device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int K, T (&w)[VEC], T (&vv)[KMAX][VEC]) {
+  load_vec<T, VEC>(a.w + i, w);
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      VT t[VEC];
+      load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) vv[k][e] = to_c<T>(t[e]);
+    }
+  }
+}
 
 template <class T, class VT, int KMAX, int VEC, int MODE>
 __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
   if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  // the first chunk's loads go out before the coefficient reduction
+  T w[VEC];
+  T vv[KMAX][VEC];
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
+
   __shared__ double tot[KMAX + 1];
   T coef[KMAX];
   if constexpr (MODE != PASS_A) {
     // projections of the previous pass on the stored vectors (+ ||J v_j||^2 from pass A)
-    reduce_partials(a.in.part, a.in.nb, MODE == PASS_B ? K + 1 : K, tot);
+    reduce_partials(a.in, MODE == PASS_B ? K + 1 : K, tot);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) coef[k] = k < K ? T(tot[k] * ctl->scale[k] * ctl->scale[k]) : T(0);
+    for (int k = 0; k < KMAX; ++k) coef[k] = uniform(k < K ? T(tot[k] * ctl->scale[k] * ctl->scale[k]) : T(0));
     if (blockIdx.x == 0 && threadIdx.x < K) {
       const double h = tot[threadIdx.x] * ctl->scale[threadIdx.x];
       if (MODE == PASS_B)
@@ -146,20 +192,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
 #pragma unroll
   for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
 
-  const long long step = (long long)gridDim.x * blockDim.x * VEC;
-  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < a.n; i += step) {
-    T w[VEC];
-    load_vec<T, VEC>(a.w + i, w);
-    T vv[KMAX][VEC];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      if (k < K) {
-        VT t[VEC];
-        load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) vv[k][e] = to_c<T>(t[e]);
-      }
-    }
+  for (; i < a.n; i += step) {
     if constexpr (MODE == PASS_A) {
 #pragma unroll
       for (int k = 0; k < KMAX; ++k)
@@ -194,6 +227,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
         store_vec<VT, VEC>(a.wout + i, o);
       }
     }
+    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC>(a, i + step, K, w, vv);
   }
 
   int nr = MODE == PASS_C ? 1 : K;
@@ -205,7 +239,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
     nr = K + 1;
   }
   __shared__ double lds[(KMAX + 1) * 8];
-  block_partials<KMAX + 1>(acc, nr, a.out, lds);
+  block_partials<KMAX + 1>(acc, nr, a.out.part, a.out.ld, lds);
 }
 
 // Start of a restart cycle: V_0 = sign * R - w (w nullable) and its partial
@@ -217,7 +251,7 @@ struct InitArgs {
   double sign;
   const T* w;   // nullable
   VT* V0;
-  double* out;  // partial rows
+  PartSink out;
 };
 
 template <class T, class VT, int VEC>
@@ -246,14 +280,14 @@ __global__ void __launch_bounds__(256) init_cycle_kernel(const InitArgs<T, VT> a
     store_vec<VT, VEC>(a.V0 + i, o);
   }
   __shared__ double lds[4];
-  block_partials<1>(acc, 1, a.out, lds);
+  block_partials<1>(acc, 1, a.out.part, a.out.ld, lds);
 }
 
 // One block: beta = ||V_0||; the first cycle of a solve also fixes ||rhs||.
 template <int kUnused = 0>
 __global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in, int m) {
   __shared__ double tot[1];
-  reduce_partials(in.part, in.nb, 1, tot);
+  reduce_partials(in, 1, tot);
   if (threadIdx.x == 0) {
     const double beta = sqrt(tot[0]);
     if (ctl->first) {
@@ -284,7 +318,7 @@ struct VyArgs {
   int jmax;     // last Arnoldi step enqueued in this cycle (-1: none)
   Ctl* ctl;
   Partials pc;  // partial norms of the last pass C
-  double* out;  // partial rows of ||dx||^2
+  PartSink out;  // partial sums of ||dx||^2
   int* host_flags;
 };
 
@@ -329,7 +363,7 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   __syncthreads();
   T coef[KMAX];
 #pragma unroll
-  for (int c = 0; c < KMAX; ++c) coef[c] = c < k ? T(y[c] * ctl->scale[c]) : T(0);
+  for (int c = 0; c < KMAX; ++c) coef[c] = uniform(c < k ? T(y[c] * ctl->scale[c]) : T(0));
   double acc[1] = {0.0};
   const long long step = (long long)gridDim.x * blockDim.x * VEC;
   for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < a.n; i += step) {
@@ -354,14 +388,14 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
     store_vec<T, VEC>(a.dx + i, d);
   }
   __shared__ double lds[8];
-  block_partials<1>(acc, 1, a.out, lds);
+  block_partials<1>(acc, 1, a.out.part, a.out.ld, lds);
 }
 
 // One block: write column sums of earlier partial rows to device scalars.
 template <int kUnused = 0>
 __global__ void __launch_bounds__(256) finish_sums_kernel(Partials in, int nr, double* out0, double* out1) {
   __shared__ double tot[2];
-  reduce_partials(in.part, in.nb, nr, tot);
+  reduce_partials(in, nr, tot);
   if (threadIdx.x == 0) {
     *out0 = tot[0];
     if (nr > 1 && out1) *out1 = tot[1];
@@ -407,7 +441,7 @@ __global__ void __launch_bounds__(256) cast_kernel(long long n, const double* __
 
 // Partial sums of p^2 over an arbitrary (possibly unaligned) vector.
 template <class T>
-__global__ void __launch_bounds__(256) norm2_kernel(long long n, const T* __restrict__ p, double* out) {
+__global__ void __launch_bounds__(256) norm2_kernel(long long n, const T* __restrict__ p, PartSink out) {
   double acc[1] = {0.0};
   const long long step = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
@@ -415,7 +449,7 @@ __global__ void __launch_bounds__(256) norm2_kernel(long long n, const T* __rest
     acc[0] += v * v;
   }
   __shared__ double lds[4];
-  block_partials<1>(acc, 1, out, lds);
+  block_partials<1>(acc, 1, out.part, out.ld, lds);
 }
 
 // Zero fill (used instead of memset so every step is a plain kernel).

@@ -20,10 +20,16 @@ template <class T>
 constexpr int stencil_vec(int pid) {
   return pid == kKerr ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
 }
-// Elements per thread of the streaming Krylov kernels.
+// Elements per thread of the streaming Krylov kernels (16-byte accesses; the
+// FP64 passes over 17..32 basis vectors use 8-byte accesses so that the
+// register-resident basis chunk fits without spilling).
 template <class T>
 constexpr int krylov_vec() {
   return (int)(16 / sizeof(T));
+}
+template <class T, int KMAX>
+constexpr int cgs_vec() {
+  return (sizeof(T) == 8 && KMAX > 16) ? 1 : (int)(16 / sizeof(T));
 }
 
 constexpr int kStencilRY = 4;       // rows per thread (2D problems)
@@ -31,22 +37,36 @@ constexpr int kStencilThreads = 256;
 constexpr int kKrylovThreads = 512;
 constexpr int kStreamThreads = 256;
 
-// Launch shape of the stencil kernel for an nx-by-ny grid.
-inline void stencil_shape(int pid, int nx, int ny, int vec, dim3& grid, dim3& block) {
+// Block shape and tile count of the stencil kernel for an nx-by-ny grid:
+// blocks of 256 threads, blockDim.x a multiple of 64 covering up to 256 * vec
+// columns; a tile is blockDim.x * vec columns by blockDim.y * kStencilRY rows.
+inline void stencil_shape(int pid, int nx, int ny, int vec, dim3& block, int& ntiles) {
   const bool dim2 = pid != kBurgers1D;
   const int tcols = (nx + vec - 1) / vec;
   int tx = ((tcols + kWave - 1) / kWave) * kWave;
   if (tx > kStencilThreads) tx = kStencilThreads;
   const int ty = dim2 ? kStencilThreads / tx : 1;
   block = dim3(tx, ty, 1);
-  grid = dim3((tcols + tx - 1) / tx, dim2 ? (ny + ty * kStencilRY - 1) / (ty * kStencilRY) : 1, 1);
+  const int tiles_x = (tcols + tx - 1) / tx;
+  const int tiles_y = dim2 ? (ny + ty * kStencilRY - 1) / (ty * kStencilRY) : 1;
+  ntiles = tiles_x * tiles_y;
 }
 
-// Launches the stencil kernel; *nblocks (nullable) receives its block count
-// (the number of partial rows it writes when reducing).
+// Blocks of a persistent stencil launch with at most `cap` blocks.
+inline int stencil_blocks(int pid, int nx, int ny, int vec, int cap) {
+  dim3 b;
+  int nt = 0;
+  stencil_shape(pid, nx, ny, vec, b, nt);
+  return nt < cap ? nt : cap;
+}
+
+// Launches the stencil kernel on at most `cap` blocks; *nblocks (nullable)
+// receives the block count (the number of partial rows it writes).  In
+// Arnoldi mode with a.Vb set, the first CGS projection on a.K basis vectors
+// is fused in.
 template <class T, class VT>
 hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
-                          const Coefs& c, hipStream_t s, int* nblocks = nullptr);
+                          const Coefs& c, int cap, hipStream_t s, int* nblocks = nullptr);
 
 template <class T, class VT>
 hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s);
@@ -65,7 +85,7 @@ template <class T>
 hipError_t launch_cast(long long n, const double* src, T* dst, int grid, hipStream_t s);
 
 template <class T>
-hipError_t launch_norm2(long long n, const T* p, double* part, int grid, hipStream_t s);
+hipError_t launch_norm2(long long n, const T* p, PartSink part, int grid, hipStream_t s);
 
 template <class T>
 hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s);

@@ -6,51 +6,71 @@
 
 namespace jfnk {
 
+template <class P, class T, class VT, int VEC, int OP, bool WITHF>
+static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid, dim3 block, hipStream_t s) {
+  constexpr int RY = kStencilRY;
+  if (a.Vb == nullptr)
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, WITHF, 0>), grid, block, 0, s, a, c);
+  else if (a.K <= 4)
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, 0, s, a, c);
+  else if (a.K <= 8)
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, 0, s, a, c);
+  else if (a.K <= 16)
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, 0, s, a, c);
+  else
+    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, 0, s, a, c);
+  return hipGetLastError();
+}
+
 template <class P, class T, class VT, int VEC>
 static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid,
                                 dim3 block, hipStream_t s) {
   constexpr int RY = kStencilRY;
   if (op == OP_RES) {
     if constexpr (std::is_same<T, VT>::value) {
-      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false>), grid, block, 0, s, a, c);
+      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false, 0>), grid, block, 0, s, a, c);
+      return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
-  } else if (op == OP_AD) {
-    if (withf) {
-      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true>), grid, block, 0, s, a, c);
-    } else {
-      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, false>), grid, block, 0, s, a, c);
-    }
-  } else {
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_FD, false>), grid, block, 0, s, a, c);
   }
-  return hipGetLastError();
+  if (op == OP_AD) {
+    if (withf) {
+      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true, 0>), grid, block, 0, s, a, c);
+      return hipGetLastError();
+    }
+    return stencil_kdot<P, T, VT, VEC, OP_AD, false>(a, c, grid, block, s);
+  }
+  return stencil_kdot<P, T, VT, VEC, OP_FD, false>(a, c, grid, block, s);
 }
 
 template <class P, class T, class VT>
 static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
-                                      const Coefs& c, hipStream_t s, int* nblocks) {
+                                      const Coefs& c, int cap, hipStream_t s, int* nblocks) {
   constexpr int V = P::kInterleaved ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
-  dim3 grid, block;
-  stencil_shape(pid, a.nx, a.ny, vectorized ? V : 1, grid, block);
-  if (nblocks) *nblocks = (int)(grid.x * grid.y);
+  const int vec = vectorized ? V : 1;
+  dim3 block;
+  int ntiles = 0;
+  stencil_shape(pid, a.nx, a.ny, vec, block, ntiles);
+  const int nb = ntiles < cap ? ntiles : cap;
+  if (nblocks) *nblocks = nb;
+  const dim3 grid(nb, 1, 1);
   if (vectorized) return stencil_by_op<P, T, VT, V>(op, withf, a, c, grid, block, s);
   return stencil_by_op<P, T, VT, 1>(op, withf, a, c, grid, block, s);
 }
 
 template <class T, class VT>
 hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
-                          const Coefs& c, hipStream_t s, int* nblocks) {
+                          const Coefs& c, int cap, hipStream_t s, int* nblocks) {
   switch (pid) {
     case kBurgers1D:
-      return stencil_for_problem<Burgers1DOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+      return stencil_for_problem<Burgers1DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kBurgers2D:
-      return stencil_for_problem<Burgers2DOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+      return stencil_for_problem<Burgers2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kGrayScott:
-      return stencil_for_problem<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+      return stencil_for_problem<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kKerr:
-      return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, s, nblocks);
+      return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;
   }
@@ -58,7 +78,7 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
 
 template <class T, class VT, int KMAX>
 static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
-  constexpr int VEC = krylov_vec<T>();
+  constexpr int VEC = cgs_vec<T, KMAX>();
   const dim3 g(grid), b(kKrylovThreads);
   if (mode == PASS_A)
     hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_A>), g, b, 0, s, a);
@@ -112,7 +132,7 @@ hipError_t launch_cast(long long n, const double* src, T* dst, int grid, hipStre
 }
 
 template <class T>
-hipError_t launch_norm2(long long n, const T* p, double* part, int grid, hipStream_t s) {
+hipError_t launch_norm2(long long n, const T* p, PartSink part, int grid, hipStream_t s) {
   hipLaunchKernelGGL((norm2_kernel<T>), dim3(grid), dim3(kStreamThreads), 0, s, n, p, part);
   return hipGetLastError();
 }
@@ -124,7 +144,7 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
 }
 
 #define JFNK_INSTANTIATE(T, VT)                                                                                  \
-  template hipError_t launch_stencil<T, VT>(int, int, bool, bool, const StencilArgs<T, VT>&, const Coefs&,      \
+  template hipError_t launch_stencil<T, VT>(int, int, bool, bool, const StencilArgs<T, VT>&, const Coefs&, int, \
                                             hipStream_t, int*);                                                 \
   template hipError_t launch_cgs<T, VT>(int, const KArgs<T, VT>&, int, hipStream_t);                            \
   template hipError_t launch_init<T, VT>(const InitArgs<T, VT>&, int, hipStream_t);                             \
@@ -133,7 +153,7 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
 #define JFNK_INSTANTIATE_SCALAR(T)                                                                               \
   template hipError_t launch_trial<T>(long long, const double*, const T*, double, double*, T*, int, hipStream_t);\
   template hipError_t launch_cast<T>(long long, const double*, T*, int, hipStream_t);                           \
-  template hipError_t launch_norm2<T>(long long, const T*, double*, int, hipStream_t);                          \
+  template hipError_t launch_norm2<T>(long long, const T*, PartSink, int, hipStream_t);                         \
   template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);
 
 }  // namespace jfnk

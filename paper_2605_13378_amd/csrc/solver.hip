@@ -177,6 +177,9 @@ int stream_grid(const jfnk_solver* s, int vec) {
   return (int)std::max<long long>(1, std::min<long long>(need, 4LL * s->cu));
 }
 
+// Block cap of plain stencil launches (residual, standalone JVP).
+int stencil_cap(const jfnk_solver* s) { return 4 * s->cu; }
+
 bool aligned(const void* p, size_t a) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 EpsSpec eps_spec(const jfnk_solver* s, double fixed, int rule, const double* vnorm2) {
@@ -196,7 +199,9 @@ template <class T, class VT>
 struct Impl {
   static constexpr int KVEC = krylov_vec<T>();
 
-  static double* part(jfnk_solver* s, int region) { return s->parts + (size_t)region * s->part_rows * kPartStride; }
+  static double* part(jfnk_solver* s, int region) { return s->parts + (size_t)region * s->part_rows * kMaxCols; }
+  static PartSink sink(jfnk_solver* s, int region) { return PartSink{part(s, region), (int)s->part_rows}; }
+  static Partials parts(jfnk_solver* s, int region, int nb) { return Partials{part(s, region), nb, (int)s->part_rows}; }
 
   // Residual F = alpha x + cN N(x) + beta b; optional norms into ctl.
   static jfnk_status residual(jfnk_solver* s, const T* x, T* F, bool norms) {
@@ -210,25 +215,27 @@ struct Impl {
     a.alpha = s->alpha;
     a.cN = s->cN;
     a.beta = s->beta;
-    a.part_out = part(s, 5);
+    a.part_out = sink(s, 5);
     a.nred = norms ? 2 : 0;
     const int vec = stencil_vec<T>(s->pid);
     const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(F, 16) && aligned(s->b, 16);
     int nb = 0;
     {
       ProfScope ps(s, PK_RES, 3.0 * s->n * sizeof(T));
-      JFNK_HIP(s, launch_stencil<T, T>(s->pid, OP_RES, false, vz, a, s->coefs, s->stream, &nb));
+      JFNK_HIP(s, launch_stencil<T, T>(s->pid, OP_RES, false, vz, a, s->coefs, stencil_cap(s), s->stream, &nb));
     }
-    if (norms) JFNK_HIP(s, launch_finish_sums(Partials{part(s, 5), nb}, 2, &s->ctl->fnorm2, &s->ctl->xnorm2, s->stream));
+    if (norms) JFNK_HIP(s, launch_finish_sums(parts(s, 5, nb), 2, &s->ctl->fnorm2, &s->ctl->xnorm2, s->stream));
     return JFNK_OK;
   }
 
   // Jv = J(x) v (AD or FD), optional F(x) for AD; v is of type W (T or VT).
   // Arnoldi mode (arn_j >= 0): v is basis vector arn_j, its scale and the
-  // pending Givens column come from the device control block.
+  // pending Givens column come from the device control block, and the first
+  // CGS projection on V_0..V_arn_j is fused in (partial sums into region 0;
+  // *nb_out receives their row count).
   template <class W>
   static jfnk_status jvp(jfnk_solver* s, const T* x, const W* v, const double* vscale, T* Jv, T* Fout, int mode,
-                         const EpsSpec& eps, int arn_j = -1) {
+                         const EpsSpec& eps, int arn_j = -1, int* nb_out = nullptr) {
     StencilArgs<T, W> a{};
     a.nx = s->prob.nx;
     a.ny = s->prob.ny;
@@ -247,17 +254,23 @@ struct Impl {
     if (arn_j >= 0) {
       a.ctl = s->ctl;
       a.arn_j = arn_j;
-      a.pc = Partials{part(s, 2), krylov_grid(s, KVEC)};
+      a.pc = parts(s, 2, krylov_grid(s, KVEC));
       a.host_flags = s->dflags;
+      a.Vb = reinterpret_cast<const W*>(basis(s, 0));
+      a.vstride = s->npad;
+      a.K = arn_j + 1;
+      a.dots_out = sink(s, 0);
     }
     const int vec = stencil_vec<T>(s->pid);
     const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(v, vec * sizeof(W)) && aligned(Jv, 16) &&
                     aligned(Fout, 16) && aligned(a.b, 16);
     const int op = mode == JFNK_JVP_AD ? OP_AD : OP_FD;
-    const double nvec = mode == JFNK_JVP_AD ? 2.0 + (Fout ? 2.0 : 0.0) : 3.0;
-    ProfScope ps(s, mode == JFNK_JVP_AD ? PK_AD : PK_FD,
-                 nvec * s->n * sizeof(T) + (double)s->n * sizeof(W));
-    JFNK_HIP(s, launch_stencil<T, W>(s->pid, op, Fout != nullptr, vz, a, s->coefs, s->stream));
+    // algorithmic bytes: x, v (b for F / FD), Jv (F); fused: x, V_0..V_j, Jv
+    double bytes = (mode == JFNK_JVP_AD ? 2.0 + (Fout ? 2.0 : 0.0) : 3.0) * s->n * sizeof(T) + (double)s->n * sizeof(W);
+    if (arn_j >= 0) bytes += (double)arn_j * s->n * sizeof(W);
+    ProfScope ps(s, mode == JFNK_JVP_AD ? PK_AD : PK_FD, bytes);
+    const int cap = arn_j >= 0 ? 2 * s->cu : stencil_cap(s);
+    JFNK_HIP(s, launch_stencil<T, W>(s->pid, op, Fout != nullptr, vz, a, s->coefs, cap, s->stream, nb_out));
     return JFNK_OK;
   }
 
@@ -279,7 +292,7 @@ struct Impl {
     const int sgrid = stream_grid(s, KVEC);
     const EpsSpec eps_arnoldi = eps_spec(s, fixed_eps, eps_rule, nullptr);  // ||v_j|| = 1
     EpsSpec eps_restart = eps_spec(s, fixed_eps, eps_rule, nullptr);        // v = dx
-    if (eps_rule == JFNK_EPS_NORMALIZED) eps_restart.vparts = Partials{part(s, 4), kgrid};
+    if (eps_rule == JFNK_EPS_NORMALIZED) eps_restart.vparts = parts(s, 4, kgrid);
     volatile int* flags = reinterpret_cast<volatile int*>(s->hflags);
     JFNK_HIP(s, launch_ctl_begin(s->ctl, tol, brk, m, s->stream));
     bool updated = false;
@@ -291,11 +304,11 @@ struct Impl {
         wr = w;
       }
       {
-        InitArgs<T, VT> ia{s->npad, R, sign, wr, basis(s, 0), part(s, 3)};
+        InitArgs<T, VT> ia{s->npad, R, sign, wr, basis(s, 0), sink(s, 3)};
         ProfScope ps(s, PK_INIT, (double)s->n * ((wr ? 2.0 : 1.0) * sizeof(T) + sizeof(VT)));
         JFNK_HIP(s, launch_init<T, VT>(ia, sgrid, s->stream));
       }
-      JFNK_HIP(s, launch_cycle_begin(s->ctl, Partials{part(s, 3), sgrid}, m, s->stream));
+      JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->stream));
       JFNK_TRY(sync_read_ctl(s));
       if (s->prof) prof_harvest(s, 0);
       if (cycle == 0) go.bnorm = s->hctl->bnorm;
@@ -320,20 +333,15 @@ struct Impl {
         s->cur_step = j;
         const int K = j + 1;
         if (j >= 1) flags[j - 1] = -1;
-        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j));
-        KArgs<T, VT> ka{s->npad, basis(s, 0), s->npad, w, basis(s, K), K, s->ctl, Partials{nullptr, 0}, part(s, 0)};
-        {
-          ProfScope ps(s, PK_A, (double)s->n * (K * sizeof(VT) + sizeof(T)));
-          JFNK_HIP(s, launch_cgs<T, VT>(PASS_A, ka, kgrid, s->stream));
-        }
-        ka.in = Partials{part(s, 0), kgrid};
-        ka.out = part(s, 1);
+        int nb_jvp = 0;  // the JVP carries the first projection (pass A)
+        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp));
+        KArgs<T, VT> ka{s->npad, basis(s, 0), s->npad, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1)};
         {
           ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
           JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, kgrid, s->stream));
         }
-        ka.in = Partials{part(s, 1), kgrid};
-        ka.out = part(s, 2);
+        ka.in = parts(s, 1, kgrid);
+        ka.out = sink(s, 2);
         {
           ProfScope ps(s, PK_C, (double)s->n * (K * sizeof(VT) + sizeof(T) + sizeof(VT)));
           JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, kgrid, s->stream));
@@ -349,7 +357,7 @@ struct Impl {
       flags[jmax] = -1;
       {
         VyArgs<T, VT> va{s->npad, basis(s, 0), s->npad, dxi, updated ? 0 : 1, jmax, s->ctl,
-                         Partials{part(s, 2), kgrid}, part(s, 4), s->dflags};
+                         parts(s, 2, kgrid), sink(s, 4), s->dflags};
         ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
         JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
       }
@@ -537,12 +545,10 @@ long long problem_n(const jfnk_problem* p) {
   return p->id == JFNK_BURGERS1D ? cells : 2 * cells;
 }
 
-size_t max_blocks(const jfnk_problem* p, int cu) {
-  dim3 g, b;
-  stencil_shape(p->id, p->nx, p->ny, 1, g, b);
-  const size_t st = (size_t)g.x * g.y;
-  return std::max<size_t>({st, (size_t)4 * cu, (size_t)cu}) + 1;
-}
+// Upper bound on the blocks of any reducing launch: persistent stencil
+// launches take at most 4 * cu blocks, Krylov launches at most cu, streaming
+// ones at most 4 * cu.
+size_t max_blocks(const jfnk_problem*, int cu) { return (size_t)4 * cu + 1; }
 
 size_t elem_size(int prec) { return prec == JFNK_F64 ? 8 : 4; }
 size_t basis_elem_size(int prec) { return prec == JFNK_F64 ? 8 : (prec == JFNK_F32 ? 4 : 2); }
@@ -554,7 +560,7 @@ size_t footprint(const jfnk_problem* p, int prec, int m, int cu) {
   bytes += (size_t)(m + 1) * npad * basis_elem_size(prec);  // basis
   bytes += 8 * (size_t)npad * t;                            // w R dx F Ft xw xwt b
   bytes += 3 * (size_t)npad * 8;                            // x64 x64t tmp64
-  bytes += 6 * max_blocks(p, cu) * kPartStride * 8;         // partial-sum rows
+  bytes += 6 * max_blocks(p, cu) * kMaxCols * 8;            // partial sums
   bytes += sizeof(Ctl);
   return bytes;
 }
@@ -599,10 +605,10 @@ namespace {
 // ||p||^2 of a caller vector into a device scalar (stream-ordered).
 template <class T>
 jfnk_status device_norm2(jfnk_solver* s, const T* p, double* out) {
-  double* part = s->parts + 5 * s->part_rows * kPartStride;
+  double* part = s->parts + 5 * s->part_rows * kMaxCols;
   const int g = stream_grid(s, 1);
-  JFNK_HIP(s, launch_norm2<T>(s->n, p, part, g, s->stream));
-  JFNK_HIP(s, launch_finish_sums(Partials{part, g}, 1, out, nullptr, s->stream));
+  JFNK_HIP(s, launch_norm2<T>(s->n, p, PartSink{part, (int)s->part_rows}, g, s->stream));
+  JFNK_HIP(s, launch_finish_sums(Partials{part, g, (int)s->part_rows}, 1, out, nullptr, s->stream));
   return JFNK_OK;
 }
 
@@ -735,7 +741,7 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   if (st == JFNK_OK) st = malloc_dev(s, &s->x64t, (size_t)s->npad * 8);
   if (st == JFNK_OK) st = malloc_dev(s, &s->tmp64, (size_t)s->npad * 8);
   s->part_rows = max_blocks(problem, s->cu);
-  if (st == JFNK_OK) st = malloc_dev(s, &s->parts, 6 * s->part_rows * kPartStride * sizeof(double));
+  if (st == JFNK_OK) st = malloc_dev(s, &s->parts, 6 * s->part_rows * kMaxCols * sizeof(double));
   if (st == JFNK_OK) st = malloc_dev(s, &s->ctl, sizeof(Ctl));
   if (st == JFNK_OK) {
     void* h = nullptr;
@@ -832,7 +838,7 @@ jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double
   a.out = dst;
   const int vec = stencil_vec<double>(s->pid);
   const bool vz = (p.nx % vec == 0) && aligned(x_prev, 16) && aligned(source, 16);
-  JFNK_HIP(s, launch_stencil<double, double>(s->pid, OP_RES, false, vz, a, s->coefs, s->stream));
+  JFNK_HIP(s, launch_stencil<double, double>(s->pid, OP_RES, false, vz, a, s->coefs, stencil_cap(s), s->stream));
   if (s->prec != JFNK_F64)
     JFNK_HIP(s, launch_cast<float>(s->npad, s->tmp64, static_cast<float*>(s->b), sgrid, s->stream));
   s->has_prev = true;

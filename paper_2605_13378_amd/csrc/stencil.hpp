@@ -49,8 +49,14 @@ struct StencilArgs {
   int arn_j;
   Partials pc;
   int* host_flags;
-  double* part_out;      // RES: partial rows of sum(out^2) and sum(x^2)
+  PartSink part_out;     // RES: partial sums of sum(out^2) and sum(x^2)
   int nred;              // 0, 1 or 2 reductions
+  // Arnoldi JVP with the first CGS projection fused in (KDOT > 0):
+  // partial sums of V_k . Jv for k < K and of ||Jv||^2 go to dots_out.
+  const VT* Vb;          // basis, vector k at Vb + k * vstride
+  long long vstride;
+  int K;
+  PartSink dots_out;
 };
 
 template <bool PERIODIC>
@@ -112,9 +118,11 @@ struct Tile {
   T lh[P::NF][RC];
   T rh[P::NF][RC];
 
+  // Issue the loads: rows r0-1 .. r0+RY, and the left/right halo words of
+  // lanes at a wavefront or grid edge (the rest come from exchange()).
   template <class S>
   __device__ __forceinline__ void load(const S* __restrict__ base, long long plane, int nx, int ny, int r0,
-                                       int col0, int cc, int lane, T scale) {
+                                       int col0, int cc, int lane) {
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
       const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + t, ny) : 0;
@@ -123,7 +131,7 @@ struct Tile {
 #pragma unroll
       for (int f = 0; f < P::NF; ++f)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) a[f][t][e] = to_c<T>(tmp[f][e]) * scale;
+        for (int e = 0; e < VEC; ++e) a[f][t][e] = to_c<T>(tmp[f][e]);
     }
     const int cl = wrap_idx<P::kPeriodic>(col0 - 1, nx);
     const int cr = wrap_idx<P::kPeriodic>(col0 + VEC, nx);
@@ -131,16 +139,43 @@ struct Tile {
     const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
 #pragma unroll
     for (int tt = 0; tt < RC; ++tt) {
-      const int t = P::kDim2 ? tt + 1 : 0;
       const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 + tt, ny) : 0;
 #pragma unroll
       for (int f = 0; f < P::NF; ++f) {
-        T lv = __shfl_up(a[f][t][VEC - 1], 1, kWave);
-        T rv = __shfl_down(a[f][t][0], 1, kWave);
-        if (need_l) lv = to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) * scale;
-        if (need_r) rv = to_c<T>(load_node<P, S>(base, plane, nx, r, cr, f)) * scale;
-        lh[f][tt] = lv;
-        rh[f][tt] = rv;
+        lh[f][tt] = need_l ? to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) : T(0);
+        rh[f][tt] = need_r ? to_c<T>(load_node<P, S>(base, plane, nx, r, cr, f)) : T(0);
+      }
+    }
+  }
+
+  // Left/right neighbours of the other lanes from the adjacent lane.
+  __device__ __forceinline__ void exchange(int col0, int nx, int lane) {
+    const bool need_l = (lane == 0) || (col0 == 0);
+    const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
+#pragma unroll
+    for (int tt = 0; tt < RC; ++tt) {
+      const int t = P::kDim2 ? tt + 1 : 0;
+#pragma unroll
+      for (int f = 0; f < P::NF; ++f) {
+        const T lv = __shfl_up(a[f][t][VEC - 1], 1, kWave);
+        const T rv = __shfl_down(a[f][t][0], 1, kWave);
+        if (!need_l) lh[f][tt] = lv;
+        if (!need_r) rh[f][tt] = rv;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void scale_by(T s) {
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) {
+#pragma unroll
+      for (int t = 0; t < NR; ++t)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) a[f][t][e] *= s;
+#pragma unroll
+      for (int tt = 0; tt < RC; ++tt) {
+        lh[f][tt] *= s;
+        rh[f][tt] *= s;
       }
     }
   }
@@ -158,34 +193,27 @@ struct Tile {
   }
 };
 
-template <class P, class T, class VT, int VEC, int RY, int OP, bool WITHF>
+// Persistent launch: the grid holds at most a bounded number of blocks and
+// each block walks a contiguous range of tiles (vertically adjacent row
+// bands, so the halo rows of one tile are still in cache for the next).  A
+// tile is blockDim.x * VEC columns by blockDim.y * RY rows.
+template <class P, class T, class VT, int VEC, int RY, int OP, bool WITHF, int KDOT>
 __global__ void __launch_bounds__(256)
 stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
-  double vscale = 1.0;
+  // Arnoldi mode: leave at once if the cycle has already stopped
   if constexpr (OP != OP_RES) {
     if (a.ctl != nullptr) {
       const int j = a.arn_j;
-      if (j == 0) {
-        if (a.ctl->done_col[0] != kRunning) return;
-        vscale = a.ctl->scale[0];
-      } else {
-        const int prev = a.ctl->done_col[j - 1];
-        if (prev != kRunning) {
-          // the cycle stopped earlier: carry the state forward so that the
-          // flags stay monotone (later kernels only look at their own column)
-          if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-            a.ctl->done_col[j] = prev;
-            if (a.host_flags) a.host_flags[j - 1] = prev;
-          }
-          return;
+      const int prev = a.ctl->done_col[j > 0 ? j - 1 : 0];
+      if (prev != kRunning) {
+        // carry the state forward so that the flags stay monotone (later
+        // kernels only look at the state after their own column)
+        if (j > 0 && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+          a.ctl->done_col[j] = prev;
+          if (a.host_flags) a.host_flags[j - 1] = prev;
         }
-        __shared__ double col[kMaxM + 1];
-        const GivensOut g = finish_column(a.ctl, j - 1, a.pc, a.host_flags, col);
-        if (g.done != kRunning) return;
-        vscale = 1.0 / g.wn;
+        return;
       }
-    } else if (a.vscale != nullptr) {
-      vscale = *a.vscale;
     }
   }
   constexpr int NF = P::NF;
@@ -193,115 +221,184 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   const auto k = P::template make<T>(coefs);
   const int nx = a.nx, ny = a.ny;
   const int lane = threadIdx.x & (kWave - 1);
-  const int col0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  const int r0 = P::kDim2 ? (blockIdx.y * blockDim.y + threadIdx.y) * RY : 0;
-  const bool colok = col0 < nx;
-  const int cc = colok ? col0 : 0;
   const T alpha = T(a.alpha), cN = T(a.cN), beta = T(a.beta);
 
-  Tile<P, T, VEC, RY> X;
-  X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane, T(1));
+  // this block's tiles
+  const int tcols = (nx + VEC - 1) / VEC;
+  const int tiles_x = (tcols + blockDim.x - 1) / blockDim.x;
+  const int band = P::kDim2 ? blockDim.y * RY : 1;
+  const int tiles_y = P::kDim2 ? (ny + band - 1) / band : 1;
+  const int ntiles = tiles_x * tiles_y;
+  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int t_begin = blockIdx.x * per;
+  const int t_end = min(ntiles, t_begin + per);
 
+  auto tile_origin = [&](int t, int& col0, int& r0) {
+    const int tx = t % tiles_x;
+    const int ty = t / tiles_x;
+    col0 = (tx * blockDim.x + threadIdx.x) * VEC;
+    r0 = P::kDim2 ? (ty * blockDim.y + threadIdx.y) * RY : 0;
+  };
+
+  Tile<P, T, VEC, RY> X;
+  Tile<P, T, VEC, RY> Vt;
+  int col0 = 0, r0 = 0;
+
+  double vscale = 1.0;
+  if constexpr (OP != OP_RES) {
+    if (a.ctl != nullptr) {
+      const int j = a.arn_j;
+      if (j == 0) {
+        vscale = a.ctl->scale[0];
+      } else {
+        __shared__ double gcol[kMaxM + 1];
+        const GivensOut g = finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
+        if (g.done != kRunning) return;  // uniform: every block computed the same update
+        vscale = 1.0 / g.wn;
+      }
+    } else if (a.vscale != nullptr) {
+      vscale = *a.vscale;
+    }
+  }
   double eps = 0.0;
   T eps_s = T(0);
-  Tile<P, T, VEC, RY> Vt;
-  if constexpr (OP == OP_AD) {
-    Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane, T(vscale));
-  } else if constexpr (OP == OP_FD) {
+  if constexpr (OP == OP_FD) {
     double vn2 = -1.0;
     if (a.eps.vparts.nb > 0) {
       __shared__ double tot[1];
-      reduce_partials(a.eps.vparts.part, a.eps.vparts.nb, 1, tot);
+      reduce_partials(a.eps.vparts, 1, tot);
       vn2 = tot[0];
     }
     eps = fd_eps(a.eps, vn2);
     eps_s = T(eps * vscale);
-    Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane, T(1));
   }
   const T eps_t = T(eps);
+  const T vs_t = T(vscale);
 
-  double acc[2] = {0.0, 0.0};
+  constexpr int NACC = OP == OP_RES ? 2 : (KDOT > 0 ? KDOT + 1 : 1);
+  double acc[NACC];
 #pragma unroll
-  for (int tt = 0; tt < RC; ++tt) {
-    const int r = r0 + tt;
-    const bool ok = colok && (!P::kDim2 || r < ny);
-    const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
-    T bval[NF][VEC];
-    if (a.b != nullptr) {
-      load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval);
-    } else {
-#pragma unroll
-      for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) bval[f][e] = T(0);
+  for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+
+  for (int t = t_begin; t < t_end; ++t) {
+    {
+      tile_origin(t, col0, r0);
+      const int cc = col0 < nx ? col0 : 0;
+      X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
+      if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
     }
-    T o[NF][VEC];
-    T o2[NF][VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      Nbr<T> xn[NF];
-      X.nbr(tt, e, xn);
-      const bool bnd = P::boundary(col0 + e, rr, nx, ny);
-      if constexpr (OP == OP_RES) {
-        T n[NF];
-        P::template N<T, T>(k, xn, n);
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-          o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[f][e];
-      } else if constexpr (OP == OP_AD) {
-        Nbr<T> vn[NF];
-        Vt.nbr(tt, e, vn);
-        Nbr<dual<T>> dn[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          dn[f].c = {xn[f].c, vn[f].c};
-          dn[f].l = {xn[f].l, vn[f].l};
-          dn[f].r = {xn[f].r, vn[f].r};
-          dn[f].d = {xn[f].d, vn[f].d};
-          dn[f].u = {xn[f].u, vn[f].u};
-        }
-        dual<T> n[NF];
-        P::template N<T, dual<T>>(k, dn, n);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          o[f][e] = bnd ? vn[f].c : alpha * vn[f].c + cN * n[f].t;
-          o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[f][e];
-        }
-      } else {
-        Nbr<T> vn[NF];
-        Vt.nbr(tt, e, vn);
-        Nbr<T> yn[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          yn[f].c = xn[f].c + eps_s * vn[f].c;
-          yn[f].l = xn[f].l + eps_s * vn[f].l;
-          yn[f].r = xn[f].r + eps_s * vn[f].r;
-          yn[f].d = xn[f].d + eps_s * vn[f].d;
-          yn[f].u = xn[f].u + eps_s * vn[f].u;
-        }
-        T n0[NF], n1[NF];
-        P::template N<T, T>(k, xn, n0);
-        P::template N<T, T>(k, yn, n1);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[f][e];
-          const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[f][e];
-          o[f][e] = (f1 - f0) / eps_t;
-        }
+    const bool colok = col0 < nx;
+    const int cc = colok ? col0 : 0;
+    X.exchange(col0, nx, lane);
+    if constexpr (OP != OP_RES) {
+      Vt.exchange(col0, nx, lane);
+      if constexpr (OP == OP_AD) {
+        if (vscale != 1.0) Vt.scale_by(vs_t);
       }
     }
-    if (ok) {
-      store_nodes<P, T, VEC>(a.out, a.plane, nx, rr, cc, o);
-      if constexpr (OP == OP_AD && WITHF) store_nodes<P, T, VEC>(a.out2, a.plane, nx, rr, cc, o2);
-      if constexpr (OP == OP_RES) {
-        const int t = P::kDim2 ? tt + 1 : 0;
+
+#pragma unroll
+    for (int tt = 0; tt < RC; ++tt) {
+      const int r = r0 + tt;
+      const bool ok = colok && (!P::kDim2 || r < ny);
+      const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
+      T bval[NF][VEC];
+      if (a.b != nullptr) {
+        load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval);
+      } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            acc[0] += (double)o[f][e] * (double)o[f][e];
-            acc[1] += (double)X.a[f][t][e] * (double)X.a[f][t][e];
+          for (int e = 0; e < VEC; ++e) bval[f][e] = T(0);
+      }
+      T o[NF][VEC];
+      T o2[NF][VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        Nbr<T> xn[NF];
+        X.nbr(tt, e, xn);
+        const bool bnd = P::boundary(col0 + e, rr, nx, ny);
+        if constexpr (OP == OP_RES) {
+          T n[NF];
+          P::template N<T, T>(k, xn, n);
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+            o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[f][e];
+        } else if constexpr (OP == OP_AD) {
+          Nbr<T> vn[NF];
+          Vt.nbr(tt, e, vn);
+          Nbr<dual<T>> dn[NF];
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            dn[f].c = {xn[f].c, vn[f].c};
+            dn[f].l = {xn[f].l, vn[f].l};
+            dn[f].r = {xn[f].r, vn[f].r};
+            dn[f].d = {xn[f].d, vn[f].d};
+            dn[f].u = {xn[f].u, vn[f].u};
           }
+          dual<T> n[NF];
+          P::template N<T, dual<T>>(k, dn, n);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            o[f][e] = bnd ? vn[f].c : alpha * vn[f].c + cN * n[f].t;
+            o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[f][e];
+          }
+        } else {
+          Nbr<T> vn[NF];
+          Vt.nbr(tt, e, vn);
+          Nbr<T> yn[NF];
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            yn[f].c = xn[f].c + eps_s * vn[f].c;
+            yn[f].l = xn[f].l + eps_s * vn[f].l;
+            yn[f].r = xn[f].r + eps_s * vn[f].r;
+            yn[f].d = xn[f].d + eps_s * vn[f].d;
+            yn[f].u = xn[f].u + eps_s * vn[f].u;
+          }
+          T n0[NF], n1[NF];
+          P::template N<T, T>(k, xn, n0);
+          P::template N<T, T>(k, yn, n1);
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[f][e];
+            const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[f][e];
+            o[f][e] = (f1 - f0) / eps_t;
+          }
+        }
+      }
+      if (ok) {
+        store_nodes<P, T, VEC>(a.out, a.plane, nx, rr, cc, o);
+        if constexpr (OP == OP_AD && WITHF) store_nodes<P, T, VEC>(a.out2, a.plane, nx, rr, cc, o2);
+        if constexpr (OP == OP_RES) {
+          const int t2 = P::kDim2 ? tt + 1 : 0;
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+              acc[0] += (double)o[f][e] * (double)o[f][e];
+              acc[1] += (double)X.a[f][t2][e] * (double)X.a[f][t2][e];
+            }
+        }
+        if constexpr (OP != OP_RES && KDOT > 0) {
+          // first CGS projection of the new vector on the stored basis
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[KDOT] += (double)o[f][e] * (double)o[f][e];
+#pragma unroll
+          for (int q = 0; q < KDOT; ++q) {
+            if (q < a.K) {
+              VT vq[NF][VEC];
+              load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rr, cc, vq);
+              double s = 0.0;
+#pragma unroll
+              for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[f][e]) * (double)o[f][e];
+              acc[q] += s;
+            }
+          }
+        }
       }
     }
   }
@@ -309,8 +406,15 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   if constexpr (OP == OP_RES) {
     if (a.nred > 0) {
       __shared__ double lds[2 * 4];
-      block_partials<2>(acc, a.nred, a.part_out, lds);
+      block_partials<2>(acc, a.nred, a.part_out.part, a.part_out.ld, lds);
     }
+  } else if constexpr (KDOT > 0) {
+    // ||Jv||^2 next to the K projections (static indices keep acc in registers)
+#pragma unroll
+    for (int q = 0; q < KDOT; ++q)
+      if (q == a.K) acc[q] = acc[KDOT];
+    __shared__ double lds[(KDOT + 1) * 4];
+    block_partials<KDOT + 1>(acc, a.K + 1, a.dots_out.part, a.dots_out.ld, lds);
   }
 }
 
