@@ -46,7 +46,7 @@ def percentile(xs, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def make_solver(spec, prec, xp, torch):
+def make_solver(spec, prec, xp, torch):  # prec: f64 | f32 | f16s
     from paper_2605_13378_amd import Solver
 
     s = Solver(spec, prec, m=30)
@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
@@ -191,7 +191,7 @@ def main():
     # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
     variants = {}
     if not args.no_variants:
-        for pr in ("f32", "f64"):
+        for pr in ("f32", "f16s", "f64"):
             sv = s if pr == prec else make_solver(spec, pr, xp, torch)
             for mode in ("ad", "fd"):
                 o = options_for(pr, mode)

@@ -69,6 +69,18 @@ template <> __device__ __forceinline__ float to_c<float, __half>(__half x) { ret
 template <class S, class C> __device__ __forceinline__ S to_s(C x) { return static_cast<S>(x); }
 template <> __device__ __forceinline__ __half to_s<__half, float>(float x) { return __float2half_rn(x); }
 
+template <class VT> constexpr bool is_half() { return false; }
+template <> constexpr bool is_half<__half>() { return true; }
+
+// Power-of-two storage scale for an FP16 basis vector of n entries and 2-norm
+// `norm`: typical entries |w_i| ~ norm / sqrt(n) are mapped near 1, far from
+// FP16's overflow (65504) and subnormal (6.1e-5) limits.
+__device__ __forceinline__ double fp16_scale(double norm, long long n) {
+  if (!(norm > 0.0) || !isfinite(norm)) return 1.0;
+  const double typical = norm / sqrt((double)n);
+  return exp2(-rint(log2(typical)));
+}
+
 // Wave-uniform values moved to scalar registers (the coefficients of the
 // Krylov updates), freeing vector registers for the register-resident basis.
 __device__ __forceinline__ float uniform(float x) {
@@ -206,6 +218,7 @@ struct Ctl {
   double hA[kMaxM + 1];              // first CGS projection of the current column
   double hB[kMaxM + 1];              // second CGS projection of the current column
   double scale[kMaxM + 1];           // stored V_i = v_i / scale_i  (true v_i = scale_i * V_i)
+  double vsig[kMaxM + 1];            // FP16 storage: V_i holds w_i * vsig_i (a power of two)
   double H[(kMaxM + 1) * kMaxM];     // rotated Hessenberg, column-major, ld = kMaxM + 1
 };
 

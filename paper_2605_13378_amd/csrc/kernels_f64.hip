@@ -11,8 +11,8 @@ hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, hipStream_t s) {
-  hipLaunchKernelGGL(cycle_begin_kernel<0>, dim3(1), dim3(kStreamThreads), 0, s, c, in, m);
+hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s) {
+  hipLaunchKernelGGL(cycle_begin_kernel<0>, dim3(1), dim3(kStreamThreads), 0, s, c, in, m, n, fp16);
   return hipGetLastError();
 }
 

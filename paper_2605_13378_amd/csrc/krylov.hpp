@@ -35,6 +35,7 @@ enum { PASS_A = 0, PASS_B = 1, PASS_C = 2 };
 // ---------------------------------------------------------------------------
 struct GivensOut {
   double c, s, gr, gp1, est, wn;
+  double vs;  // scale of the stored V_{j+1}: 1 / (||w|| * storage scale)
   int done;
 };
 
@@ -43,7 +44,7 @@ struct GivensIn {
   double h[kMaxM + 1];  // hA + hB
   double cs[kMaxM];
   double sn[kMaxM];
-  double gp, tol_abs, brk_tol, jvn2;
+  double gp, tol_abs, brk_tol, jvn2, sig;
 };
 
 __device__ inline void givens_gather(const Ctl* __restrict__ ctl, int j, GivensIn& in) {
@@ -58,12 +59,14 @@ __device__ inline void givens_gather(const Ctl* __restrict__ ctl, int j, GivensI
     in.tol_abs = ctl->tol_abs;
     in.brk_tol = ctl->brk_tol;
     in.jvn2 = ctl->jvn2;
+    in.sig = ctl->vsig[j + 1];
   }
 }
 
 __device__ inline GivensOut givens_column(const GivensIn& in, int j, double wn2, double* col) {
   GivensOut o;
   o.wn = sqrt(wn2);
+  o.vs = 1.0 / (o.wn * in.sig);
   for (int i = 0; i <= j; ++i) col[i] = in.h[i];
   col[j + 1] = o.wn;
   bool finite = isfinite(o.wn);
@@ -105,7 +108,7 @@ __device__ inline void givens_commit(Ctl* __restrict__ ctl, int j, const GivensO
   ctl->gr[j] = o.gr;
   ctl->gp[j + 1] = o.gp1;
   ctl->res_est = o.est;
-  ctl->scale[j + 1] = 1.0 / o.wn;
+  ctl->scale[j + 1] = o.vs;
   ctl->done_col[j + 1] = o.done;
   if (host_flags) host_flags[j] = o.done;
 }
@@ -173,10 +176,13 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
 
   __shared__ double tot[KMAX + 1];
+  __shared__ double s_sig;
   T coef[KMAX];
+  T sig = T(1);
   if constexpr (MODE != PASS_A) {
-    // projections of the previous pass on the stored vectors (+ ||J v_j||^2 from pass A)
-    reduce_partials(a.in, MODE == PASS_B ? K + 1 : K, tot);
+    // projections of the previous pass on the stored vectors (+ ||J v_j||^2
+    // from pass A; + ||w||^2 from pass B when the basis is stored in FP16)
+    reduce_partials(a.in, (MODE == PASS_B || is_half<VT>()) ? K + 1 : K, tot);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) coef[k] = uniform(k < K ? T(tot[k] * ctl->scale[k] * ctl->scale[k]) : T(0));
     if (blockIdx.x == 0 && threadIdx.x < K) {
@@ -187,6 +193,27 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
         ctl->hB[threadIdx.x] = h;
     }
     if (MODE == PASS_B && blockIdx.x == 0 && threadIdx.x == 0) ctl->jvn2 = tot[K];
+    if constexpr (MODE == PASS_C) {
+      if (threadIdx.x == 0) {
+        double sg = 1.0;
+        if constexpr (is_half<VT>()) {
+          // ||w_C||^2 = ||w_B||^2 - ||h2||^2 (orthogonal projection), to pick
+          // the power-of-two storage scale before w_C is written
+          double p2 = 0.0;
+          for (int k = 0; k < K; ++k) {
+            const double h = tot[k] * ctl->scale[k];
+            p2 += h * h;
+          }
+          const double wb2 = tot[K];
+          const double wc2 = wb2 - p2;
+          sg = fp16_scale(sqrt(wc2 > 1e-6 * wb2 ? wc2 : 1e-6 * wb2), a.n);
+        }
+        s_sig = sg;
+        if (blockIdx.x == 0) ctl->vsig[K] = sg;
+      }
+      __syncthreads();
+      sig = T(s_sig);
+    }
   }
   double acc[KMAX + 1];
 #pragma unroll
@@ -217,13 +244,17 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
           if (k < K)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[k] += (double)vv[k][e] * (double)wn[e];
+        if constexpr (is_half<VT>()) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];
+        }
         store_vec<T, VEC>(a.w + i, wn);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[0] += (double)wn[e] * (double)wn[e];
         VT o[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) o[e] = to_s<VT>(wn[e]);
+        for (int e = 0; e < VEC; ++e) o[e] = to_s<VT>(is_half<VT>() ? wn[e] * sig : wn[e]);
         store_vec<VT, VEC>(a.wout + i, o);
       }
     }
@@ -231,7 +262,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   }
 
   int nr = MODE == PASS_C ? 1 : K;
-  if constexpr (MODE == PASS_A) {
+  if constexpr (MODE == PASS_A || (MODE == PASS_B && is_half<VT>())) {
     // move ||w||^2 next to the K dot products (static indices keep acc in registers)
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
@@ -252,6 +283,7 @@ struct InitArgs {
   const T* w;   // nullable
   VT* V0;
   PartSink out;
+  T* tmp;       // FP16 storage: r is written here in the working precision
 };
 
 template <class T, class VT, int VEC>
@@ -271,13 +303,13 @@ __global__ void __launch_bounds__(256) init_cycle_kernel(const InitArgs<T, VT> a
 #pragma unroll
       for (int e = 0; e < VEC; ++e) r[e] = sg * r[e];
     }
-    VT o[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      o[e] = to_s<VT>(r[e]);
-      acc[0] += (double)r[e] * (double)r[e];
+    for (int e = 0; e < VEC; ++e) acc[0] += (double)r[e] * (double)r[e];
+    if constexpr (is_half<VT>()) {
+      store_vec<T, VEC>(a.tmp + i, r);
+    } else {
+      store_vec<VT, VEC>(a.V0 + i, r);
     }
-    store_vec<VT, VEC>(a.V0 + i, o);
   }
   __shared__ double lds[4];
   block_partials<1>(acc, 1, a.out.part, a.out.ld, lds);
@@ -285,11 +317,13 @@ __global__ void __launch_bounds__(256) init_cycle_kernel(const InitArgs<T, VT> a
 
 // One block: beta = ||V_0||; the first cycle of a solve also fixes ||rhs||.
 template <int kUnused = 0>
-__global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in, int m) {
+__global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in, int m, long long n, int fp16) {
   __shared__ double tot[1];
   reduce_partials(in, 1, tot);
   if (threadIdx.x == 0) {
     const double beta = sqrt(tot[0]);
+    const double sig = fp16 ? fp16_scale(beta, n) : 1.0;
+    ctl->vsig[0] = sig;
     if (ctl->first) {
       ctl->bnorm = beta;
       ctl->tol_abs = ctl->tol * beta;
@@ -298,11 +332,27 @@ __global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in,
     ctl->beta = beta;
     ctl->res_est = beta;
     ctl->gp[0] = beta;
-    ctl->scale[0] = 1.0 / beta;
+    ctl->scale[0] = 1.0 / (beta * sig);
     ctl->k = 0;
     ctl->done_col[0] = !isfinite(beta) ? kNonfinite : (beta <= ctl->tol_abs ? kConverged : kRunning);
   }
   if (threadIdx.x >= 1 && threadIdx.x <= m) ctl->done_col[threadIdx.x] = kRunning;
+}
+
+// FP16 storage of the first basis vector: V_0 = half(r * vsig[0]).
+template <class T, class VT, int VEC>
+__global__ void __launch_bounds__(256) store_basis0_kernel(long long n, const T* __restrict__ r, VT* __restrict__ V0,
+                                                          const Ctl* ctl) {
+  const T sig = T(ctl->vsig[0]);
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC; i < n; i += step) {
+    T x[VEC];
+    load_vec<T, VEC>(r + i, x);
+    VT o[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) o[e] = to_s<VT>(x[e] * sig);
+    store_vec<VT, VEC>(V0 + i, o);
+  }
 }
 
 // End of a cycle: finish the pending Givens column (if the last enqueued step

@@ -77,6 +77,9 @@ hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s);
 template <class T, class VT>
 hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s);
 
+template <class T, class VT>
+hipError_t launch_store_basis0(long long n, const T* r, VT* V0, const Ctl* c, int grid, hipStream_t s);
+
 template <class T>
 hipError_t launch_trial(long long n, const double* x64, const T* dx, double alpha, double* x64t, T* xw, int grid,
                         hipStream_t s);
@@ -91,7 +94,7 @@ template <class T>
 hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s);
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
-hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, hipStream_t s);
+hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);
 hipError_t launch_finish_sums(Partials in, int nr, double* out0, double* out1, hipStream_t s);
 
 }  // namespace jfnk

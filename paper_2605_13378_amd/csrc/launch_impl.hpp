@@ -117,6 +117,13 @@ hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T, class VT>
+hipError_t launch_store_basis0(long long n, const T* r, VT* V0, const Ctl* c, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  hipLaunchKernelGGL((store_basis0_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), 0, s, n, r, V0, c);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_trial(long long n, const double* x64, const T* dx, double alpha, double* x64t, T* xw, int grid,
                         hipStream_t s) {
@@ -148,7 +155,8 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
                                             hipStream_t, int*);                                                 \
   template hipError_t launch_cgs<T, VT>(int, const KArgs<T, VT>&, int, hipStream_t);                            \
   template hipError_t launch_init<T, VT>(const InitArgs<T, VT>&, int, hipStream_t);                             \
-  template hipError_t launch_vy<T, VT>(const VyArgs<T, VT>&, int, int, hipStream_t);
+  template hipError_t launch_vy<T, VT>(const VyArgs<T, VT>&, int, int, hipStream_t);                            \
+  template hipError_t launch_store_basis0<T, VT>(long long, const T*, VT*, const Ctl*, int, hipStream_t);
 
 #define JFNK_INSTANTIATE_SCALAR(T)                                                                               \
   template hipError_t launch_trial<T>(long long, const double*, const T*, double, double*, T*, int, hipStream_t);\

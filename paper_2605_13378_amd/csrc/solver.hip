@@ -304,11 +304,13 @@ struct Impl {
         wr = w;
       }
       {
-        InitArgs<T, VT> ia{s->npad, R, sign, wr, basis(s, 0), sink(s, 3)};
+        InitArgs<T, VT> ia{s->npad, R, sign, wr, basis(s, 0), sink(s, 3), w};
         ProfScope ps(s, PK_INIT, (double)s->n * ((wr ? 2.0 : 1.0) * sizeof(T) + sizeof(VT)));
         JFNK_HIP(s, launch_init<T, VT>(ia, sgrid, s->stream));
       }
-      JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->stream));
+      constexpr bool fp16 = !std::is_same<T, VT>::value;
+      JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->n, fp16 ? 1 : 0, s->stream));
+      if (fp16) JFNK_HIP(s, launch_store_basis0<T, VT>(s->npad, w, basis(s, 0), s->ctl, sgrid, s->stream));
       JFNK_TRY(sync_read_ctl(s));
       if (s->prof) prof_harvest(s, 0);
       if (cycle == 0) go.bnorm = s->hctl->bnorm;
@@ -622,15 +624,15 @@ jfnk_status jvp_api(jfnk_solver* s, const T* x, const T* v, T* Jv, T* F, int mod
   return Impl<T, T>::template jvp<T>(s, x, v, nullptr, Jv, mode == JFNK_JVP_AD ? F : nullptr, mode, e);
 }
 
-template <class T>
+template <class T, class VT>
 jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, double tol, int max_restarts, int mode,
                       double eps, int rule, jfnk_info* info) {
   const long long n = s->n;
   JFNK_HIP(s, hipMemcpyAsync(s->R, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
   const double brk = s->prec == JFNK_F64 ? 1e-14 : 1e-6;
-  typename Impl<T, T>::GOut go;
-  JFNK_TRY(Impl<T, T>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go));
+  typename Impl<T, VT>::GOut go;
+  JFNK_TRY(Impl<T, VT>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go));
   JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   JFNK_HIP(s, hipStreamSynchronize(s->stream));
   if (info) {
@@ -708,8 +710,8 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
     g_create_error = why;
     return JFNK_ERR_ARG;
   }
-  if (precision != JFNK_F64 && precision != JFNK_F32) {
-    g_create_error = "precision not supported by this build (F64 and F32 are)";
+  if (precision != JFNK_F64 && precision != JFNK_F32 && precision != JFNK_F16S) {
+    g_create_error = "unknown precision";
     return JFNK_ERR_ARG;
   }
   if (m < 1 || m > kMaxM) {
@@ -887,11 +889,14 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
   const auto t0 = std::chrono::steady_clock::now();
   jfnk_status st;
   if (s->prec == JFNK_F64)
-    st = gmres_api<double>(s, (const double*)x, (const double*)rhs, (double*)dx, m, tol, max_restarts, mode, eps,
-                           eps_rule, info);
+    st = gmres_api<double, double>(s, (const double*)x, (const double*)rhs, (double*)dx, m, tol, max_restarts, mode,
+                                   eps, eps_rule, info);
+  else if (s->prec == JFNK_F32)
+    st = gmres_api<float, float>(s, (const float*)x, (const float*)rhs, (float*)dx, m, tol, max_restarts, mode, eps,
+                                 eps_rule, info);
   else
-    st = gmres_api<float>(s, (const float*)x, (const float*)rhs, (float*)dx, m, tol, max_restarts, mode, eps,
-                          eps_rule, info);
+    st = gmres_api<float, __half>(s, (const float*)x, (const float*)rhs, (float*)dx, m, tol, max_restarts, mode, eps,
+                                  eps_rule, info);
   if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
 }
@@ -914,8 +919,10 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
   jfnk_status st;
   if (s->prec == JFNK_F64)
     st = Impl<double, double>::newton(s, x_inout, o, info);
-  else
+  else if (s->prec == JFNK_F32)
     st = Impl<float, float>::newton(s, x_inout, o, info);
+  else
+    st = Impl<float, __half>::newton(s, x_inout, o, info);
   info->status = st;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;

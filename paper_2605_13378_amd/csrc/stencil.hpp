@@ -254,7 +254,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         __shared__ double gcol[kMaxM + 1];
         const GivensOut g = finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
         if (g.done != kRunning) return;  // uniform: every block computed the same update
-        vscale = 1.0 / g.wn;
+        vscale = g.vs;
       }
     } else if (a.vscale != nullptr) {
       vscale = *a.vscale;

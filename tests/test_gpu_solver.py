@@ -196,3 +196,26 @@ def test_full_size_grayscott_f64_ad_per_iterate():
     """The benchmark workload (Gray-Scott 1024^2, FP64, AD, GMRES(30)) against the oracle."""
     spec, xp, src = W.config("grayscott")
     compare_newton(spec, xp, src, "f64", "ad", 1e-12)
+
+
+@pytest.mark.parametrize("kind,nx,ny", [("grayscott", 64, 64), ("burgers2d", 48, 40), ("grayscott", 1024, 1024)])
+@pytest.mark.parametrize("mode", ["ad", "fd"])
+def test_newton_f16s(kind, nx, ny, mode):
+    """FP16-stored basis and tangent, FP32 arithmetic, FP64 Givens/update/merit.
+
+    Not a per-iterate parity case (FP16 storage perturbs every basis vector by
+    ~2^-11 relative); the bound is the tolerance-implied one: both solutions
+    satisfy ||F(x)|| <= tol_N ||F0|| and ||J^-1|| <= 1 for these diffusive
+    implicit steps, so ||x_gpu - x_ref|| <= 2 tol_N ||F0|| (+ FP32 rounding).
+    """
+    spec, xp, src = case(kind, nx, ny) if nx < 1024 else W.config("grayscott")
+    p = Problem.from_spec(spec)
+    o = NewtonOptions.for_precision("f32", mode=mode, eps_rule="normalized")
+    x_ref, ref = newton_solve(p, xp, o, source=src)
+    s = solver(spec, "f16s", xp, src)
+    x, info = s.newton_solve(dev(xp, wdtype("f64")), mode=mode, eps_rule="normalized")
+    assert info["converged"] and ref.converged, (info, ref)
+    assert info["rel_res"][-1] < o.tol_newton
+    bound = 2 * o.tol_newton * ref.f0_norm + 1e-6 * np.linalg.norm(x_ref)
+    assert np.linalg.norm(host(x) - x_ref) <= bound
+    assert abs(info["newton_iters"] - ref.newton_iters) <= 1
