@@ -32,6 +32,25 @@ sys.path.insert(0, HERE)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 CONFIG_NAME = "grayscott-1024x1024-backward-euler"
 
+# Calibrated HBM traffic / algorithmic bytes of the dominant kernel class, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarized in profiles/, valid only for the
+# kernel sources they were taken with (hash of the device headers).
+MEASURED_TRAFFIC = {
+    "jvp_ad": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.933},
+    "cgs_b": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.852},
+    "cgs_c": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.851},
+}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("common.hpp", "krylov.hpp", "problems.hpp", "stencil.hpp"):
+        with open(os.path.join(HERE, "paper_2605_13378_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
@@ -73,8 +92,13 @@ def run_solves(s, x0, torch, count, opts, sync_each=True):
     return time.perf_counter() - t0, lat, info
 
 
-def jvp_bandwidth(s, torch, n, prec, mode, reps=200):
-    """Average duration (HIP events on the solver stream) and algorithmic GB/s of one JVP kind."""
+def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
+    """Average duration (HIP events on the solver stream) and algorithmic GB/s of one JVP kind.
+
+    With `scrub` (a large device tensor), the 256 MB last-level cache is
+    flushed by overwriting it before every launch (cold-cache protocol); the
+    events bracket the JVP kernel only.
+    """
     dt = torch.float64 if prec == "f64" else torch.float32
     g = torch.Generator(device="cuda").manual_seed(1)
     x = 1.0 + 0.1 * torch.randn(n, device="cuda", dtype=dt, generator=g)
@@ -84,6 +108,8 @@ def jvp_bandwidth(s, torch, n, prec, mode, reps=200):
     s.profile_reset()
     s.profile(True)
     for _ in range(reps):
+        if scrub is not None:
+            scrub.add_(1.0)
         s.jvp(x, v, mode=mode)
     torch.cuda.synchronize()
     st = s.profile_read()["jvp_ad" if mode == "ad" else "jvp_fd"]
@@ -125,6 +151,9 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="run a plain device copy of MB megabytes 3 times first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -140,6 +169,23 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    copy_gbs = None
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src_t = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = round(3 * 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        log(f"[bench] copy calibration {args.copy_calibration} MB: {copy_gbs} GB/s (read+write)")
+        del src_t, dst_t
 
     spec, xp, _ = W.config("grayscott", seed=0)
     n = W.n_unknowns(spec)
@@ -174,19 +220,38 @@ def main():
                        gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0.0,
                        share=round(v["ms"] / total_ms, 4) if total_ms > 0 else 0.0)
                for k, v in stats.items() if v["launches"]}
+    bpl = dom["bytes"] / max(1, dom["launches"])
+    meas = MEASURED_TRAFFIC.get(dom_name)
+    traffic = None
+    if meas is not None and meas["sources"] == kernel_sources_hash():
+        traffic = round(meas["ratio"] * bpl)  # HBM bytes per launch, calibrated counters
     roofline = dict(bound="hbm", kernel=dom_name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=None, avg_us=round(dom_avg_us, 3),
-                    launches=dom["launches"], bytes_per_launch_avg=dom["bytes"] / max(1, dom["launches"]))
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic, avg_us=round(dom_avg_us, 3),
+                    launches=dom["launches"], bytes_per_launch_avg=bpl)
 
     # ---- JVP bandwidth: AD vs FD -------------------------------------------
     jvp = {}
-    for pr in ("f32", "f64"):
+    for pr in (() if args.no_jvp_rows else ("f32", "f64")):
         sj = s if pr == prec else make_solver(spec, pr, xp, torch)
         for mode in ("ad", "fd"):
             jvp[f"{pr}-{mode}"] = jvp_bandwidth(sj, torch, n, pr, mode)
             log(f"[bench] jvp {pr}-{mode}: {jvp[f'{pr}-{mode}']}")
         if sj is not s:
             sj.close()
+
+    # ---- JVP bandwidth at the 2D Burgers 2048^2 shape (100-134 MB per call), hot and cold
+    jvp2048 = {}
+    spec_b, xp_b, _ = W.config("burgers2d", seed=0)
+    n_b = W.n_unknowns(spec_b)
+    scrub = torch.zeros(128 << 20, dtype=torch.float32, device="cuda")  # 512 MB
+    for pr in (() if args.no_jvp_rows else ("f32", "f64")):
+        sb = make_solver(spec_b, pr, xp_b, torch)
+        for mode in ("ad", "fd"):
+            jvp2048[f"{pr}-{mode}"] = jvp_bandwidth(sb, torch, n_b, pr, mode, reps=100)
+            jvp2048[f"{pr}-{mode}-cold"] = jvp_bandwidth(sb, torch, n_b, pr, mode, reps=50, scrub=scrub)
+            log(f"[bench] jvp 2048^2 {pr}-{mode}: {jvp2048[f'{pr}-{mode}']} cold {jvp2048[f'{pr}-{mode}-cold']}")
+        sb.close()
+    del scrub
 
     # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
     variants = {}
@@ -244,6 +309,8 @@ def main():
         "kernels": kernels,
         "profiled_pass_ms_per_step": round(1e3 * p_el / args.steps, 4),
         "jvp": jvp,
+        "jvp_burgers2d_2048": jvp2048,
+        "copy_calibration_gbs": copy_gbs,
         "variants": variants,
         "cpu_baseline": cpu,
     }

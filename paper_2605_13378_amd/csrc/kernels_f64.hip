@@ -7,17 +7,17 @@ JFNK_INSTANTIATE(double, double)
 JFNK_INSTANTIATE_SCALAR(double)
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s) {
-  hipLaunchKernelGGL(ctl_begin_kernel<0>, dim3(1), dim3(64), 0, s, c, tol, brk_tol, m);
+  JFNK_LAUNCH(ctl_begin_kernel<0>, dim3(1), dim3(64), s, c, tol, brk_tol, m);
   return hipGetLastError();
 }
 
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s) {
-  hipLaunchKernelGGL(cycle_begin_kernel<0>, dim3(1), dim3(kStreamThreads), 0, s, c, in, m, n, fp16);
+  JFNK_LAUNCH(cycle_begin_kernel<0>, dim3(1), dim3(kStreamThreads), s, c, in, m, n, fp16);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_sums(Partials in, int nr, double* out0, double* out1, hipStream_t s) {
-  hipLaunchKernelGGL(finish_sums_kernel<0>, dim3(1), dim3(kStreamThreads), 0, s, in, nr, out0, out1);
+  JFNK_LAUNCH(finish_sums_kernel<0>, dim3(1), dim3(kStreamThreads), s, in, nr, out0, out1);
   return hipGetLastError();
 }
 

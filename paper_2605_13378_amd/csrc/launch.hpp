@@ -4,6 +4,7 @@
 // translation units compile in parallel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -14,6 +15,25 @@
 namespace jfnk {
 
 enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3 };
+
+// Kernel timing: when the host driver sets g_timing around one launch, the
+// launch goes through hipExtLaunchKernelGGL with start/stop events attached
+// to the dispatch itself, so the events measure the kernel's execution
+// rather than launch-to-completion on the stream.
+struct KernelTiming {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+extern thread_local KernelTiming* g_timing;
+
+#define JFNK_LAUNCH(kernel, grid, block, stream, ...)                                                     \
+  do {                                                                                                    \
+    if (::jfnk::g_timing != nullptr)                                                                      \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ::jfnk::g_timing->start, ::jfnk::g_timing->stop, \
+                            0, __VA_ARGS__);                                                              \
+    else                                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                                    \
+  } while (0)
 
 // Elements per thread of the stencil kernel's vector path (16-byte accesses).
 template <class T>

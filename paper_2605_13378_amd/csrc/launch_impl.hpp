@@ -10,15 +10,15 @@ template <class P, class T, class VT, int VEC, int OP, bool WITHF>
 static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid, dim3 block, hipStream_t s) {
   constexpr int RY = kStencilRY;
   if (a.Vb == nullptr)
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, WITHF, 0>), grid, block, 0, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, WITHF, 0>), grid, block, s, a, c);
   else if (a.K <= 4)
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, 0, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
   else if (a.K <= 8)
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, 0, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, s, a, c);
   else if (a.K <= 16)
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, 0, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, s, a, c);
   else
-    hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, 0, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, s, a, c);
   return hipGetLastError();
 }
 
@@ -28,7 +28,7 @@ static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a,
   constexpr int RY = kStencilRY;
   if (op == OP_RES) {
     if constexpr (std::is_same<T, VT>::value) {
-      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false, 0>), grid, block, 0, s, a, c);
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false, 0>), grid, block, s, a, c);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -36,7 +36,7 @@ static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a,
   }
   if (op == OP_AD) {
     if (withf) {
-      hipLaunchKernelGGL((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true, 0>), grid, block, 0, s, a, c);
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true, 0>), grid, block, s, a, c);
       return hipGetLastError();
     }
     return stencil_kdot<P, T, VT, VEC, OP_AD, false>(a, c, grid, block, s);
@@ -81,11 +81,11 @@ static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStre
   constexpr int VEC = cgs_vec<T, KMAX>();
   const dim3 g(grid), b(kKrylovThreads);
   if (mode == PASS_A)
-    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_A>), g, b, 0, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_A>), g, b, s, a);
   else if (mode == PASS_B)
-    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_B>), g, b, 0, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_B>), g, b, s, a);
   else
-    hipLaunchKernelGGL((cgs_kernel<T, VT, KMAX, VEC, PASS_C>), g, b, 0, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_C>), g, b, s, a);
   return hipGetLastError();
 }
 
@@ -100,7 +100,7 @@ hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) 
 template <class T, class VT>
 hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s) {
   constexpr int VEC = krylov_vec<T>();
-  hipLaunchKernelGGL((init_cycle_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), 0, s, a);
+  JFNK_LAUNCH((init_cycle_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), s, a);
   return hipGetLastError();
 }
 
@@ -109,44 +109,44 @@ hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
   constexpr int VEC = krylov_vec<T>();
   const dim3 g(grid), b(kKrylovThreads);
   if (m <= 8)
-    hipLaunchKernelGGL((vy_kernel<T, VT, 8, VEC>), g, b, 0, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 8, VEC>), g, b, s, a);
   else if (m <= 16)
-    hipLaunchKernelGGL((vy_kernel<T, VT, 16, VEC>), g, b, 0, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 16, VEC>), g, b, s, a);
   else
-    hipLaunchKernelGGL((vy_kernel<T, VT, 32, VEC>), g, b, 0, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 32, VEC>), g, b, s, a);
   return hipGetLastError();
 }
 
 template <class T, class VT>
 hipError_t launch_store_basis0(long long n, const T* r, VT* V0, const Ctl* c, int grid, hipStream_t s) {
   constexpr int VEC = krylov_vec<T>();
-  hipLaunchKernelGGL((store_basis0_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), 0, s, n, r, V0, c);
+  JFNK_LAUNCH((store_basis0_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), s, n, r, V0, c);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_trial(long long n, const double* x64, const T* dx, double alpha, double* x64t, T* xw, int grid,
                         hipStream_t s) {
-  hipLaunchKernelGGL((newton_trial_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), 0, s, n, x64, dx, alpha, x64t,
+  JFNK_LAUNCH((newton_trial_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), s, n, x64, dx, alpha, x64t,
                      xw);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_cast(long long n, const double* src, T* dst, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((cast_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), 0, s, n, src, dst);
+  JFNK_LAUNCH((cast_kernel<T, 2>), dim3(grid), dim3(kStreamThreads), s, n, src, dst);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_norm2(long long n, const T* p, PartSink part, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((norm2_kernel<T>), dim3(grid), dim3(kStreamThreads), 0, s, n, p, part);
+  JFNK_LAUNCH((norm2_kernel<T>), dim3(grid), dim3(kStreamThreads), s, n, p, part);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((fill_zero_kernel<T>), dim3(grid), dim3(kStreamThreads), 0, s, n, p);
+  JFNK_LAUNCH((fill_zero_kernel<T>), dim3(grid), dim3(kStreamThreads), s, n, p);
   return hipGetLastError();
 }
 

@@ -26,6 +26,10 @@
 
 using namespace jfnk;
 
+namespace jfnk {
+thread_local KernelTiming* g_timing = nullptr;
+}
+
 namespace {
 
 constexpr int kNumProf = 9;
@@ -119,26 +123,26 @@ hipEvent_t pool_get(jfnk_solver* s) {
   return e;
 }
 
+// Times the single kernel launched while it is alive (see g_timing).
 struct ProfScope {
   jfnk_solver* s;
   int kid;
   double bytes;
-  hipEvent_t a = nullptr;
+  KernelTiming t;
   ProfScope(jfnk_solver* s_, int kid_, double bytes_) : s(s_), kid(kid_), bytes(bytes_) {
     if (s->prof) {
-      a = pool_get(s);
-      if (a) (void)hipEventRecord(a, s->stream);
+      t.start = pool_get(s);
+      t.stop = pool_get(s);
+      if (t.start && t.stop) g_timing = &t;
     }
   }
   ~ProfScope() {
-    if (s->prof && a) {
-      hipEvent_t b = pool_get(s);
-      if (b) {
-        (void)hipEventRecord(b, s->stream);
-        s->recs.push_back({kid, bytes, a, b, s->cur_step});
-      } else {
-        s->pool.push_back(a);
-      }
+    if (g_timing == &t) {
+      g_timing = nullptr;
+      s->recs.push_back({kid, bytes, t.start, t.stop, s->cur_step});
+    } else {
+      if (t.start) s->pool.push_back(t.start);
+      if (t.stop) s->pool.push_back(t.stop);
     }
   }
 };
