@@ -92,6 +92,9 @@ def run_solves(s, x0, torch, count, opts, sync_each=True):
     return time.perf_counter() - t0, lat, info
 
 
+QUEUE_SPIN_CYCLES = 50_000_000
+
+
 def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
     """Average duration (HIP events on the solver stream) and algorithmic GB/s of one JVP kind.
 
@@ -105,8 +108,13 @@ def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
     v = torch.randn(n, device="cuda", dtype=dt, generator=g)
     for _ in range(5):
         s.jvp(x, v, mode=mode)
+    torch.cuda.synchronize()
     s.profile_reset()
     s.profile(True)
+    # queue every launch behind a spin kernel so that they run back to back,
+    # as inside a solve, instead of one at a time from an idle device
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(QUEUE_SPIN_CYCLES)
     for _ in range(reps):
         if scrub is not None:
             scrub.add_(1.0)
@@ -119,6 +127,82 @@ def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9 if st["ms"] > 0 else 0.0
     return dict(avg_us=round(avg_us, 3), gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4),
                 bytes_per_launch=st["bytes"] / max(1, st["launches"]), launches=st["launches"])
+
+
+def serving_pass(batch, reqs, inputs, rate_scale, saturate):
+    """Feed `reqs` to `batch` (Poisson arrivals scaled by 1/rate_scale, or all at
+    once) and return solves/s and arrival-to-result latency percentiles."""
+    import threading
+
+    tickets = [None] * len(reqs)
+    results = [None] * len(reqs)
+    submitted = threading.Semaphore(0)
+
+    def collect():
+        for i in range(len(reqs)):
+            submitted.acquire()
+            results[i] = batch.wait(tickets[i])
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = batch.clock()
+    arrivals = []
+    for i, req in enumerate(reqs):
+        target = t0 if saturate else t0 + req["arrival"] / rate_scale
+        if not saturate:
+            while True:
+                dt = target - batch.clock()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
+        spec, xp = inputs[i]
+        tickets[i] = batch.submit(spec, xp)
+        arrivals.append(target)
+        submitted.release()
+    th.join()
+    done = [r[1]["times"][2] for r in results]
+    lat = [d - a for d, a in zip(done, arrivals)]
+    span = max(done) - t0
+    bad = sum(1 for r in results if r[1]["rc"] not in (0, 6))
+    unconv = sum(1 for r in results if not r[1]["converged"])
+    return dict(solves_per_s=round(len(reqs) / span, 2), makespan_s=round(span, 3),
+                p50_ms=round(1e3 * percentile(lat, 0.5), 3), p99_ms=round(1e3 * percentile(lat, 0.99), 3),
+                failed=bad, not_converged=unconv)
+
+
+def serving_bench(count, slots, budget_gib, seed=0):
+    """Continuous batching vs one request at a time on the serving mix (FP32, AD)."""
+    from paper_2605_13378_amd import Batch
+
+    import workloads as W
+
+    reqs = W.serving_stream(count=count, seed=seed, rate=1.0)
+    inputs = [W.serving_request_inputs(r) for r in reqs]
+    budget = int(budget_gib * (1 << 30))
+    single = Batch("f32", m=30, max_slots=1, budget_bytes=budget)
+    multi = Batch("f32", m=30, max_slots=slots, budget_bytes=budget)
+    warm = min(len(reqs), 200)
+    serving_pass(single, reqs[:warm], inputs[:warm], 1.0, True)
+    serving_pass(multi, reqs[:warm], inputs[:warm], 1.0, True)
+    out = {"requests": count, "stream_seed": seed, "slots": slots, "budget_gib": budget_gib,
+           "precision": "f32", "jvp": "ad", "mix": "1D Burgers N=2^8..2^16 / Gray-Scott side 2^6..2^10, 1:1"}
+    sat1 = serving_pass(single, reqs, inputs, 1.0, True)
+    satm = serving_pass(multi, reqs, inputs, 1.0, True)
+    mu1 = sat1["solves_per_s"]
+    out["saturation"] = {"one_at_a_time": sat1, "batched": satm}
+    log(f"[bench] serving saturation: one-at-a-time {sat1} batched {satm}")
+    rows = []
+    for lam in (0.5, 1.0, 2.0, 4.0):
+        rate = lam * mu1  # requests/s; the stream was drawn at 1 request/s
+        r1 = serving_pass(single, reqs, inputs, rate, False)
+        rm = serving_pass(multi, reqs, inputs, rate, False)
+        rows.append({"lambda_over_mu1": lam, "rate_per_s": round(rate, 2), "one_at_a_time": r1, "batched": rm})
+        log(f"[bench] serving lambda={lam} mu1: one-at-a-time {r1} batched {rm}")
+    out["poisson"] = rows
+    out["batched_stats"] = multi.stats()
+    single.close()
+    multi.close()
+    return out
 
 
 def cpu_baseline(spec, xp, prec):
@@ -152,6 +236,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
+    ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run a plain device copy of MB megabytes 3 times first (HBM counter calibration)")
     args = ap.parse_args()
@@ -280,6 +368,11 @@ def main():
             if sv is not s:
                 sv.close()
 
+    serving = None
+    if not args.no_serving:
+        log(f"[bench] serving: {args.serving_requests} requests, {args.serving_slots} slots")
+        serving = serving_bench(args.serving_requests, args.serving_slots, args.serving_budget_gib)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (1 solve)")
@@ -312,6 +405,7 @@ def main():
         "jvp_burgers2d_2048": jvp2048,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

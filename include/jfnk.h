@@ -174,6 +174,11 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts,
                               jfnk_info* info);
 
+/* Move a solver to another stream (a hipStream_t; NULL = the default stream)
+ * for its later calls.  The caller orders any work still pending on the old
+ * stream (the solver keeps no pointer to it). */
+jfnk_status jfnk_set_stream(jfnk_solver* s, void* hip_stream);
+
 /* The paper's defaults for a precision (see jfnk_options). */
 void jfnk_default_options(int precision, jfnk_options* out);
 
@@ -189,6 +194,67 @@ jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);
 jfnk_status jfnk_profile_read(jfnk_solver* s, int kernel, long long* launches, double* total_ms,
                               double* bytes);
 jfnk_status jfnk_profile_reset(jfnk_solver* s);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent implicit-step solves.
+ *
+ * A batch owns `max_slots` worker threads, each with its own HIP stream, and a
+ * device-memory budget.  Requests (one Newton solve each: problem, previous
+ * state, options) are admitted first come, first served as soon as a slot is
+ * free and the request's workspace fits the budget; admitted requests run
+ * concurrently on their slots' streams, so their kernels overlap on the
+ * device.  Solver workspaces stay on the device between requests of the same
+ * shape (least recently used ones are released when the budget needs room).
+ * Every kernel's launch shape depends only on the problem, so a request's
+ * result is bitwise the same whether it runs alone or in a mix.
+ * ------------------------------------------------------------------------ */
+typedef struct jfnk_batch jfnk_batch;
+
+typedef struct {
+  size_t budget_bytes;  /* device memory for solver workspaces (running + cached) */
+  int max_slots;        /* requests on the device at once, 1..64 */
+  int precision;        /* jfnk_precision of every request */
+  int m;                /* GMRES restart length of every request, 1..32 */
+  int keep_workspaces;  /* 1: cache idle workspaces by shape; 0: free after each request */
+} jfnk_batch_config;
+
+typedef struct {
+  long long submitted, completed, failed;
+  long long workspaces_created, workspaces_released;
+  int max_running;          /* most requests seen on the device at once */
+  size_t bytes_in_use;      /* workspaces held now */
+  size_t peak_bytes;        /* most workspace bytes held at once (never above the budget) */
+} jfnk_batch_stats;
+
+/* Create a batch; the calling thread's current device is used. */
+jfnk_status jfnk_batch_create(const jfnk_batch_config* cfg, jfnk_batch** out);
+
+/* Wait for running requests, drop queued ones, free everything. */
+jfnk_status jfnk_batch_destroy(jfnk_batch* b);
+
+/* Queue one solve.  x_prev (and source, nullable; Kerr only) are host FP64
+ * arrays of jfnk_problem_size() entries, copied before the call returns; the
+ * Newton iteration starts from x_prev.  opts NULL = jfnk_default_options.
+ * Returns JFNK_ERR_ARG for an invalid problem and JFNK_ERR_OOM when the
+ * request alone exceeds the budget.  Thread-safe. */
+jfnk_status jfnk_batch_submit(jfnk_batch* b, const jfnk_problem* problem, const double* x_prev,
+                              const double* source, const jfnk_options* opts, long long* ticket);
+
+/* 1 when the request has finished, 0 while queued or running, -1 for an
+ * unknown ticket.  Thread-safe. */
+int jfnk_batch_poll(jfnk_batch* b, long long ticket);
+
+/* Block until the request finishes, copy its last iterate to x_out (host,
+ * nullable) and its info (nullable), and retire the ticket.  times (nullable,
+ * 3 doubles): submit, start and finish time in seconds on the batch clock.
+ * Returns the request's Newton status (jfnk_newton_solve's). */
+jfnk_status jfnk_batch_wait(jfnk_batch* b, long long ticket, double* x_out, jfnk_info* info,
+                            double* times);
+
+/* Seconds since jfnk_batch_create on the clock used by jfnk_batch_wait. */
+double jfnk_batch_clock(const jfnk_batch* b);
+
+jfnk_status jfnk_batch_get_stats(jfnk_batch* b, jfnk_batch_stats* out);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@ kernels behind the C ABI of include/jfnk.h; ``jfnk`` is the Python binding.
 
 from .jfnk import (  # noqa: F401
     EPS_RULES,
+    Batch,
     MODES,
     PRECISIONS,
     PROBLEM_IDS,

@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libjfnk.so")
 ARCH = os.environ.get("JFNK_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["solver.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_f16.hip"]
+SOURCES = ["solver.hip", "serving.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_f16.hip"]
 
 
 def hipcc() -> str:

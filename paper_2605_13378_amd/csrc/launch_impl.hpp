@@ -6,11 +6,10 @@
 
 namespace jfnk {
 
-template <class P, class T, class VT, int VEC, int OP, bool WITHF>
+template <class P, class T, class VT, int VEC, int RY, int OP>
 static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid, dim3 block, hipStream_t s) {
-  constexpr int RY = kStencilRY;
   if (a.Vb == nullptr)
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, WITHF, 0>), grid, block, s, a, c);
+    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
   else if (a.K <= 4)
     JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
   else if (a.K <= 8)
@@ -22,10 +21,9 @@ static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3
   return hipGetLastError();
 }
 
-template <class P, class T, class VT, int VEC>
+template <class P, class T, class VT, int VEC, int RY>
 static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid,
                                 dim3 block, hipStream_t s) {
-  constexpr int RY = kStencilRY;
   if (op == OP_RES) {
     if constexpr (std::is_same<T, VT>::value) {
       JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false, 0>), grid, block, s, a, c);
@@ -39,9 +37,9 @@ static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a,
       JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true, 0>), grid, block, s, a, c);
       return hipGetLastError();
     }
-    return stencil_kdot<P, T, VT, VEC, OP_AD, false>(a, c, grid, block, s);
+    return stencil_kdot<P, T, VT, VEC, RY, OP_AD>(a, c, grid, block, s);
   }
-  return stencil_kdot<P, T, VT, VEC, OP_FD, false>(a, c, grid, block, s);
+  return stencil_kdot<P, T, VT, VEC, RY, OP_FD>(a, c, grid, block, s);
 }
 
 template <class P, class T, class VT>
@@ -49,14 +47,14 @@ static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectoriz
                                       const Coefs& c, int cap, hipStream_t s, int* nblocks) {
   constexpr int V = P::kInterleaved ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
   const int vec = vectorized ? V : 1;
-  dim3 block;
-  int ntiles = 0;
-  stencil_shape(pid, a.nx, a.ny, vec, block, ntiles);
-  const int nb = ntiles < cap ? ntiles : cap;
-  if (nblocks) *nblocks = nb;
-  const dim3 grid(nb, 1, 1);
-  if (vectorized) return stencil_by_op<P, T, VT, V>(op, withf, a, c, grid, block, s);
-  return stencil_by_op<P, T, VT, 1>(op, withf, a, c, grid, block, s);
+  const StencilPlan p = stencil_plan(pid, a.nx, a.ny, vec, cap);
+  if (nblocks) *nblocks = p.grid;
+  const dim3 grid(p.grid, 1, 1);
+  if (!vectorized) return stencil_by_op<P, T, VT, 1, 2>(op, withf, a, c, grid, p.block, s);
+  if constexpr (P::kDim2) {
+    if (p.ry == 4) return stencil_by_op<P, T, VT, V, 4>(op, withf, a, c, grid, p.block, s);
+  }
+  return stencil_by_op<P, T, VT, V, 2>(op, withf, a, c, grid, p.block, s);
 }
 
 template <class T, class VT>

@@ -181,8 +181,13 @@ int stream_grid(const jfnk_solver* s, int vec) {
   return (int)std::max<long long>(1, std::min<long long>(need, 4LL * s->cu));
 }
 
-// Block cap of plain stencil launches (residual, standalone JVP).
+// Block caps of stencil launches: a launch that writes per-block partial sums
+// (residual norms) stays within the partial-sum rows; the Arnoldi JVP, whose
+// partials carry up to 33 columns, within 2 blocks per compute unit; launches
+// without partial sums take one tile per block.
 int stencil_cap(const jfnk_solver* s) { return 4 * s->cu; }
+int arnoldi_cap(const jfnk_solver* s) { return 2 * s->cu; }
+constexpr int kNoCap = 1 << 30;
 
 bool aligned(const void* p, size_t a) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -226,7 +231,8 @@ struct Impl {
     int nb = 0;
     {
       ProfScope ps(s, PK_RES, 3.0 * s->n * sizeof(T));
-      JFNK_HIP(s, launch_stencil<T, T>(s->pid, OP_RES, false, vz, a, s->coefs, stencil_cap(s), s->stream, &nb));
+      JFNK_HIP(s, launch_stencil<T, T>(s->pid, OP_RES, false, vz, a, s->coefs, norms ? stencil_cap(s) : kNoCap,
+                                        s->stream, &nb));
     }
     if (norms) JFNK_HIP(s, launch_finish_sums(parts(s, 5, nb), 2, &s->ctl->fnorm2, &s->ctl->xnorm2, s->stream));
     return JFNK_OK;
@@ -273,7 +279,7 @@ struct Impl {
     double bytes = (mode == JFNK_JVP_AD ? 2.0 + (Fout ? 2.0 : 0.0) : 3.0) * s->n * sizeof(T) + (double)s->n * sizeof(W);
     if (arn_j >= 0) bytes += (double)arn_j * s->n * sizeof(W);
     ProfScope ps(s, mode == JFNK_JVP_AD ? PK_AD : PK_FD, bytes);
-    const int cap = arn_j >= 0 ? 2 * s->cu : stencil_cap(s);
+    const int cap = arn_j >= 0 ? arnoldi_cap(s) : kNoCap;
     JFNK_HIP(s, launch_stencil<T, W>(s->pid, op, Fout != nullptr, vz, a, s->coefs, cap, s->stream, nb_out));
     return JFNK_OK;
   }
@@ -782,8 +788,8 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
         st = JFNK_ERR_HIP;
       }
   }
-  if (st == JFNK_OK && hipDeviceSynchronize() != hipSuccess) {
-    s->err = "device synchronize after set-up failed";
+  if (st == JFNK_OK && hipStreamSynchronize(s->stream) != hipSuccess) {
+    s->err = "stream synchronize after set-up failed";
     st = JFNK_ERR_HIP;
   }
   if (st != JFNK_OK) {
@@ -793,6 +799,12 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
     return st;
   }
   *out = s;
+  return JFNK_OK;
+}
+
+jfnk_status jfnk_set_stream(jfnk_solver* s, void* hip_stream) {
+  if (!s) return JFNK_ERR_ARG;
+  s->stream = static_cast<hipStream_t>(hip_stream);
   return JFNK_OK;
 }
 
@@ -844,7 +856,7 @@ jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double
   a.out = dst;
   const int vec = stencil_vec<double>(s->pid);
   const bool vz = (p.nx % vec == 0) && aligned(x_prev, 16) && aligned(source, 16);
-  JFNK_HIP(s, launch_stencil<double, double>(s->pid, OP_RES, false, vz, a, s->coefs, stencil_cap(s), s->stream));
+  JFNK_HIP(s, launch_stencil<double, double>(s->pid, OP_RES, false, vz, a, s->coefs, kNoCap, s->stream));
   if (s->prec != JFNK_F64)
     JFNK_HIP(s, launch_cast<float>(s->npad, s->tmp64, static_cast<float*>(s->b), sgrid, s->stream));
   s->has_prev = true;

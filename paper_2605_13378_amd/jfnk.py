@@ -60,6 +60,20 @@ class Info(ctypes.Structure):
                     seconds=self.seconds)
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("precision", ctypes.c_int),
+                ("m", ctypes.c_int), ("keep_workspaces", ctypes.c_int)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("workspaces_created", ctypes.c_longlong), ("workspaces_released", ctypes.c_longlong),
+                ("max_running", ctypes.c_int), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class JfnkError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -91,6 +105,17 @@ _SIGNATURES = [
     ("jfnk_profile_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("jfnk_profile_reset", ctypes.c_int, [ctypes.c_void_p]),
+    ("jfnk_set_stream", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("jfnk_batch_create", ctypes.c_int, [ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    ("jfnk_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("jfnk_batch_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(Options),
+                                         ctypes.POINTER(ctypes.c_longlong)]),
+    ("jfnk_batch_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong]),
+    ("jfnk_batch_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p,
+                                       ctypes.POINTER(Info), ctypes.c_void_p]),
+    ("jfnk_batch_clock", ctypes.c_double, [ctypes.c_void_p]),
+    ("jfnk_batch_get_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BatchStats)]),
 ]
 
 
@@ -278,6 +303,86 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().jfnk_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Continuous batching of independent Newton solves (jfnk_batch_* calls).
+
+    Requests carry host FP64 arrays (numpy); `submit` copies them and returns
+    a ticket at once, `wait` blocks for the result.  The library's worker
+    threads run admitted requests concurrently, each on its own HIP stream.
+    """
+
+    def __init__(self, precision: str = "f32", m: int = 30, max_slots: int = 4,
+                 budget_bytes: int = 16 << 30, keep_workspaces: bool = True):
+        self.precision = precision
+        self.m = m
+        cfg = BatchConfig(budget_bytes=int(budget_bytes), max_slots=int(max_slots),
+                          precision=PRECISIONS[precision], m=int(m), keep_workspaces=1 if keep_workspaces else 0)
+        h = ctypes.c_void_p()
+        rc = lib().jfnk_batch_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != 0:
+            raise JfnkError(rc, "jfnk_batch_create rejected the configuration")
+        self._h = h
+        self._n = {}
+
+    def submit(self, spec: dict, x_prev, source=None, **opts) -> int:
+        import numpy as np
+
+        prob = make_problem(spec)
+        n = problem_size(spec)
+        xp = np.ascontiguousarray(x_prev, dtype=np.float64)
+        if xp.size != n:
+            raise ValueError(f"x_prev must have {n} entries")
+        src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+        if src is not None and src.size != n:
+            raise ValueError(f"source must have {n} entries")
+        o = default_options(self.precision, **opts)
+        if o.m > self.m:
+            raise ValueError("options.m exceeds the batch's m")
+        t = ctypes.c_longlong()
+        rc = lib().jfnk_batch_submit(self._h, ctypes.byref(prob), xp.ctypes.data,
+                                     None if src is None else src.ctypes.data, ctypes.byref(o), ctypes.byref(t))
+        if rc != 0:
+            raise JfnkError(rc, "jfnk_batch_submit rejected the request")
+        self._n[t.value] = n
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        return lib().jfnk_batch_poll(self._h, ticket) == 1
+
+    def wait(self, ticket: int):
+        """(x, info dict with 'times' = (submit, start, finish) on the batch clock)."""
+        import numpy as np
+
+        n = self._n.pop(ticket)
+        x = np.empty(n, dtype=np.float64)
+        info = Info()
+        times = (ctypes.c_double * 3)()
+        rc = lib().jfnk_batch_wait(self._h, ticket, x.ctypes.data, ctypes.byref(info), times)
+        d = info.as_dict()
+        d["rc"] = rc
+        d["times"] = (times[0], times[1], times[2])
+        return x, d
+
+    def clock(self) -> float:
+        return float(lib().jfnk_batch_clock(self._h))
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        lib().jfnk_batch_get_stats(self._h, ctypes.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().jfnk_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
