@@ -129,6 +129,54 @@ def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
                 bytes_per_launch=st["bytes"] / max(1, st["launches"]), launches=st["launches"])
 
 
+def latency_c1(torch, repeats, seeds):
+    """1D Burgers N=256, one backward-Euler step, FP64, GMRES(30), tol_N 1e-10,
+    tol_K 1e-12: per-solve wall time (p50/p99) of the single-workgroup engine
+    and of the multi-kernel one, AD and FD (paper step), and over seeds."""
+    import workloads as W
+
+    spec, xp, _ = W.config("burgers1d", seed=0)
+    s = make_solver(spec, "f64", xp, torch)
+    x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
+    base = dict(tol_newton=1e-10, tol_krylov=1e-12, m=30, max_newton=15)
+    out = {"workload": "burgers1d_256_f64", "tol_newton": 1e-10, "tol_krylov": 1e-12}
+    for engine in ("single", "multi"):
+        for mode in ("ad", "fd"):
+            o = dict(base, mode=mode, engine=engine)
+            # FD cannot reach tol_K 1e-12 (its JVP carries ~sqrt(eps) relative
+            # error), so every FD Newton step runs all restart cycles: few repeats
+            if mode == "fd":
+                count = 5 if engine == "single" else 2
+            else:
+                count = repeats if engine == "single" else max(1, repeats // 5)
+            run_solves(s, x0, torch, 1 if mode == "fd" else 5, o)
+            el, lat, info = run_solves(s, x0, torch, count, o)
+            out[f"{engine}-{mode}"] = dict(solves=count, solves_per_s=round(count / el, 1),
+                                           p50_us=round(1e6 * percentile(lat, 0.5), 1),
+                                           p99_us=round(1e6 * percentile(lat, 0.99), 1),
+                                           newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                                           converged=info["converged"])
+            log(f"[bench] C1 {engine}-{mode}: {out[f'{engine}-{mode}']}")
+    # seeds 0..seeds-1 (a new previous state per solve), single workgroup, AD
+    lat = []
+    conv = 0
+    o = dict(base, mode="ad", engine="single")
+    for sd in range(seeds):
+        _, xs, _ = W.config("burgers1d", seed=sd)
+        xt = torch.tensor(xs, dtype=torch.float64, device="cuda")
+        s.set_previous(xt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = s.newton_solve(xt, **o)
+        lat.append(time.perf_counter() - t1)
+        conv += int(info["converged"])
+    out["seeds-single-ad"] = dict(seeds=seeds, converged=conv, p50_us=round(1e6 * percentile(lat, 0.5), 1),
+                                  p99_us=round(1e6 * percentile(lat, 0.99), 1))
+    log(f"[bench] C1 seeds: {out['seeds-single-ad']}")
+    s.close()
+    return out
+
+
 def serving_pass(batch, reqs, inputs, rate_scale, saturate):
     """Feed `reqs` to `batch` (Poisson arrivals scaled by 1/rate_scale, or all at
     once) and return solves/s and arrival-to-result latency percentiles."""
@@ -221,10 +269,24 @@ def cpu_baseline(spec, xp, prec):
         t0 = time.perf_counter()
         _, info = newton_solve(p, xp, o)
         el = time.perf_counter() - t0
+    # the latency workload (1D Burgers N=256, FP64, tol_N 1e-10, tol_K 1e-12) on the same core
+    import workloads as W
+
+    spec1, xp1, _ = W.config("burgers1d", seed=0)
+    p1 = Problem.from_spec(spec1)
+    o1 = NewtonOptions.for_precision("f64", mode="ad", tol_newton=1e-10, tol_krylov=1e-12)
+    with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
+        newton_solve(p1, xp1, o1)
+        t1 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            newton_solve(p1, xp1, o1)
+        el1 = (time.perf_counter() - t1) / reps
     return dict(value=round(1.0 / el, 5), unit="Newton solves/s", cores=1, kind="oracle",
                 sample=f"1 full Newton solve (AD, {prec.upper()} tolerances, FP64 arithmetic) of the "
                        f"Gray-Scott 1024^2 implicit step; {info.newton_iters} Newton / "
-                       f"{info.krylov_iters} GMRES iterations in {el:.1f} s")
+                       f"{info.krylov_iters} GMRES iterations in {el:.1f} s",
+                latency_burgers1d_256_us=round(1e6 * el1, 1))
 
 
 def main():
@@ -237,6 +299,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
+    ap.add_argument("--no-latency", action="store_true", help="skip the 1D Burgers N=256 latency rows")
+    ap.add_argument("--latency-repeats", type=int, default=1000)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
@@ -368,6 +432,11 @@ def main():
             if sv is not s:
                 sv.close()
 
+    c1 = None
+    if not args.no_latency:
+        log(f"[bench] latency rows: 1D Burgers N=256, {args.latency_repeats} repeats")
+        c1 = latency_c1(torch, args.latency_repeats, seeds=1000)
+
     serving = None
     if not args.no_serving:
         log(f"[bench] serving: {args.serving_requests} requests, {args.serving_slots} slots")
@@ -405,6 +474,7 @@ def main():
         "jvp_burgers2d_2048": jvp2048,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
+        "latency_burgers1d_256": c1,
         "serving": serving,
         "cpu_baseline": cpu,
     }

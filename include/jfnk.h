@@ -109,7 +109,19 @@ typedef struct {
   int eps_rule;          /* jfnk_eps_rule */
   double* history;       /* nullable DEVICE array of (max_newton + 1) * n doubles:
                             receives every Newton iterate x_k (k = 0, 1, ...) */
+  int engine;            /* jfnk_engine */
 } jfnk_options;
+
+/* How jfnk_newton_solve runs the method (same algorithm, same options):
+ *   AUTO:  SINGLE_WORKGROUP when the problem fits it, else MULTI_KERNEL;
+ *   MULTI_KERNEL: one kernel per step of the method, the grid spread over
+ *          the whole device (the throughput path);
+ *   SINGLE_WORKGROUP: the whole solve in one launch of one workgroup with
+ *          every vector in LDS (the latency path for small problems: about
+ *          n (m + 6) * sizeof(working type) + 16 n bytes must fit the
+ *          device's LDS per workgroup; FP64 and FP32 only).  Requesting it
+ *          for a problem that does not fit returns JFNK_ERR_ARG. */
+typedef enum { JFNK_ENGINE_AUTO = 0, JFNK_ENGINE_MULTI_KERNEL = 1, JFNK_ENGINE_SINGLE_WORKGROUP = 2 } jfnk_engine;
 
 #define JFNK_MAX_ITERS 64
 
@@ -188,7 +200,7 @@ const char* jfnk_last_error(const jfnk_solver* s);
 /* Kernel timing with HIP events on the solver's stream (off by default).
  * kernel: 0 residual, 1 AD JVP, 2 FD JVP, 3 CGS pass A (V^T w), 4 CGS pass B
  * (update + dot), 5 CGS pass C (update + norm + Givens), 6 V y update,
- * 7 cycle start, 8 Newton trial update.  Reports the launches timed since
+ * 7 cycle start, 8 Newton trial update, 9 single-workgroup whole solve.  Reports the launches timed since
  * the last reset, their summed duration (ms) and their algorithmic HBM bytes. */
 jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);
 jfnk_status jfnk_profile_read(jfnk_solver* s, int kernel, long long* launches, double* total_ms,

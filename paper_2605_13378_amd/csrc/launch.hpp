@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "fused.hpp"
 #include "krylov.hpp"
 #include "problems.hpp"
 #include "stencil.hpp"
@@ -25,6 +26,15 @@ struct KernelTiming {
   hipEvent_t stop = nullptr;
 };
 extern thread_local KernelTiming* g_timing;
+
+#define JFNK_LAUNCH_SHM(kernel, grid, block, shm, stream, ...)                                            \
+  do {                                                                                                    \
+    if (::jfnk::g_timing != nullptr)                                                                      \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, ::jfnk::g_timing->start,                    \
+                            ::jfnk::g_timing->stop, 0, __VA_ARGS__);                                      \
+    else                                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                                  \
+  } while (0)
 
 #define JFNK_LAUNCH(kernel, grid, block, stream, ...)                                                     \
   do {                                                                                                    \
@@ -136,6 +146,11 @@ hipError_t launch_norm2(long long n, const T* p, PartSink part, int grid, hipStr
 
 template <class T>
 hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s);
+
+// Whole Newton-GMRES solve in one workgroup with `lds` bytes of LDS
+// (fused_lds_bytes<T>(n, m)); problem kinds as in launch_stencil.
+template <class T>
+hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStream_t s);
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);

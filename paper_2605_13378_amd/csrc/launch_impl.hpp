@@ -148,6 +148,32 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class P, class T>
+static hipError_t fused_for_problem(const FusedArgs<T>& a, size_t lds, hipStream_t s) {
+  const auto k = fused_solve_kernel<P, T>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  JFNK_LAUNCH_SHM(k, dim3(1), dim3(kFusedThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
+  switch (pid) {
+    case kBurgers1D:
+      return fused_for_problem<Burgers1DOp, T>(a, lds, s);
+    case kBurgers2D:
+      return fused_for_problem<Burgers2DOp, T>(a, lds, s);
+    case kGrayScott:
+      return fused_for_problem<GrayScottOp, T>(a, lds, s);
+    case kKerr:
+      return fused_for_problem<KerrOp, T>(a, lds, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 #define JFNK_INSTANTIATE(T, VT)                                                                                  \
   template hipError_t launch_stencil<T, VT>(int, int, bool, bool, const StencilArgs<T, VT>&, const Coefs&, int, \
                                             hipStream_t, int*);                                                 \
@@ -160,6 +186,7 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
   template hipError_t launch_trial<T>(long long, const double*, const T*, double, double*, T*, int, hipStream_t);\
   template hipError_t launch_cast<T>(long long, const double*, T*, int, hipStream_t);                           \
   template hipError_t launch_norm2<T>(long long, const T*, PartSink, int, hipStream_t);                         \
-  template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);
+  template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);                                     \
+  template hipError_t launch_fused_solve<T>(int, const FusedArgs<T>&, size_t, hipStream_t);
 
 }  // namespace jfnk

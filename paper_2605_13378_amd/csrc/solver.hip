@@ -32,8 +32,10 @@ thread_local KernelTiming* g_timing = nullptr;
 
 namespace {
 
-constexpr int kNumProf = 9;
-enum ProfKernel { PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8 };
+constexpr int kNumProf = 10;
+enum ProfKernel {
+  PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8, PK_FUSED = 9
+};
 
 struct ProfRec {
   int kid;
@@ -81,6 +83,9 @@ struct jfnk_solver {
   int* hflags = nullptr;   // pinned, mapped: per-step stop flags written by the device
   int* dflags = nullptr;   // device view of hflags
   std::vector<hipEvent_t> step_ev;
+  size_t lds_max = 0;           // LDS bytes one workgroup may use
+  FusedInfo* dinfo = nullptr;   // single-workgroup solve record (device)
+  FusedInfo* hinfo = nullptr;   // pinned host copy
   bool has_prev = false;
   std::string err;
   bool prof = false;
@@ -391,7 +396,69 @@ struct Impl {
     return JFNK_OK;
   }
 
+  // The whole solve in one workgroup (small problems, FP64/FP32).
+  static bool fused_fits(const jfnk_solver* s, int m) {
+    return std::is_same<T, VT>::value && fused_lds_bytes<T>(s->n, m) <= s->lds_max;
+  }
+
+  static jfnk_status newton_fused(jfnk_solver* s, double* x_user, const jfnk_options& o, jfnk_info* info) {
+    FusedArgs<T> a{};
+    a.nx = s->prob.nx;
+    a.ny = s->prob.ny;
+    a.cells = s->prob.nx * s->prob.ny;
+    a.n = (int)s->n;
+    a.alpha = s->alpha;
+    a.cN = s->cN;
+    a.beta = s->beta;
+    a.coefs = s->coefs;
+    a.b = static_cast<const T*>(s->b);
+    a.x = x_user;
+    a.history = o.history;
+    a.o.m = o.m;
+    a.o.max_restarts = o.max_restarts;
+    a.o.max_newton = o.max_newton;
+    a.o.ls_max = o.ls_max_backtracks;
+    a.o.tol_k = o.tol_krylov;
+    a.o.tol_n = o.tol_newton;
+    a.o.ls_c = o.ls_c;
+    a.o.fd_eps = o.fd_eps;
+    a.o.brk = o.breakdown_tol;
+    a.o.root_eps = std::sqrt(eps_mach(s->prec));
+    a.o.mode = o.mode;
+    a.o.eps_rule = o.eps_rule;
+    a.info = s->dinfo;
+    {
+      ProfScope ps(s, PK_FUSED, 0.0);
+      JFNK_HIP(s, launch_fused_solve<T>(s->pid, a, fused_lds_bytes<T>(s->n, o.m), s->stream));
+    }
+    JFNK_HIP(s, hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(FusedInfo), hipMemcpyDeviceToHost, s->stream));
+    JFNK_HIP(s, hipStreamSynchronize(s->stream));
+    if (s->prof) prof_harvest(s, 0);
+    const FusedInfo& h = *s->hinfo;
+    const int k = std::min(std::max(h.newton_iters, 0), JFNK_MAX_ITERS);
+    info->converged = h.converged;
+    info->newton_iters = k;
+    info->krylov_iters = h.krylov_iters;
+    info->restarts = h.restarts;
+    info->ls_backtracks = h.ls_backtracks;
+    info->ls_failures = h.ls_failures;
+    info->f0_norm = h.f0_norm;
+    for (int i = 0; i < k; ++i) {
+      info->lin_iters[i] = h.lin_iters[i];
+      info->alpha[i] = h.alpha[i];
+    }
+    for (int i = 0; i <= k; ++i) info->rel_res[i] = h.rel_res[i];
+    if (h.status == 0) return JFNK_OK;
+    if (h.status == 4) return JFNK_ERR_NONFINITE;
+    return JFNK_ERR_NOT_CONVERGED;
+  }
+
   static jfnk_status newton(jfnk_solver* s, double* x_user, const jfnk_options& o, jfnk_info* info) {
+    if (o.engine == JFNK_ENGINE_SINGLE_WORKGROUP && !fused_fits(s, o.m)) {
+      s->err = "the single-workgroup engine needs FP64 or FP32 and a problem that fits in LDS";
+      return JFNK_ERR_ARG;
+    }
+    if (o.engine != JFNK_ENGINE_MULTI_KERNEL && fused_fits(s, o.m)) return newton_fused(s, x_user, o, info);
     const long long n = s->n;
     const bool f64 = std::is_same<T, double>::value;
     const int sgrid = stream_grid(s, 2);
@@ -573,7 +640,7 @@ size_t footprint(const jfnk_problem* p, int prec, int m, int cu) {
   bytes += 8 * (size_t)npad * t;                            // w R dx F Ft xw xwt b
   bytes += 3 * (size_t)npad * 8;                            // x64 x64t tmp64
   bytes += 6 * max_blocks(p, cu) * kMaxCols * 8;            // partial sums
-  bytes += sizeof(Ctl);
+  bytes += sizeof(Ctl) + sizeof(FusedInfo);
   return bytes;
 }
 
@@ -599,6 +666,8 @@ void release(jfnk_solver* s) {
     if (p) (void)hipFree(p);
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->hflags) (void)hipHostFree(s->hflags);
+  if (s->dinfo) (void)hipFree(s->dinfo);
+  if (s->hinfo) (void)hipHostFree(s->hinfo);
   for (hipEvent_t e : s->step_ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : s->pool)
@@ -683,6 +752,7 @@ void jfnk_default_options(int precision, jfnk_options* o) {
   o->ls_c = 1e-4;
   o->mode = JFNK_JVP_AD;
   o->eps_rule = JFNK_EPS_PAPER;
+  o->engine = JFNK_ENGINE_AUTO;
   if (precision == JFNK_F64) {
     o->tol_newton = 1e-6;
     o->tol_krylov = 1e-8;
@@ -743,6 +813,11 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
       prop.multiProcessorCount > 0)
     s->cu = prop.multiProcessorCount;
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      s->lds_max = (size_t)lds;
+  }
   jfnk_status st = fill_problem(s);
   const size_t vec_bytes = (size_t)s->npad * s->tsize;
   if (st == JFNK_OK) st = malloc_dev(s, &s->V, (size_t)(m + 1) * s->npad * s->vsize);
@@ -755,6 +830,16 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   s->part_rows = max_blocks(problem, s->cu);
   if (st == JFNK_OK) st = malloc_dev(s, &s->parts, 6 * s->part_rows * kMaxCols * sizeof(double));
   if (st == JFNK_OK) st = malloc_dev(s, &s->ctl, sizeof(Ctl));
+  if (st == JFNK_OK) st = malloc_dev(s, &s->dinfo, sizeof(FusedInfo));
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(FusedInfo), hipHostMallocDefault) != hipSuccess) {
+      s->err = "hipHostMalloc (info) failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hinfo = static_cast<FusedInfo*>(h);
+    }
+  }
   if (st == JFNK_OK) {
     void* h = nullptr;
     if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
@@ -922,7 +1007,8 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
   const jfnk_options& o = *opts;
   if (o.m < 1 || o.m > s->m || o.max_newton < 0 || o.max_newton > JFNK_MAX_ITERS || o.max_restarts < 0 ||
       o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
-      (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0)) {
+      (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0) ||
+      o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP) {
     s->err = "invalid options";
     return JFNK_ERR_ARG;
   }

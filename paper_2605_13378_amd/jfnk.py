@@ -21,10 +21,11 @@ PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3}
 PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
+ENGINES = {"auto": 0, "multi": 1, "single": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
           5: "breakdown", 6: "not_converged"}
 PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
-                   "cycle_start": 7, "newton_trial": 8}
+                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9}
 
 
 class Problem(ctypes.Structure):
@@ -40,7 +41,7 @@ class Options(ctypes.Structure):
                 ("tol_krylov", ctypes.c_double), ("tol_newton", ctypes.c_double), ("ls_c", ctypes.c_double),
                 ("fd_eps", ctypes.c_double), ("breakdown_tol", ctypes.c_double),
                 ("mode", ctypes.c_int), ("eps_rule", ctypes.c_int),
-                ("history", ctypes.c_void_p)]
+                ("history", ctypes.c_void_p), ("engine", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -168,6 +169,8 @@ def default_options(precision: str = "f64", **kw) -> Options:
             val = MODES[val]
         elif key == "eps_rule":
             val = EPS_RULES[val]
+        elif key == "engine":
+            val = ENGINES[val]
         elif key == "history":
             val = None if val is None else val.data_ptr()
         setattr(o, key, val)

@@ -36,16 +36,26 @@ def solver(spec, prec, xp, src, m=30):
     return s
 
 
-def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", krylov_slack=None, **kw):
+def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", krylov_slack=None, engine="multi",
+                   **kw):
     p = Problem.from_spec(spec)
     o = NewtonOptions.for_precision(prec, mode=mode, eps_rule=eps_rule, **kw)
     x_ref, info_ref = newton_solve(p, xp, o, source=src, x0=x0, record=True)
     s = solver(spec, prec, xp, src, m=o.m)
     start = xp if x0 is None else x0
+    s.profile_reset()
+    s.profile(True)
     x_gpu, info = s.newton_solve(dev(start, wdtype("f64")), history=True, mode=mode, eps_rule=eps_rule,
                                  m=o.m, tol_newton=o.tol_newton, tol_krylov=o.tol_krylov,
                                  max_newton=o.max_newton, max_restarts=o.max_restarts,
-                                 breakdown_tol=o.breakdown_tol)
+                                 breakdown_tol=o.breakdown_tol, engine=engine)
+    prof = s.profile_read()
+    s.profile(False)
+    # the engine asked for is the one that ran
+    if engine == "single":
+        assert prof["fused_solve"]["launches"] == 1 and prof["residual"]["launches"] == 0, prof
+    elif engine == "multi":
+        assert prof["fused_solve"]["launches"] == 0 and prof["residual"]["launches"] >= 1, prof
     assert info["newton_iters"] == info_ref.newton_iters, (info, info_ref)
     assert info["converged"] == info_ref.converged
     hist = host(info["history"])
@@ -62,9 +72,47 @@ def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", kr
     return info, info_ref
 
 
-def test_newton_burgers1d_config_f64_ad():
+@pytest.mark.parametrize("engine", ["multi", "single"])
+def test_newton_burgers1d_config_f64_ad(engine):
     spec, xp, _ = W.config("burgers1d")
-    compare_newton(spec, xp, None, "f64", "ad", 1e-12, tol_newton=1e-10, tol_krylov=1e-12)
+    compare_newton(spec, xp, None, "f64", "ad", 1e-12, tol_newton=1e-10, tol_krylov=1e-12, engine=engine)
+
+
+# Single-workgroup engine (the whole solve in one launch, vectors in LDS) on
+# problems small enough for it, at the same per-iterate bounds as the
+# multi-kernel path.
+@pytest.mark.parametrize("kind,nx,ny,prec,mode,rule,tol", [
+    ("burgers1d", 256, None, "f32", "ad", "paper", 1e-5),
+    ("burgers1d", 256, None, "f64", "fd", "paper", 1e-7),
+    ("burgers1d", 200, None, "f64", "fd", "normalized", 1e-7),
+    ("grayscott", 16, 12, "f64", "ad", "paper", 1e-12),
+    ("grayscott", 16, 16, "f32", "ad", "paper", 1e-5),
+    ("burgers2d", 12, 10, "f64", "ad", "paper", 1e-12),
+    ("burgers2d", 12, 10, "f64", "fd", "paper", 1e-7),
+])
+def test_newton_single_workgroup(kind, nx, ny, prec, mode, rule, tol):
+    if kind == "burgers1d":
+        spec, xp, src = W.burgers1d_spec(nx), W.burgers1d_initial(nx, 0), None
+    else:
+        spec, xp, src = case(kind, nx, ny)
+    compare_newton(spec, xp, src, prec, mode, tol, eps_rule=rule, engine="single")
+
+
+def test_single_workgroup_statuses_and_fallback():
+    spec, xp, src = case("grayscott", 16, 12)
+    s = solver(spec, "f64", xp, src)
+    x_bad = xp.copy()
+    x_bad[17] = np.nan
+    _, info = s.newton_solve(dev(x_bad, wdtype("f64")), engine="single")
+    assert info["status"] == "nonfinite"
+    _, info = s.newton_solve(dev(xp, wdtype("f64")), tol_newton=1e-15, max_newton=1, engine="single")
+    assert info["status"] == "not_converged" and info["newton_iters"] == 1
+    big, xb, _ = case("grayscott", 64, 64)
+    sb = solver(big, "f64", xb, None)
+    from paper_2605_13378_amd import JfnkError
+
+    with pytest.raises(JfnkError):
+        sb.newton_solve(dev(xb, wdtype("f64")), engine="single")  # does not fit in LDS
 
 
 @pytest.mark.parametrize("kind,nx,ny", [("grayscott", 64, 64), ("grayscott", 130, 37), ("burgers2d", 48, 40),
@@ -74,8 +122,9 @@ def test_newton_f64_ad(kind, nx, ny):
     compare_newton(spec, xp, src, "f64", "ad", 1e-12)
 
 
+@pytest.mark.parametrize("engine", ["multi", "single"])
 @pytest.mark.parametrize("cpw,chi,tol,slack", [(64.0, 0.3, 1e-10, None), (32.0, 1.0, 1e-10, 0.1)])
-def test_newton_kerr_f64_ad(cpw, chi, tol, slack):
+def test_newton_kerr_f64_ad(cpw, chi, tol, slack, engine):
     # well-posed small cases (GMRES(30) converges in ~30 steps).  -Lap - k0^2 eps
     # is indefinite and Newton runs from E = 0, so rounding-order differences of
     # the dot products grow by the condition number (~1e2..1e3 here) per solve:
@@ -84,7 +133,8 @@ def test_newton_kerr_f64_ad(cpw, chi, tol, slack):
     # few Arnoldi steps between cycles.
     spec = dict(W.kerr_spec(12, chi3=chi, cells_per_wavelength=cpw, eps_im=0.05), ny=10)
     src = W.kerr_gaussian_source(12, amp=1.0, sigma=2.0, ny=10)
-    compare_newton(spec, np.zeros(2 * 12 * 10), src, "f64", "ad", tol, max_newton=20, krylov_slack=slack)
+    compare_newton(spec, np.zeros(2 * 12 * 10), src, "f64", "ad", tol, max_newton=20, krylov_slack=slack,
+                   engine=engine)
 
 
 @pytest.mark.parametrize("kind,nx,ny", [("grayscott", 64, 64), ("burgers2d", 48, 40), ("burgers1d", 256, None)])
@@ -109,11 +159,12 @@ def test_fd_and_ad_reach_the_same_root_f64():
     assert float(np.linalg.norm(host(xa) - host(xf))) <= 2 * 1e-8 * ia["f0_norm"]
 
 
-def test_line_search_sequence_matches():
+@pytest.mark.parametrize("engine", ["multi", "single"])
+def test_line_search_sequence_matches(engine):
     spec = W.burgers1d_spec(24, nu=0.05, dt=1.0)
     xp = 1.0 + 2.0 * np.sin(2 * np.pi * np.arange(24) / 24)
     info, ref = compare_newton(spec, xp, None, "f64", "ad", 1e-12, tol_newton=1e-8, tol_krylov=1e-10,
-                               max_newton=40)
+                               max_newton=40, engine=engine)
     assert info["ls_backtracks"] == ref.ls_backtracks > 0
     assert info["alphas"] == ref.alphas
 
