@@ -46,7 +46,7 @@ def kernel_sources_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("common.hpp", "krylov.hpp", "problems.hpp", "stencil.hpp"):
+    for f in ("common.hpp", "krylov.hpp", "problems.hpp", "stencil.hpp", "launch.hpp", "launch_impl.hpp"):
         with open(os.path.join(HERE, "paper_2605_13378_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -177,6 +177,105 @@ def latency_c1(torch, repeats, seeds):
     return out
 
 
+def completion_c3(torch, seeds, steps=10, n=2048, modes=("ad", "fd"), precisions=("f32", "f16s")):
+    """2D Burgers n^2 (Crank-Nicolson, nu 1e-3, dt 5e-4), `steps` implicit steps
+    from each seed's random-Fourier field; AD vs FD (paper step), FP32 and FP16S
+    with FP64 Givens/update/merit.  A step fails when its final relative
+    residual is non-finite or above 100 tol_N; a run fails on a non-finite step
+    or when more than 20% of its steps fail.  Completion = runs not failed."""
+    from paper_2605_13378_amd import Solver
+
+    import workloads as W
+
+    spec = W.burgers2d_spec(n)
+    tol_n = 1e-4
+    out = {"workload": f"burgers2d_{n}_cn_{steps}steps", "seeds": seeds, "steps": steps}
+    inits = [W.burgers2d_initial(n, sd) for sd in range(seeds)]
+    for prec in precisions:
+        s = Solver(spec, prec, m=30)
+        for mode in modes:
+            ok_runs = 0
+            failed_steps = 0
+            solve_s = 0.0
+            solves = 0
+            newton = 0
+            krylov = 0
+            worst = 0.0
+            for sd in range(seeds):
+                x = torch.tensor(inits[sd], dtype=torch.float64, device="cuda")
+                bad = 0
+                nonfinite = False
+                for _ in range(steps):
+                    s.set_previous(x)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    xn, info = s.newton_solve(x, mode=mode, eps_rule="paper")
+                    solve_s += time.perf_counter() - t1
+                    solves += 1
+                    newton += info["newton_iters"]
+                    krylov += info["krylov_iters"]
+                    last = info["rel_res"][-1] if info["rel_res"] else float("nan")
+                    if info["status"] == "nonfinite" or not math.isfinite(last):
+                        nonfinite = True
+                        break
+                    worst = max(worst, last)
+                    if not last <= 100 * tol_n:
+                        bad += 1
+                    x = xn
+                failed_steps += bad
+                if not nonfinite and bad <= 0.2 * steps:
+                    ok_runs += 1
+            out[f"{prec}-{mode}"] = dict(completion=round(ok_runs / seeds, 4), runs_ok=ok_runs,
+                                         failed_steps=failed_steps, solves=solves,
+                                         solves_per_s=round(solves / solve_s, 2) if solve_s > 0 else None,
+                                         newton_per_solve=round(newton / max(1, solves), 3),
+                                         krylov_per_newton=round(krylov / max(1, newton), 2),
+                                         worst_final_rel_res=worst)
+            log(f"[bench] C3 {prec}-{mode}: {out[f'{prec}-{mode}']}")
+        s.close()
+    return out
+
+
+def kerr_solver(torch, prec, chi3=0.1, eps_im=0.0, n=1024):
+    from paper_2605_13378_amd import Solver
+
+    import workloads as W
+
+    spec = W.kerr_spec(n, chi3=chi3, eps_im=eps_im)
+    src = W.kerr_gaussian_source(n)
+    s = Solver(spec, prec, m=30)
+    s.set_previous(None, torch.tensor(src, dtype=torch.float64, device="cuda"))
+    return s, spec
+
+
+def kerr_newton(torch, max_newton=50):
+    """Helmholtz-Kerr 1024^2 from E = 0: Newton completion per precision
+    (complex64 / complex128), chi3 and loss, AD vs FD.  Unpreconditioned
+    GMRES(30) on this indefinite operator is expected to stagnate."""
+    import workloads as W
+
+    out = {}
+    n_unk = 2 * 1024 * 1024
+    x0 = torch.zeros(n_unk, dtype=torch.float64, device="cuda")
+    for prec in ("f32", "f64"):
+        for chi3 in (0.01, 0.1):
+            for eps_im in (0.0, -0.05):
+                s, _ = kerr_solver(torch, prec, chi3=chi3, eps_im=eps_im)
+                for mode in ("ad", "fd"):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    _, info = s.newton_solve(x0, mode=mode, eps_rule="paper", max_newton=max_newton)
+                    el = time.perf_counter() - t1
+                    key = f"{prec}-chi{chi3}-{'lossy' if eps_im else 'lossless'}-{mode}"
+                    out[key] = dict(converged=info["converged"], status=info["status"],
+                                    newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                                    final_rel_res=info["rel_res"][-1] if info["rel_res"] else None,
+                                    seconds=round(el, 3))
+                    log(f"[bench] C4 {key}: {out[key]}")
+                s.close()
+    return out
+
+
 def serving_pass(batch, reqs, inputs, rate_scale, saturate):
     """Feed `reqs` to `batch` (Poisson arrivals scaled by 1/rate_scale, or all at
     once) and return solves/s and arrival-to-result latency percentiles."""
@@ -300,6 +399,10 @@ def main():
     ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
     ap.add_argument("--no-latency", action="store_true", help="skip the 1D Burgers N=256 latency rows")
+    ap.add_argument("--kerr-newton", action="store_true",
+                    help="run the Helmholtz-Kerr 1024^2 Newton completion rows (minutes)")
+    ap.add_argument("--completion-seeds", type=int, default=64,
+                    help="seeds of the 2D Burgers 2048^2 10-step completion sweep (0: skip)")
     ap.add_argument("--latency-repeats", type=int, default=1000)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -405,6 +508,15 @@ def main():
         sb.close()
     del scrub
 
+    # ---- JVP bandwidth on the Helmholtz-Kerr 1024^2 grid (complex64 / complex128)
+    jvpkerr = {}
+    for pr in (() if args.no_jvp_rows else ("f32", "f64")):
+        sk, spec_k = kerr_solver(torch, pr)
+        for mode in ("ad", "fd"):
+            jvpkerr[f"{pr}-{mode}"] = jvp_bandwidth(sk, torch, W.n_unknowns(spec_k), pr, mode)
+            log(f"[bench] jvp kerr 1024^2 {pr}-{mode}: {jvpkerr[f'{pr}-{mode}']}")
+        sk.close()
+
     # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
     variants = {}
     if not args.no_variants:
@@ -431,6 +543,16 @@ def main():
                 log(f"[bench] variant {pr}-{mode}: {variants[f'{pr}-{mode}']}")
             if sv is not s:
                 sv.close()
+
+    c3 = None
+    if args.completion_seeds > 0:
+        log(f"[bench] completion sweep: 2D Burgers 2048^2, 10 steps, {args.completion_seeds} seeds")
+        c3 = completion_c3(torch, args.completion_seeds)
+
+    c4 = None
+    if args.kerr_newton:
+        log("[bench] Helmholtz-Kerr 1024^2 Newton rows")
+        c4 = kerr_newton(torch)
 
     c1 = None
     if not args.no_latency:
@@ -472,9 +594,12 @@ def main():
         "profiled_pass_ms_per_step": round(1e3 * p_el / args.steps, 4),
         "jvp": jvp,
         "jvp_burgers2d_2048": jvp2048,
+        "jvp_kerr_1024": jvpkerr,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
         "latency_burgers1d_256": c1,
+        "completion_burgers2d_2048": c3,
+        "kerr_newton_1024": c4,
         "serving": serving,
         "cpu_baseline": cpu,
     }

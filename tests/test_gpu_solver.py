@@ -249,6 +249,59 @@ def test_full_size_grayscott_f64_ad_per_iterate():
     compare_newton(spec, xp, src, "f64", "ad", 1e-12)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_full_size_burgers2d_two_steps_f32_ad(seed):
+    """2D Burgers 2048^2, Crank-Nicolson, FP32 AD: two implicit steps, every
+    Newton iterate of both against the oracle (each side steps from its own
+    previous result).
+
+    The FP32 residual cannot fall below its rounding floor: x - b cancels to
+    ~5e-4 per component while x and b carry 2^-24 relative rounding, so
+    ||F_fp32(x*)|| ~ 2^-24 ||x|| (4e-5 of ||F0|| here, against the oracle's
+    FP64 2.8e-6).  The relative-residual bound is 1e-5 plus twice that floor;
+    the iterates themselves match at 1e-5."""
+    from oracle import NewtonOptions as NO
+
+    spec, xp, _ = W.config("burgers2d", seed=seed)
+    p = Problem.from_spec(spec)
+    o = NO.for_precision("f32", mode="ad")
+    s = solver(spec, "f32", xp, None)
+    x_ref_prev, x_gpu_prev = xp, xp
+    for step in range(2):
+        x_ref, ref = newton_solve(p, x_ref_prev, o, record=True)
+        s.set_previous(dev(x_gpu_prev, wdtype("f64")))
+        x_gpu, info = s.newton_solve(dev(x_gpu_prev, wdtype("f64")), history=True, mode="ad")
+        assert info["converged"] and ref.converged
+        assert info["newton_iters"] == ref.newton_iters, (step, info, ref)
+        hist = host(info["history"])
+        for k, (r_gpu, r_ref) in enumerate(zip(info["rel_res"], ref.rel_res)):
+            xr = ref.iterates[k]
+            floor = 2 * 2.0 ** -24 * np.linalg.norm(xr) / ref.f0_norm
+            assert abs(r_gpu - r_ref) <= 1e-5 + floor, (step, k, r_gpu, r_ref, floor)
+            assert np.linalg.norm(hist[k] - xr) <= 1e-5 * np.linalg.norm(xr), (step, k)
+        for a, b in zip(info["lin_iters"], ref.lin_iters):
+            assert abs(a - b) <= 2
+        x_ref_prev, x_gpu_prev = x_ref, host(x_gpu)
+
+
+def test_full_size_burgers2d_f16s_ad():
+    """2048^2 FP16-stored basis: the result meets the Newton tolerance when its
+    residual is evaluated by the oracle in FP64, and lies within the
+    tolerance-implied distance of the oracle's root."""
+    from oracle import NewtonOptions as NO
+
+    spec, xp, _ = W.config("burgers2d", seed=2)
+    p = Problem.from_spec(spec)
+    o = NO.for_precision("f32", mode="ad")
+    x_ref, ref = newton_solve(p, xp, o)
+    s = solver(spec, "f16s", xp, None)
+    x, info = s.newton_solve(dev(xp, wdtype("f64")), mode="ad")
+    assert info["converged"]
+    r = np.linalg.norm(residual(p, host(x), xp))
+    assert r <= 1.01 * o.tol_newton * ref.f0_norm, (r, ref.f0_norm)
+    assert np.linalg.norm(host(x) - x_ref) <= 2 * o.tol_newton * ref.f0_norm + 1e-6 * np.linalg.norm(x_ref)
+
+
 @pytest.mark.parametrize("kind,nx,ny", [("grayscott", 64, 64), ("burgers2d", 48, 40), ("grayscott", 1024, 1024)])
 @pytest.mark.parametrize("mode", ["ad", "fd"])
 def test_newton_f16s(kind, nx, ny, mode):

@@ -116,20 +116,24 @@ def burgers2d_initial(n: int = 2048, seed: int = 0, modes: int = 32, kmax: int =
     rng = np.random.default_rng(seed)
     h = 2.0 * np.pi / n
     coord = np.arange(n) * h
-    X = coord[None, :]
-    Y = coord[:, None]
     comps = []
     for _ in range(2):
-        f = np.zeros((n, n))
-        for _m in range(modes):
+        # cos(kx x + ky y + phi) = cos(kx x + phi) cos(ky y) - sin(kx x + phi) sin(ky y):
+        # the field is a rank-2*modes product (rows y, columns x)
+        A = np.empty((n, 2 * modes))
+        B = np.empty((2 * modes, n))
+        for m in range(modes):
             while True:
                 kx, ky = (int(t) for t in rng.integers(-kmax, kmax + 1, size=2))
                 if kx != 0 or ky != 0:
                     break
             amp = rng.standard_normal() / math.hypot(kx, ky)
             phi = rng.uniform(0.0, 2.0 * np.pi)
-            f += amp * np.cos(kx * X + ky * Y + phi)
-        comps.append(f)
+            A[:, 2 * m] = np.cos(ky * coord)
+            A[:, 2 * m + 1] = -np.sin(ky * coord)
+            B[2 * m] = amp * np.cos(kx * coord + phi)
+            B[2 * m + 1] = amp * np.sin(kx * coord + phi)
+        comps.append(A @ B)
     u, v = comps
     ke = 0.5 * np.mean(u * u + v * v)
     s = math.sqrt(energy / ke)
