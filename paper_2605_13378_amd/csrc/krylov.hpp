@@ -167,13 +167,14 @@ template <class T, class VT, int KMAX, int VEC, int MODE>
 __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
-  if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
   const long long step = (long long)gridDim.x * blockDim.x * VEC;
   long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  // the first chunk's loads go out before the coefficient reduction
+  // the first chunk's loads go out before the stop check and the coefficient
+  // reduction (in-bounds either way; unused if the cycle has stopped)
   T w[VEC];
   T vv[KMAX][VEC];
   if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
+  if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
 
   __shared__ double tot[KMAX + 1];
   __shared__ double s_sig;
@@ -378,34 +379,53 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   __shared__ double y[kMaxM];
   __shared__ double lastcol[kMaxM + 1];
   __shared__ double lastgr;
+  __shared__ int flags[kMaxM + 1];
+  __shared__ double R[kMaxM * kMaxM];  // columns l < k of the rotated H (rows i <= l), column-major
+  __shared__ double gr[kMaxM];
+  __shared__ int s_k;
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  // stop flags of the cycle, read by all threads at once
+  if (a.jmax >= 0 && tid <= a.jmax) flags[tid] = ctl->done_col[tid];
+  __syncthreads();
   // columns completed: stop at the first column whose Givens update ended the cycle
-  int k = 0;
-  bool pending = false;
-  if (a.jmax >= 0 && ctl->done_col[0] == kRunning) {
-    k = a.jmax + 1;
-    for (int c = 0; c < a.jmax; ++c)
-      if (ctl->done_col[c + 1] != kRunning) {
-        k = c + 1;
-        break;
-      }
-    pending = (k == a.jmax + 1);
-  }
-  if (pending) {
-    const GivensOut g = finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
-    if (threadIdx.x == 0) lastgr = g.gr;
+  if (tid == 0) {
+    int kk = 0;
+    if (a.jmax >= 0 && flags[0] == kRunning) {
+      kk = a.jmax + 1;
+      for (int c = 0; c < a.jmax; ++c)
+        if (flags[c + 1] != kRunning) {
+          kk = c + 1;
+          break;
+        }
+    }
+    s_k = kk;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // block 0 may just have written column k-1 of H: every block uses the
-    // column it computed itself for that one
-    const int ld = kMaxM + 1;
+  const int k = s_k;
+  const bool pending = a.jmax >= 0 && k == a.jmax + 1;
+  if (pending) {
+    const GivensOut g = finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
+    if (tid == 0) lastgr = g.gr;
+  }
+  // block 0 may just have written column k-1 of H: every block uses the
+  // column it computed itself for that one; the others are staged in LDS
+  const int ld = kMaxM + 1;
+  const int kc = pending ? k - 1 : k;  // columns read from the control block
+  for (int idx = tid; idx < kc * kMaxM; idx += nt) {
+    const int l = idx / kMaxM, i = idx % kMaxM;
+    if (i <= l) R[l * kMaxM + i] = ctl->H[l * ld + i];
+  }
+  if (tid < k) gr[tid] = (pending && tid == k - 1) ? 0.0 : ctl->gr[tid];
+  __syncthreads();
+  if (tid == 0) {
     for (int i = k - 1; i >= 0; --i) {
-      double s = (pending && i == k - 1) ? lastgr : ctl->gr[i];
+      double s = (pending && i == k - 1) ? lastgr : gr[i];
       for (int l = i + 1; l < k; ++l) {
-        const double r = (pending && l == k - 1) ? lastcol[i] : ctl->H[l * ld + i];
+        const double r = (pending && l == k - 1) ? lastcol[i] : R[l * kMaxM + i];
         s -= r * y[l];
       }
-      const double d = (pending && i == k - 1) ? lastcol[i] : ctl->H[i * ld + i];
+      const double d = (pending && i == k - 1) ? lastcol[i] : R[i * kMaxM + i];
       y[i] = s / d;
     }
     if (blockIdx.x == 0) ctl->k = k;

@@ -200,22 +200,6 @@ struct Tile {
 template <class P, class T, class VT, int VEC, int RY, int OP, bool WITHF, int KDOT>
 __global__ void __launch_bounds__(256)
 stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
-  // Arnoldi mode: leave at once if the cycle has already stopped
-  if constexpr (OP != OP_RES) {
-    if (a.ctl != nullptr) {
-      const int j = a.arn_j;
-      const int prev = a.ctl->done_col[j > 0 ? j - 1 : 0];
-      if (prev != kRunning) {
-        // carry the state forward so that the flags stay monotone (later
-        // kernels only look at the state after their own column)
-        if (j > 0 && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-          a.ctl->done_col[j] = prev;
-          if (a.host_flags) a.host_flags[j - 1] = prev;
-        }
-        return;
-      }
-    }
-  }
   constexpr int NF = P::NF;
   constexpr int RC = P::kDim2 ? RY : 1;
   const auto k = P::template make<T>(coefs);
@@ -243,6 +227,31 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   Tile<P, T, VEC, RY> X;
   Tile<P, T, VEC, RY> Vt;
   int col0 = 0, r0 = 0;
+  // the first tile's loads go out before the stop check and the prologue
+  // reductions (in-bounds either way; unused if the cycle has stopped)
+  if (t_begin < t_end) {
+    tile_origin(t_begin, col0, r0);
+    const int cc = col0 < nx ? col0 : 0;
+    X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
+    if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
+  }
+
+  // Arnoldi mode: leave at once if the cycle has already stopped
+  if constexpr (OP != OP_RES) {
+    if (a.ctl != nullptr) {
+      const int j = a.arn_j;
+      const int prev = a.ctl->done_col[j > 0 ? j - 1 : 0];
+      if (prev != kRunning) {
+        // carry the state forward so that the flags stay monotone (later
+        // kernels only look at the state after their own column)
+        if (j > 0 && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+          a.ctl->done_col[j] = prev;
+          if (a.host_flags) a.host_flags[j - 1] = prev;
+        }
+        return;
+      }
+    }
+  }
 
   double vscale = 1.0;
   if constexpr (OP != OP_RES) {
@@ -280,13 +289,8 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
 
-  for (int t = t_begin; t < t_end; ++t) {
-    {
-      tile_origin(t, col0, r0);
-      const int cc = col0 < nx ? col0 : 0;
-      X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
-      if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
-    }
+  // one tile whose loads have been issued (X, Vt at col0, r0)
+  auto process = [&]() {
     const bool colok = col0 < nx;
     const int cc = colok ? col0 : 0;
     X.exchange(col0, nx, lane);
@@ -401,6 +405,15 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         }
       }
     }
+  };
+
+  if (t_begin < t_end) process();
+  for (int t = t_begin + 1; t < t_end; ++t) {
+    tile_origin(t, col0, r0);
+    const int cc = col0 < nx ? col0 : 0;
+    X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
+    if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
+    process();
   }
 
   if constexpr (OP == OP_RES) {
