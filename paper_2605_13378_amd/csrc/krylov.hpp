@@ -149,6 +149,10 @@ struct KArgs {
   PartSink out;       // this pass's partial sums
 };
 
+// Loads w and the K basis chunks at element i.  The caller zero-fills vv once:
+// chunks k >= K are never loaded and stay zero, so the arithmetic runs over
+// all KMAX slots without per-slot conditions (a zero coefficient times a zero
+// element leaves every sum unchanged, exactly).
 template <class T, class VT, int KMAX, int VEC>
 __device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int K, T (&w)[VEC], T (&vv)[KMAX][VEC]) {
   load_vec<T, VEC>(a.w + i, w);
@@ -173,6 +177,10 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   // reduction (in-bounds either way; unused if the cycle has stopped)
   T w[VEC];
   T vv[KMAX][VEC];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
   if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
   if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
 
@@ -235,8 +243,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
       for (int e = 0; e < VEC; ++e) {
         T x = w[e];
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K) x = x - coef[k] * vv[k][e];
+        for (int k = 0; k < KMAX; ++k) x = x - coef[k] * vv[k][e];
         wn[e] = x;
       }
       if constexpr (MODE == PASS_B) {
@@ -446,12 +453,15 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
     }
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
+      VT t[VEC];
       if (c < k) {
-        VT t[VEC];
         load_vec<VT, VEC>(a.V + c * a.vstride + i, t);
+      } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) d[e] = d[e] + coef[c] * to_c<T>(t[e]);
+        for (int e = 0; e < VEC; ++e) t[e] = VT(0);
       }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) d[e] = d[e] + coef[c] * to_c<T>(t[e]);
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[0] += (double)d[e] * (double)d[e];
