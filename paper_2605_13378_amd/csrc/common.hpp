@@ -198,6 +198,8 @@ struct Ctl {
   int k;             // Arnoldi columns completed in the current cycle (written by the V y kernel)
   int m;             // restart length of the current solve
   int first;         // 1 until the first cycle start has fixed ||rhs||
+  int k_last;        // k of the last V y update (kept across the next cycle start)
+  int k_last_state;  // stop state after that update's last column (kRunning if k_last == 0)
   int pad0;
   int done_col[kMaxM + 2];
   double bnorm;      // ||rhs||

@@ -411,9 +411,13 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   __syncthreads();
   const int k = s_k;
   const bool pending = a.jmax >= 0 && k == a.jmax + 1;
+  __shared__ int lastdone;
   if (pending) {
     const GivensOut g = finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
-    if (tid == 0) lastgr = g.gr;
+    if (tid == 0) {
+      lastgr = g.gr;
+      lastdone = g.done;
+    }
   }
   // block 0 may just have written column k-1 of H: every block uses the
   // column it computed itself for that one; the others are staged in LDS
@@ -435,7 +439,11 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
       const double d = (pending && i == k - 1) ? lastcol[i] : R[i * kMaxM + i];
       y[i] = s / d;
     }
-    if (blockIdx.x == 0) ctl->k = k;
+    if (blockIdx.x == 0) {
+      ctl->k = k;
+      ctl->k_last = k;
+      ctl->k_last_state = k == 0 ? kRunning : (pending ? lastdone : flags[k]);
+    }
   }
   __syncthreads();
   T coef[KMAX];

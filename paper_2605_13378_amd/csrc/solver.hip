@@ -324,6 +324,10 @@ struct Impl {
     volatile int* flags = reinterpret_cast<volatile int*>(s->hflags);
     JFNK_HIP(s, launch_ctl_begin(s->ctl, tol, brk, m, s->stream));
     bool updated = false;
+    // The V y update that ends a cycle is read back together with the next
+    // cycle's start (one synchronization per cycle): its k and stop state sit
+    // in fields the cycle start leaves alone.
+    bool pending_vy = false;
     for (int cycle = 0;; ++cycle) {
       const T* wr = nullptr;
       s->cur_step = -1;
@@ -340,7 +344,22 @@ struct Impl {
       JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->n, fp16 ? 1 : 0, s->stream));
       if (fp16) JFNK_HIP(s, launch_store_basis0<T, VT>(s->npad, w, basis(s, 0), s->ctl, sgrid, s->stream));
       JFNK_TRY(sync_read_ctl(s));
-      if (s->prof) prof_harvest(s, 0);
+      if (pending_vy) {
+        pending_vy = false;
+        const int k = s->hctl->k_last;
+        if (s->prof) {
+          for (ProfRec& r : s->recs)
+            if (r.kid == PK_VY) r.bytes = (double)s->n * (k * sizeof(VT) + (cycle == 1 ? 1.0 : 2.0) * sizeof(T));
+          prof_harvest(s, k);
+        }
+        go.iters += k;
+        if (k > 0 && s->hctl->k_last_state == kNonfinite) {
+          go.nonfinite = true;
+          break;
+        }
+      } else if (s->prof) {
+        prof_harvest(s, 0);
+      }
       if (cycle == 0) go.bnorm = s->hctl->bnorm;
       go.true_res = s->hctl->beta;
       const int d0 = s->hctl->done_col[0];
@@ -392,18 +411,7 @@ struct Impl {
         JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
       }
       updated = true;
-      JFNK_TRY(sync_read_ctl(s));
-      const int k = s->hctl->k;
-      if (s->prof) {
-        for (ProfRec& r : s->recs)
-          if (r.kid == PK_VY) r.bytes = (double)s->n * (k * sizeof(VT) + (cycle == 0 ? 1.0 : 2.0) * sizeof(T));
-        prof_harvest(s, k);
-      }
-      go.iters += k;
-      if (k > 0 && s->hctl->done_col[k] == kNonfinite) {
-        go.nonfinite = true;
-        break;
-      }
+      pending_vy = true;
     }
     if (!updated) JFNK_HIP(s, launch_fill_zero<T>(s->npad, dxi, sgrid, s->stream));
     return JFNK_OK;
