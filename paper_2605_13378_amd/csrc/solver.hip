@@ -82,7 +82,6 @@ struct jfnk_solver {
   Ctl* hctl = nullptr;     // pinned host mirror of the control block header
   int* hflags = nullptr;   // pinned, mapped: per-step stop flags written by the device
   int* dflags = nullptr;   // device view of hflags
-  std::vector<hipEvent_t> step_ev;
   size_t lds_max = 0;           // LDS bytes one workgroup may use
   FusedInfo* dinfo = nullptr;   // single-workgroup solve record (device)
   FusedInfo* hinfo = nullptr;   // pinned host copy
@@ -204,6 +203,23 @@ EpsSpec eps_spec(const jfnk_solver* s, double fixed, int rule, const double* vno
   e.xnorm2 = &s->ctl->xnorm2;
   e.vnorm2 = rule == JFNK_EPS_NORMALIZED ? vnorm2 : nullptr;
   return e;
+}
+
+// Spin until the device has written a step's stop flag into mapped host
+// memory (the host resets it to -1 before launching the writer).  Returns
+// false if the stream went idle without writing it or reported an error; the
+// caller then stops the cycle and its next synchronization reads the device
+// state (and reports any error).
+bool wait_flag(jfnk_solver* s, volatile int* flags, int c) {
+  for (unsigned it = 1;; ++it) {
+    if (flags[c] != -1) return true;
+    if ((it & 1023u) == 0) {
+      const hipError_t q = hipStreamQuery(s->stream);
+      if (q == hipSuccess) return flags[c] != -1;
+      if (q != hipErrorNotReady) return false;
+    }
+    __builtin_ia32_pause();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -375,8 +391,9 @@ struct Impl {
       go.cycles += 1;
       // Arnoldi steps back to back; the Givens update of column j runs in the
       // prologue of step j+1's JVP and reports its stop flag to mapped host
-      // memory.  After enqueueing step j the host waits for step j-1, whose
-      // JVP settled column j-2: at most two enqueued steps are skipped.
+      // memory.  After enqueueing step j the host waits until step j-1's JVP
+      // has published column j-2's flag: at most two enqueued steps are
+      // skipped, and no marker is placed in the stream between steps.
       int jmax = -1;
       for (int j = 0; j < m; ++j) {
         s->cur_step = j;
@@ -396,11 +413,7 @@ struct Impl {
           JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, cgs_grid(s, K), s->stream));
         }
         jmax = j;
-        JFNK_HIP(s, hipEventRecord(s->step_ev[j], s->stream));
-        if (j >= 2) {
-          JFNK_HIP(s, hipEventSynchronize(s->step_ev[j - 1]));
-          if (flags[j - 2] != kRunning) break;
-        }
+        if (j >= 2 && (!wait_flag(s, flags, j - 2) || flags[j - 2] != kRunning)) break;
       }
       s->cur_step = -1;
       flags[jmax] = -1;
@@ -689,8 +702,6 @@ void release(jfnk_solver* s) {
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->dinfo) (void)hipFree(s->dinfo);
   if (s->hinfo) (void)hipHostFree(s->hinfo);
-  for (hipEvent_t e : s->step_ev)
-    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : s->pool)
     if (e) (void)hipEventDestroy(e);
   for (ProfRec& r : s->recs) {
@@ -885,14 +896,6 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
       }
       s->dflags = static_cast<int*>(d);
     }
-  }
-  if (st == JFNK_OK) {
-    s->step_ev.assign(kMaxM, nullptr);
-    for (auto& e : s->step_ev)
-      if (st == JFNK_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-        s->err = "hipEventCreate failed";
-        st = JFNK_ERR_HIP;
-      }
   }
   if (st == JFNK_OK && hipStreamSynchronize(s->stream) != hipSuccess) {
     s->err = "stream synchronize after set-up failed";
