@@ -36,11 +36,10 @@ CONFIG_NAME = "grayscott-1024x1024-backward-euler"
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarized in profiles/, valid only for the
 # kernel sources they were taken with (hash of the device headers).
 MEASURED_TRAFFIC = {
-    "jvp_ad": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.933},
-    "cgs_b": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.852},
-    "cgs_c": {"sources": "d9aa5fd88ceee3e8", "ratio": 0.851},
+    "jvp_ad": {"sources": "c2716c358f16987c", "ratio": 0.954},
+    "cgs_b": {"sources": "c2716c358f16987c", "ratio": 0.891},
+    "cgs_c": {"sources": "c2716c358f16987c", "ratio": 0.888},
 }
-
 
 def kernel_sources_hash() -> str:
     import hashlib
