@@ -167,6 +167,27 @@ __device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int
   }
 }
 
+// Dot product of one thread's VEC-element chunks, returned in FP64 for the
+// FP64 accumulation across chunks.  FP64 arithmetic: exact products summed in
+// FP64.  FP32 arithmetic: the VEC products are summed in FP32 first (one
+// conversion per chunk instead of one per element); the chunk sum carries a
+// relative error of a few 2^-24, which stays far below the FP32 rounding of
+// the vectors themselves, also for the small second-pass projections.
+template <class T, int VEC>
+__device__ __forceinline__ double group_dot(const T (&a)[VEC], const T (&b)[VEC]) {
+  if constexpr (sizeof(T) == 4) {
+    T p = a[0] * b[0];
+#pragma unroll
+    for (int e = 1; e < VEC; ++e) p = fmaf(a[e], b[e], p);
+    return (double)p;
+  } else {
+    double p = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) p += (double)a[e] * (double)b[e];
+    return p;
+  }
+}
+
 template <class T, class VT, int KMAX, int VEC, int MODE>
 __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
@@ -231,10 +252,10 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   for (; i < a.n; i += step) {
     if constexpr (MODE == PASS_A) {
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k)
-        if (k < K)
+      for (int kb = 0; kb < KMAX; kb += 4)
+        if (kb < K)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[k] += (double)vv[k][e] * (double)w[e];
+          for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], w);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)w[e] * (double)w[e];
     } else {
@@ -247,11 +268,13 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
         wn[e] = x;
       }
       if constexpr (MODE == PASS_B) {
+        // groups of four slots behind one uniform branch; chunks k >= K in a
+        // partly used group are zero and add exactly 0
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K)
+        for (int kb = 0; kb < KMAX; kb += 4)
+          if (kb < K)
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[k] += (double)vv[k][e] * (double)wn[e];
+            for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], wn);
         if constexpr (is_half<VT>()) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];

@@ -230,14 +230,14 @@ struct Impl {
   static constexpr int KVEC = krylov_vec<T>();
 
   // Grid of the CGS passes over K basis vectors: two 512-thread blocks per
-  // compute unit while the pass's registers leave room for them (FP32 up to 16
-  // vectors, FP64 up to 8), one block otherwise (measured on MI355X: 512
-  // blocks run passes B and C 4-10% faster at K = 12, 256 blocks 20% faster at
+  // compute unit while the pass's registers leave room for them (up to 16
+  // vectors: ~120 VGPRs), one block otherwise (measured on MI355X: 512 blocks
+  // run passes B and C 4-10% faster at K = 12, 256 blocks 20% faster at
   // K = 24).  Consumers of a pass's partial sums use the same grid.
   static int cgs_grid(const jfnk_solver* s, int K) {
     const int kmax = K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 16 ? 16 : 32));
     const int vec = (sizeof(T) == 8 && kmax > 16) ? 1 : (int)(16 / sizeof(T));
-    const bool two = sizeof(T) == 8 ? kmax <= 8 : kmax <= 16;
+    const bool two = kmax <= 16;
     const long long need = (s->npad + (long long)kKrylovThreads * vec - 1) / ((long long)kKrylovThreads * vec);
     return (int)std::max<long long>(1, std::min<long long>(need, (two ? 2LL : 1LL) * s->cu));
   }

@@ -394,12 +394,22 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
             if (q < a.K) {
               VT vq[NF][VEC];
               load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rr, cc, vq);
-              double s = 0.0;
+              if constexpr (sizeof(T) == 4) {
+                // FP32 sum over the thread's chunk, FP64 across chunks (as in pass B)
+                T p = T(0);
 #pragma unroll
-              for (int f = 0; f < NF; ++f)
+                for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[f][e]) * (double)o[f][e];
-              acc[q] += s;
+                  for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[f][e]), o[f][e], p);
+                acc[q] += (double)p;
+              } else {
+                double s = 0.0;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[f][e]) * (double)o[f][e];
+                acc[q] += s;
+              }
             }
           }
         }
