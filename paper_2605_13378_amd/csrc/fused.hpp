@@ -59,13 +59,19 @@ struct FusedArgs {
   FusedInfo* info;
 };
 
+// Row stride of the basis in LDS: a multiple of 32 elements plus 8, so that
+// lane groups of a wavefront reading consecutive elements of different
+// vectors start on different banks (8 banks apart for 4-byte elements, 16
+// for 8-byte ones).
+__host__ __device__ constexpr int fused_ldv(long long n) { return (int)((n + 31) / 32 * 32 + 8); }
+
 // LDS bytes of the kernel for n unknowns and restart length m: FP64 master
 // and trial iterates, the Hessenberg/rotation arrays and scalars in FP64; the
 // working copies, F, trial F, w, dx, b and the m + 1 basis vectors in T.
 template <class T>
 constexpr size_t fused_lds_bytes(long long n, int m) {
   const size_t dbl = (size_t)2 * n + (size_t)(m + 1) * m + 4 * (size_t)m + 1 + 64 + kMaxCols;
-  const size_t wt = (sizeof(T) == 8 ? 5 : 7) * (size_t)n + (size_t)(m + 1) * n;
+  const size_t wt = (sizeof(T) == 8 ? 5 : 7) * (size_t)n + (size_t)(m + 1) * fused_ldv(n);
   return dbl * 8 + wt * sizeof(T);
 }
 
@@ -96,16 +102,19 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* sc, doubl
 }
 
 // out[i] = V_i . w for i < K (FP64 accumulation): G lanes of one wavefront
-// per vector, then a shuffle tree inside each lane group.
+// per vector (G a power of two, G * K <= threads), then a shuffle tree inside
+// each lane group.  Vector i starts at V + i * ldv; the padded stride puts
+// the lane groups of one wavefront on different LDS banks.  Barriers on
+// entry (earlier readers of `out`) and exit.
 template <class T>
-__device__ __forceinline__ void block_dots(const T* V, int n, int K, const T* w, double* out) {
+__device__ __forceinline__ void block_dots(const T* V, int n, int ldv, int K, const T* w, double* out) {
   int G = kWave;
   while (G > 1 && G * K > kFusedThreads) G >>= 1;
   const int i = threadIdx.x / G;
   const int g = threadIdx.x % G;
   double s = 0.0;
   if (i < K) {
-    const T* v = V + (size_t)i * n;
+    const T* v = V + (size_t)i * ldv;
     for (int e = g; e < n; e += G) s += (double)v[e] * (double)w[e];
   }
   for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
@@ -254,7 +263,8 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
   T* w = Ft + n;
   T* dx = w + n;
   T* bl = dx + n;
-  T* V = bl + n;  // m + 1 vectors of n
+  T* V = bl + n;  // m + 1 vectors of n, stride ldv
+  const int ldv = fused_ldv(n);
 
   for (int e = tid; e < n; e += kFusedThreads) {
     const double xv = a.x[e];
@@ -344,44 +354,49 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
         int kk = 0;
         for (int j = 0; j < m; ++j) {
           const int K = j + 1;
-          jvp(V + (size_t)j * n, 1.0, jn2);
+          jvp(V + (size_t)j * ldv, 1.0, jn2);
           // classical Gram-Schmidt, first pass: h = V^T w, w -= V h
-          block_dots<T>(V, n, K, w, hv);
+          block_dots<T>(V, n, ldv, K, w, hv);
           for (int e = tid; e < n; e += kFusedThreads) {
             T acc = w[e];
-            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * n + e];
+            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * ldv + e];
             w[e] = acc;
           }
-          if (tid == 0)
-            for (int i = 0; i < K; ++i) H[i + (size_t)j * (m + 1)] = hv[i];
+          if (tid < K) H[tid + (size_t)j * (m + 1)] = hv[tid];
           __syncthreads();
           // second pass: h2 = V^T w, w -= V h2, ||w||^2
-          block_dots<T>(V, n, K, w, hv);
+          block_dots<T>(V, n, ldv, K, w, hv);
           double sw = 0.0;
           for (int e = tid; e < n; e += kFusedThreads) {
             T acc = w[e];
-            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * n + e];
+            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * ldv + e];
             w[e] = acc;
             sw += (double)acc * (double)acc;
           }
-          if (tid == 0)
-            for (int i = 0; i < K; ++i) H[i + (size_t)j * (m + 1)] += hv[i];
+          if (tid < K) H[tid + (size_t)j * (m + 1)] += hv[tid];
           double wn2 = 0.0;
           block_sum2(sw, 0.0, sc, wn2, dummy);
           const double wn = sqrt(wn2);
           // Givens rotations of column j (one thread), stop tests published in LDS
           if (tid == 0) {
-            double* col = H + (size_t)j * (m + 1);
+            double* __restrict__ col = H + (size_t)j * (m + 1);
+            const double* __restrict__ csr = cs;
+            const double* __restrict__ snr = sn;
             col[K] = wn;
             bool ok = isfinite(wn);
             for (int i = 0; i < K; ++i) ok = ok && isfinite(col[i]);
             if (ok) {
+              // previous rotations; the entry being rotated down the column
+              // stays in a register (cur), the untouched entries are loads
+              // off the dependency chain
+              double cur = col[0];
               for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-                col[i] = t;
+                const double nxt = col[i + 1];
+                const double ci = csr[i], si = snr[i];
+                col[i] = ci * cur + si * nxt;
+                cur = -si * cur + ci * nxt;
               }
-              const double ha = col[j], hb = col[j + 1];
+              const double ha = cur, hb = col[j + 1];
               double c = 1.0, s = 0.0;
               if (hb != 0.0) {
                 const double r = hypot(ha, hb);
@@ -407,7 +422,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           iters += 1;
           if (sc[S_EST] <= target) break;
           if (wn <= a.o.brk * sqrt(jn2)) break;
-          for (int e = tid; e < n; e += kFusedThreads) V[(size_t)K * n + e] = T((double)w[e] / wn);
+          for (int e = tid; e < n; e += kFusedThreads) V[(size_t)K * ldv + e] = T((double)w[e] / wn);
           __syncthreads();
         }
         if (nonfinite) break;
@@ -422,7 +437,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
         __syncthreads();
         for (int e = tid; e < n; e += kFusedThreads) {
           T acc = dx[e];
-          for (int i = 0; i < kk; ++i) acc = acc + T(yv[i]) * V[(size_t)i * n + e];
+          for (int i = 0; i < kk; ++i) acc = acc + T(yv[i]) * V[(size_t)i * ldv + e];
           dx[e] = acc;
         }
         __syncthreads();
