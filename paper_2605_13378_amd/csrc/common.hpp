@@ -62,6 +62,22 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&in)[N]) {
   *reinterpret_cast<vec<T, N>*>(p) = t;
 }
 
+// The same with a non-temporal hint: for outputs that no kernel of the same
+// sequence reads back right away, so they stream to memory instead of
+// displacing cached inputs.
+template <class T, int N>
+__device__ __forceinline__ void store_vec_nt(T* __restrict__ p, const T (&in)[N]) {
+  if constexpr (N == 1) {
+    __builtin_nontemporal_store(in[0], p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(N)));
+    vt t;
+#pragma unroll
+    for (int e = 0; e < N; ++e) t[e] = in[e];
+    __builtin_nontemporal_store(t, reinterpret_cast<vt*>(p));
+  }
+}
+
 // storage <-> compute conversions (FP16 storage carries a power-of-two scale
 // applied by the caller)
 template <class C, class S> __device__ __forceinline__ C to_c(S x) { return static_cast<C>(x); }

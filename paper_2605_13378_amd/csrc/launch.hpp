@@ -98,6 +98,9 @@ inline int stencil_tiles(int pid, int nx, int ny, int vec, int ry, dim3& block) 
   return tiles_x * ((ny + band - 1) / band);
 }
 
+constexpr int kStencilUncapped = 1 << 29;  // caps at or above this: one tile per block
+constexpr int kStencilRY1Tiles = 1 << 30;  // RY = 1 for uncapped 2D launches with this many tiles (off)
+
 inline StencilPlan stencil_plan(int pid, int nx, int ny, int vec, int cap) {
   StencilPlan p;
   p.ry = 2;
@@ -105,6 +108,17 @@ inline StencilPlan stencil_plan(int pid, int nx, int ny, int vec, int cap) {
   if (pid != kBurgers1D && vec > 1 && p.ntiles > cap) {
     p.ry = 4;
     p.ntiles = stencil_tiles(pid, nx, ny, vec, 4, p.block);
+  } else if (pid != kBurgers1D && vec > 1 && cap >= kStencilUncapped) {
+    // large grids without partial sums could take one row per thread; kept
+    // off: a batch-averaged probe favoured it at 2048^2 (19.0 vs 19.9 us), the
+    // per-dispatch timing of the benchmark did not (19.0 vs 18.5 us)
+    dim3 b1;
+    const int t1 = stencil_tiles(pid, nx, ny, vec, 1, b1);
+    if (t1 >= kStencilRY1Tiles) {
+      p.ry = 1;
+      p.ntiles = t1;
+      p.block = b1;
+    }
   }
   p.grid = p.ntiles < cap ? p.ntiles : cap;
   if (p.grid < 1) p.grid = 1;

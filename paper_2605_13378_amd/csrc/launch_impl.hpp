@@ -8,16 +8,22 @@ namespace jfnk {
 
 template <class P, class T, class VT, int VEC, int RY, int OP>
 static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid, dim3 block, hipStream_t s) {
-  if (a.Vb == nullptr)
+  if constexpr (RY == 1) {
+    // RY = 1 plans only uncapped launches, which carry no fused projection
+    if (a.Vb != nullptr) return hipErrorInvalidValue;
     JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
-  else if (a.K <= 4)
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
-  else if (a.K <= 8)
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, s, a, c);
-  else if (a.K <= 16)
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, s, a, c);
-  else
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, s, a, c);
+  } else {
+    if (a.Vb == nullptr)
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
+    else if (a.K <= 4)
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
+    else if (a.K <= 8)
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, s, a, c);
+    else if (a.K <= 16)
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, s, a, c);
+    else
+      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, s, a, c);
+  }
   return hipGetLastError();
 }
 
@@ -53,6 +59,7 @@ static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectoriz
   if (!vectorized) return stencil_by_op<P, T, VT, 1, 2>(op, withf, a, c, grid, p.block, s);
   if constexpr (P::kDim2) {
     if (p.ry == 4) return stencil_by_op<P, T, VT, V, 4>(op, withf, a, c, grid, p.block, s);
+    if (p.ry == 1) return stencil_by_op<P, T, VT, V, 1>(op, withf, a, c, grid, p.block, s);
   }
   return stencil_by_op<P, T, VT, V, 2>(op, withf, a, c, grid, p.block, s);
 }
