@@ -13,6 +13,7 @@ Newton-Krylov Solvers via Automatic Differentiation"):
 * ``dual``: forward-mode dual numbers (the AD JVP of Section 2).
 * ``jvp``: AD and FD Jacobian-vector products and the FD step rules.
 * ``gmres``: restarted GMRES(m), CGS2 Arnoldi, Givens least squares.
+* ``bicgstab``: BiCGSTAB, the paper's short-recurrence nonsymmetric method.
 * ``newton``: inexact Newton with backtracking line search and the
   failure classification of Section 3.4.
 
@@ -24,7 +25,8 @@ the paper does not fix: they are a reading, pinned only by the Armijo property
 (parity of the constants themselves unpinned).
 """
 
-from . import dual, gmres, jvp, newton, problems  # noqa: F401
+from . import bicgstab, dual, gmres, jvp, newton, problems  # noqa: F401
+from .bicgstab import BicgstabInfo, bicgstab as bicgstab_solve  # noqa: F401
 from .gmres import GmresInfo, gmres as gmres_solve  # noqa: F401
 from .jvp import EPS_MACH, EPS_NORMALIZED, EPS_PAPER, fd_step, jvp_ad, jvp_fd  # noqa: F401
 from .newton import NewtonInfo, NewtonOptions, newton_solve, run_failed, step_failed  # noqa: F401

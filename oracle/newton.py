@@ -1,7 +1,7 @@
 """Inexact Newton with backtracking line search (oracle).
 
 Paper, Section 2: linearize F(x^k) at each iterate, solve J(x^k) dx = -F(x^k)
-with the Krylov method (J only through JVPs), stop when
+with the Krylov method (GMRES or BiCGSTAB; J only through JVPs), stop when
 ||F(x^k, x*)|| / ||F(x*, x*)|| < tol_Newton, and damp the update to
 x^{k+1} = x^k + alpha dx with alpha reduced until the residual norm decreases
 sufficiently.  The paper leaves the line-search constants open; the reading
@@ -24,6 +24,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import gmres as gm
+from .bicgstab import bicgstab
 from .jvp import EPS_MACH, EPS_PAPER, fd_step, jvp_ad, jvp_fd
 from .problems import Problem, residual
 
@@ -46,6 +47,7 @@ class NewtonOptions:
     eps_mach: float = EPS_MACH["f64"]
     fd_eps: float = 0.0  # > 0: fixed FD step
     breakdown_tol: float = 1e-14
+    krylov: str = "gmres"  # 'gmres' | 'bicgstab' (its iteration cap: max_restarts)
 
     @classmethod
     def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
@@ -110,10 +112,13 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
                 eps = opts.fd_eps if opts.fd_eps > 0.0 else fd_step(opts.eps_rule, opts.eps_mach, _x, v)
                 return jvp_fd(p, _x, v, eps, x_prev, source, Fx=_F)
 
-        dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
-                             max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol)
+        if opts.krylov == "bicgstab":
+            dx, ginfo = bicgstab(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+        else:
+            dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
+                                 max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol)
+            info.restarts += ginfo.cycles
         info.krylov_iters += ginfo.iters
-        info.restarts += ginfo.cycles
         info.lin_iters.append(ginfo.iters)
         if ginfo.nonfinite:
             info.status = NONFINITE

@@ -116,3 +116,36 @@ def test_line_search_that_accepts_every_step(monkeypatch):
         return dataclasses.replace(onewton.NewtonOptions(**kw), ls_c=-1e30)
     monkeypatch.setattr(tn, "NewtonOptions", opts)
     _expect_failure(tn.test_line_search_armijo_and_halving)
+
+
+# --- BiCGSTAB: mistakes planted by rewriting one line of the oracle's source --
+import inspect  # noqa: E402
+
+import oracle.bicgstab as obicg  # noqa: E402
+import test_oracle_bicgstab as tb  # noqa: E402
+
+
+def _bicgstab_mutant(old: str, new: str):
+    src = inspect.getsource(obicg)
+    assert old in src
+    ns: dict = {}
+    exec(compile(src.replace(old, new, 1), "bicgstab_mutant", "exec"), ns)
+    return ns["bicgstab"]
+
+
+@pytest.mark.parametrize("old,new", [
+    ("omega = ts / tt", "omega = -ts / tt"),                            # sign of the stabilizing step
+    ("beta = (rho / rho_prev) * (alpha / omega)", "beta = (rho / rho_prev) * (omega / alpha)"),  # swapped ratio
+    ("s = r - alpha * v", "s = r + alpha * v"),                          # sign of the half step
+    ("r = s - omega * t", "r = s - omega * s"),                          # wrong operand
+    ("p = r + beta * (p - omega * v)", "p = r + beta * p"),              # dropped correction term
+])
+def test_bicgstab_mutations_fail_a_pin(monkeypatch, old, new):
+    monkeypatch.setattr(tb, "bicgstab_solve", _bicgstab_mutant(old, new))
+    failed = 0
+    for fn, args in ((tb.test_dense_solve, (60, 2)), (tb.test_matches_scipy_bicgstab, (40, 4, 1e-8))):
+        try:
+            fn(*args)
+        except AssertionError:
+            failed += 1
+    assert failed >= 1
