@@ -110,7 +110,15 @@ typedef struct {
   double* history;       /* nullable DEVICE array of (max_newton + 1) * n doubles:
                             receives every Newton iterate x_k (k = 0, 1, ...) */
   int engine;            /* jfnk_engine */
+  int krylov;            /* jfnk_krylov: the linear solver of each Newton step */
 } jfnk_options;
+
+/* The Krylov method of each Newton step (paper, Section 2: GMRES(m) or
+ * BiCGSTAB for nonsymmetric Jacobians).  BICGSTAB takes max_restarts as
+ * its iteration cap (Section 3.3 gives both the same cap of 100), ignores m
+ * and breakdown_tol, and runs on the MULTI_KERNEL engine in FP64 or FP32
+ * with a solver created with m >= 5. */
+typedef enum { JFNK_KRYLOV_GMRES = 0, JFNK_KRYLOV_BICGSTAB = 1 } jfnk_krylov;
 
 /* How jfnk_newton_solve runs the method (same algorithm, same options):
  *   AUTO:  SINGLE_WORKGROUP when the problem fits it, else MULTI_KERNEL;
@@ -179,6 +187,21 @@ jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, voi
 jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx, int m, double tol,
                        int max_restarts, int mode, double eps, int eps_rule, jfnk_info* info);
 
+/* Solve J(x) dx = rhs by BiCGSTAB (paper, Section 2: van der Vorst's
+ * stabilized bi-conjugate gradients, two JVPs per iteration) from dx = 0
+ * with shadow residual r^ = rhs; stops when ||s|| (half step) or ||r|| is at
+ * most tol ||rhs||, after max_iters iterations, on a breakdown (rho,
+ * (r^, J p) or ||J s||^2 exactly zero, or omega = 0) or on a non-finite
+ * scalar.  x, rhs, dx: device arrays of n elements of the working precision
+ * (FP64 or FP32 solvers created with m >= 5; the solver's first six basis
+ * slots are its work vectors).  Returns JFNK_OK when converged or at the
+ * cap (info->converged tells which), JFNK_ERR_BREAKDOWN, JFNK_ERR_NONFINITE
+ * or JFNK_ERR_ARG; info (nullable) receives converged, krylov_iters (completed
+ * iterations), final_res (last ||r||, or ||s|| at a half-step stop) and
+ * f0_norm (||rhs||).  Synchronizes before returning. */
+jfnk_status jfnk_bicgstab(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters,
+                          int mode, double eps, int eps_rule, jfnk_info* info);
+
 /* Newton with line search from x_inout (FP64 device array, overwritten with
  * the last iterate).  Returns JFNK_OK when converged, JFNK_ERR_NOT_CONVERGED
  * at the iteration cap, JFNK_ERR_NONFINITE on NaN/Inf; info is filled in all
@@ -200,8 +223,10 @@ const char* jfnk_last_error(const jfnk_solver* s);
 /* Kernel timing with HIP events on the solver's stream (off by default).
  * kernel: 0 residual, 1 AD JVP, 2 FD JVP, 3 CGS pass A (V^T w), 4 CGS pass B
  * (update + dot), 5 CGS pass C (update + norm + Givens), 6 V y update,
- * 7 cycle start, 8 Newton trial update, 9 single-workgroup whole solve.  Reports the launches timed since
- * the last reset, their summed duration (ms) and their algorithmic HBM bytes. */
+ * 7 cycle start, 8 Newton trial update, 9 single-workgroup whole solve,
+ * 10 BiCGSTAB streaming kernels (its JVPs count as 1 or 2).  Reports the
+ * launches timed since the last reset, their summed duration (ms) and their
+ * algorithmic HBM bytes. */
 jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);
 jfnk_status jfnk_profile_read(jfnk_solver* s, int kernel, long long* launches, double* total_ms,
                               double* bytes);

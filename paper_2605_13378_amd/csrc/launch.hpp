@@ -7,6 +7,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "bicgstab.hpp"
 #include "common.hpp"
 #include "fused.hpp"
 #include "krylov.hpp"
@@ -165,6 +166,12 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s);
 // (fused_lds_bytes<T>(n, m)); problem kinds as in launch_stencil.
 template <class T>
 hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStream_t s);
+
+// BiCGSTAB streaming kernels (bicgstab.hpp) on `grid` blocks of
+// kStreamThreads; `tol` is read by the p kernel only.
+enum { BI_INIT = 0, BI_P = 1, BI_S = 2, BI_XR = 3 };
+template <class T>
+hipError_t launch_bi(int kind, const BiArgs<T>& a, double tol, int grid, hipStream_t s);
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);

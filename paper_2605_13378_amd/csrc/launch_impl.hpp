@@ -155,6 +155,29 @@ hipError_t launch_fill_zero(long long n, T* p, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_bi(int kind, const BiArgs<T>& a, double tol, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  const dim3 g(grid), b(kStreamThreads);
+  switch (kind) {
+    case BI_INIT:
+      JFNK_LAUNCH((bi_init_kernel<T, VEC>), g, b, s, a);
+      break;
+    case BI_P:
+      JFNK_LAUNCH((bi_p_kernel<T, VEC>), g, b, s, a, tol);
+      break;
+    case BI_S:
+      JFNK_LAUNCH((bi_s_kernel<T, VEC>), g, b, s, a);
+      break;
+    case BI_XR:
+      JFNK_LAUNCH((bi_xr_kernel<T, VEC>), g, b, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class P, class T>
 static hipError_t fused_for_problem(const FusedArgs<T>& a, size_t lds, hipStream_t s) {
   const auto k = fused_solve_kernel<P, T>;
@@ -194,6 +217,7 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
   template hipError_t launch_cast<T>(long long, const double*, T*, int, hipStream_t);                           \
   template hipError_t launch_norm2<T>(long long, const T*, PartSink, int, hipStream_t);                         \
   template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);                                     \
-  template hipError_t launch_fused_solve<T>(int, const FusedArgs<T>&, size_t, hipStream_t);
+  template hipError_t launch_fused_solve<T>(int, const FusedArgs<T>&, size_t, hipStream_t);                 \
+  template hipError_t launch_bi<T>(int, const BiArgs<T>&, double, int, hipStream_t);
 
 }  // namespace jfnk

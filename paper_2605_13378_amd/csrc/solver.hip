@@ -32,9 +32,10 @@ thread_local KernelTiming* g_timing = nullptr;
 
 namespace {
 
-constexpr int kNumProf = 10;
+constexpr int kNumProf = 11;
 enum ProfKernel {
-  PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8, PK_FUSED = 9
+  PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8, PK_FUSED = 9,
+  PK_BI = 10
 };
 
 struct ProfRec {
@@ -85,6 +86,8 @@ struct jfnk_solver {
   size_t lds_max = 0;           // LDS bytes one workgroup may use
   FusedInfo* dinfo = nullptr;   // single-workgroup solve record (device)
   FusedInfo* hinfo = nullptr;   // pinned host copy
+  BiCtl* dbi = nullptr;         // BiCGSTAB scalars (device)
+  BiCtl* hbi = nullptr;         // pinned host copy
   bool has_prev = false;
   std::string err;
   bool prof = false;
@@ -430,6 +433,153 @@ struct Impl {
     return JFNK_OK;
   }
 
+  // Jacobian-vector product of a BiCGSTAB iteration: Jv = J(x) v with the
+  // partial sums of (dotv, Jv) and ||Jv||^2 into region `region` (the fused
+  // projection slot of the Arnoldi JVP with one vector); skipped on the
+  // device once the solve has stopped (see StencilArgs::gate).
+  static jfnk_status jvp_bi(jfnk_solver* s, const T* x, const T* v, T* Jv, int mode, const EpsSpec& eps,
+                            const T* dotv, int region, const int* gate, Partials gate_parts, const double* gate_tol,
+                            int* nb_out) {
+    StencilArgs<T, T> a{};
+    a.nx = s->prob.nx;
+    a.ny = s->prob.ny;
+    a.plane = (long long)s->prob.nx * s->prob.ny;
+    a.x = x;
+    a.v = v;
+    a.b = mode == JFNK_JVP_AD ? nullptr : static_cast<const T*>(s->b);
+    a.out = Jv;
+    a.alpha = s->alpha;
+    a.cN = s->cN;
+    a.beta = s->beta;
+    a.eps = eps;
+    a.Vb = dotv;
+    a.vstride = s->npad;
+    a.K = 1;
+    a.dots_out = sink(s, region);
+    a.gate = gate;
+    a.gate_parts = gate_parts;
+    a.gate_tol = gate_tol;
+    const int vec = stencil_vec<T>(s->pid);
+    const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(v, 16) && aligned(Jv, 16) &&
+                    aligned(a.b, 16) && aligned(dotv, 16);
+    const int op = mode == JFNK_JVP_AD ? OP_AD : OP_FD;
+    // algorithmic bytes: x, v, Jv (+ b for FD) and the dot vector unless it is v itself
+    const double bytes = ((mode == JFNK_JVP_AD ? 3.0 : 4.0) + (dotv == v ? 0.0 : 1.0)) * s->n * sizeof(T);
+    ProfScope ps(s, mode == JFNK_JVP_AD ? PK_AD : PK_FD, bytes);
+    JFNK_HIP(s, launch_stencil<T, T>(s->pid, op, false, vz, a, s->coefs, arnoldi_cap(s), s->stream, nb_out));
+    return JFNK_OK;
+  }
+
+  struct BOut {
+    bool converged = false, nonfinite = false, breakdown = false;
+    int iters = 0;
+    double bnorm = 0.0, res = 0.0;
+  };
+
+  // BiCGSTAB on J(x) dx = sign * R (R internal, padded) from dx = 0, dx
+  // internal.  r^, r, p, v, s, t occupy basis slots 0..5 (working precision;
+  // callers check that the basis has them).  Iterations are enqueued back to
+  // back; the p kernel of iteration i publishes the state after iteration
+  // i-1 to mapped host memory, and after enqueueing iteration i the host
+  // waits for iteration i-1's flag, so at most two enqueued iterations run
+  // empty after the stop.  A last p kernel in check-only mode settles the
+  // state after the final iteration.
+  static jfnk_status bicgstab(jfnk_solver* s, const T* x, const T* R, double sign, double tol, int maxiter,
+                              int mode, double fixed_eps, int eps_rule, BOut& bo) {
+    static_assert(std::is_same<T, VT>::value, "BiCGSTAB keeps its vectors in the working precision");
+    bo = BOut{};
+    T* rh = basis(s, 0);
+    T* r = basis(s, 1);
+    T* p = basis(s, 2);
+    T* v = basis(s, 3);
+    T* sv = basis(s, 4);
+    T* t = basis(s, 5);
+    const int sgrid = stream_grid(s, KVEC);
+    BiArgs<T> a{};
+    a.n = s->npad;
+    a.c = s->dbi;
+    a.R = R;
+    a.sign = sign;
+    a.rh = rh;
+    a.r = r;
+    a.p = p;
+    a.v = v;
+    a.s = sv;
+    a.t = t;
+    a.x = static_cast<T*>(s->dx);
+    a.host_flags = s->dflags;
+    EpsSpec eps_p = eps_spec(s, fixed_eps, eps_rule, nullptr);
+    EpsSpec eps_s = eps_p;
+    if (eps_rule == JFNK_EPS_NORMALIZED) {
+      eps_p.vparts = parts(s, 1, sgrid);  // ||p||^2 from the p kernel
+      eps_s.vparts = parts(s, 3, sgrid);  // ||s||^2 from the s kernel
+    }
+    const double vec_bytes = (double)s->n * sizeof(T);
+    // partial-sum regions: 0 xr / init, 1 p, 2 JVP of p, 3 s, 4 JVP of s
+    s->cur_step = -1;
+    a.out = sink(s, 0);
+    {
+      ProfScope ps(s, PK_BI, 4.0 * vec_bytes);
+      JFNK_HIP(s, launch_bi<T>(BI_INIT, a, tol, sgrid, s->stream));
+    }
+    volatile int* flags = reinterpret_cast<volatile int*>(s->hflags);
+    constexpr int kRing = kMaxM + 1;
+    int last = 0;
+    for (int it = 1; it <= maxiter; ++it) {
+      s->cur_step = it - 1;
+      a.it = it;
+      a.check_only = 0;
+      a.flag_slot = it % kRing;
+      flags[a.flag_slot] = -1;
+      a.in = parts(s, 0, sgrid);
+      a.out = sink(s, 1);
+      {
+        ProfScope ps(s, PK_BI, (it == 1 ? 2.0 : 4.0) * vec_bytes);
+        JFNK_HIP(s, launch_bi<T>(BI_P, a, tol, sgrid, s->stream));
+      }
+      int nb_v = 0;
+      JFNK_TRY(jvp_bi(s, x, p, v, mode, eps_p, rh, 2, &s->dbi->state_p, Partials{nullptr, 0, 0}, nullptr, &nb_v));
+      a.in = parts(s, 2, nb_v);
+      a.out = sink(s, 3);
+      {
+        ProfScope ps(s, PK_BI, 3.0 * vec_bytes);
+        JFNK_HIP(s, launch_bi<T>(BI_S, a, tol, sgrid, s->stream));
+      }
+      int nb_t = 0;
+      JFNK_TRY(jvp_bi(s, x, sv, t, mode, eps_s, sv, 4, &s->dbi->state_s, parts(s, 3, sgrid), &s->dbi->target,
+                      &nb_t));
+      a.in = parts(s, 3, sgrid);
+      a.in2 = parts(s, 4, nb_t);
+      a.out = sink(s, 0);
+      {
+        ProfScope ps(s, PK_BI, 7.0 * vec_bytes);
+        JFNK_HIP(s, launch_bi<T>(BI_XR, a, tol, sgrid, s->stream));
+      }
+      last = it;
+      if (it >= 2) {
+        const int ps = (it - 1) % kRing;
+        if (!wait_flag(s, flags, ps) || flags[ps] != kRunning) break;
+      }
+    }
+    s->cur_step = -1;
+    a.it = last + 1;
+    a.check_only = 1;
+    a.flag_slot = (last + 1) % kRing;
+    a.in = parts(s, 0, sgrid);
+    JFNK_HIP(s, launch_bi<T>(BI_P, a, tol, sgrid, s->stream));
+    JFNK_HIP(s, hipMemcpyAsync(s->hbi, s->dbi, sizeof(BiCtl), hipMemcpyDeviceToHost, s->stream));
+    JFNK_HIP(s, hipStreamSynchronize(s->stream));
+    const BiCtl& h = *s->hbi;
+    if (s->prof) prof_harvest(s, h.iters + 1);
+    bo.iters = h.iters;
+    bo.bnorm = h.bnorm;
+    bo.res = h.res;
+    bo.converged = h.state_p == kConverged;
+    bo.nonfinite = h.state_p == kNonfinite;
+    bo.breakdown = h.state_p == kBreakdown;
+    return JFNK_OK;
+  }
+
   // The whole solve in one workgroup (small problems, FP64/FP32).
   static bool fused_fits(const jfnk_solver* s, int m) {
     return std::is_same<T, VT>::value && fused_lds_bytes<T>(s->n, m) <= s->lds_max;
@@ -488,11 +638,16 @@ struct Impl {
   }
 
   static jfnk_status newton(jfnk_solver* s, double* x_user, const jfnk_options& o, jfnk_info* info) {
+    if (o.engine == JFNK_ENGINE_SINGLE_WORKGROUP && o.krylov != JFNK_KRYLOV_GMRES) {
+      s->err = "the single-workgroup engine runs GMRES only";
+      return JFNK_ERR_ARG;
+    }
     if (o.engine == JFNK_ENGINE_SINGLE_WORKGROUP && !fused_fits(s, o.m)) {
       s->err = "the single-workgroup engine needs FP64 or FP32 and a problem that fits in LDS";
       return JFNK_ERR_ARG;
     }
-    if (o.engine != JFNK_ENGINE_MULTI_KERNEL && fused_fits(s, o.m)) return newton_fused(s, x_user, o, info);
+    if (o.krylov == JFNK_KRYLOV_GMRES && o.engine != JFNK_ENGINE_MULTI_KERNEL && fused_fits(s, o.m))
+      return newton_fused(s, x_user, o, info);
     const long long n = s->n;
     const bool f64 = std::is_same<T, double>::value;
     const int sgrid = stream_grid(s, 2);
@@ -525,8 +680,18 @@ struct Impl {
         break;
       }
       GOut go;
-      JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
-                     o.fd_eps, o.eps_rule, o.breakdown_tol, go));
+      if (o.krylov == JFNK_KRYLOV_BICGSTAB) {
+        if constexpr (std::is_same<T, VT>::value) {
+          BOut bo;
+          JFNK_TRY(bicgstab(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.tol_krylov, o.max_restarts, o.mode,
+                            o.fd_eps, o.eps_rule, bo));
+          go.iters = bo.iters;
+          go.nonfinite = bo.nonfinite;
+        }
+      } else {
+        JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
+                       o.fd_eps, o.eps_rule, o.breakdown_tol, go));
+      }
       info->krylov_iters += go.iters;
       info->restarts += go.cycles;
       info->lin_iters[k] = go.iters;
@@ -674,7 +839,7 @@ size_t footprint(const jfnk_problem* p, int prec, int m, int cu) {
   bytes += 8 * (size_t)npad * t;                            // w R dx F Ft xw xwt b
   bytes += 3 * (size_t)npad * 8;                            // x64 x64t tmp64
   bytes += 6 * max_blocks(p, cu) * kMaxCols * 8;            // partial sums
-  bytes += sizeof(Ctl) + sizeof(FusedInfo);
+  bytes += sizeof(Ctl) + sizeof(FusedInfo) + sizeof(BiCtl);
   return bytes;
 }
 
@@ -702,6 +867,8 @@ void release(jfnk_solver* s) {
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->dinfo) (void)hipFree(s->dinfo);
   if (s->hinfo) (void)hipHostFree(s->hinfo);
+  if (s->dbi) (void)hipFree(s->dbi);
+  if (s->hbi) (void)hipHostFree(s->hbi);
   for (hipEvent_t e : s->pool)
     if (e) (void)hipEventDestroy(e);
   for (ProfRec& r : s->recs) {
@@ -755,6 +922,39 @@ jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, do
     info->status = go.nonfinite ? JFNK_ERR_NONFINITE : JFNK_OK;
   }
   return go.nonfinite ? JFNK_ERR_NONFINITE : JFNK_OK;
+}
+template <class T>
+jfnk_status bicgstab_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, double tol, int max_iters, int mode,
+                         double eps, int rule, jfnk_info* info) {
+  const long long n = s->n;
+  JFNK_HIP(s, hipMemcpyAsync(s->R, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
+  if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
+  typename Impl<T, T>::BOut bo;
+  JFNK_TRY(Impl<T, T>::bicgstab(s, x, static_cast<const T*>(s->R), 1.0, tol, max_iters, mode, eps, rule, bo));
+  JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  const jfnk_status st = bo.nonfinite ? JFNK_ERR_NONFINITE : (bo.breakdown ? JFNK_ERR_BREAKDOWN : JFNK_OK);
+  if (info) {
+    info->converged = bo.converged ? 1 : 0;
+    info->krylov_iters = bo.iters;
+    info->final_res = bo.res;
+    info->f0_norm = bo.bnorm;
+    info->status = st;
+  }
+  return st;
+}
+
+// BiCGSTAB keeps r^, r, p, v, s, t in the first six basis slots.
+bool bicgstab_fits(const jfnk_solver* s, std::string* why) {
+  if (s->prec == JFNK_F16S) {
+    *why = "BiCGSTAB runs in FP64 or FP32 (FP16 storage applies to the GMRES basis only)";
+    return false;
+  }
+  if (s->m < 5) {
+    *why = "BiCGSTAB needs a solver created with m >= 5 (six work vectors)";
+    return false;
+  }
+  return true;
 }
 }  // namespace
 
@@ -863,6 +1063,16 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   if (st == JFNK_OK) st = malloc_dev(s, &s->parts, 6 * s->part_rows * kMaxCols * sizeof(double));
   if (st == JFNK_OK) st = malloc_dev(s, &s->ctl, sizeof(Ctl));
   if (st == JFNK_OK) st = malloc_dev(s, &s->dinfo, sizeof(FusedInfo));
+  if (st == JFNK_OK) st = malloc_dev(s, &s->dbi, sizeof(BiCtl));
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(BiCtl), hipHostMallocDefault) != hipSuccess) {
+      s->err = "hipHostMalloc (BiCGSTAB scalars) failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hbi = static_cast<BiCtl*>(h);
+    }
+  }
   if (st == JFNK_OK) {
     void* h = nullptr;
     if (hipHostMalloc(&h, sizeof(FusedInfo), hipHostMallocDefault) != hipSuccess) {
@@ -1026,16 +1236,45 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
   return st;
 }
 
+jfnk_status jfnk_bicgstab(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters,
+                          int mode, double eps, int eps_rule, jfnk_info* info) {
+  if (!s || !x || !rhs || !dx) return JFNK_ERR_ARG;
+  if (max_iters < 0 || !(tol >= 0.0)) {
+    s->err = "max_iters >= 0 and tol >= 0 are required";
+    return JFNK_ERR_ARG;
+  }
+  if ((mode != JFNK_JVP_AD && mode != JFNK_JVP_FD) || (eps_rule != JFNK_EPS_PAPER && eps_rule != JFNK_EPS_NORMALIZED))
+    return JFNK_ERR_ARG;
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  if (!bicgstab_fits(s, &s->err)) return JFNK_ERR_ARG;
+  if (info) std::memset(info, 0, sizeof(*info));
+  const auto t0 = std::chrono::steady_clock::now();
+  jfnk_status st;
+  if (s->prec == JFNK_F64)
+    st = bicgstab_api<double>(s, (const double*)x, (const double*)rhs, (double*)dx, tol, max_iters, mode, eps,
+                              eps_rule, info);
+  else
+    st = bicgstab_api<float>(s, (const float*)x, (const float*)rhs, (float*)dx, tol, max_iters, mode, eps, eps_rule,
+                             info);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts, jfnk_info* info) {
   if (!s || !x_inout || !opts || !info) return JFNK_ERR_ARG;
   const jfnk_options& o = *opts;
   if (o.m < 1 || o.m > s->m || o.max_newton < 0 || o.max_newton > JFNK_MAX_ITERS || o.max_restarts < 0 ||
       o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
       (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0) ||
-      o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP) {
+      o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP ||
+      (o.krylov != JFNK_KRYLOV_GMRES && o.krylov != JFNK_KRYLOV_BICGSTAB)) {
     s->err = "invalid options";
     return JFNK_ERR_ARG;
   }
+  if (o.krylov == JFNK_KRYLOV_BICGSTAB && !bicgstab_fits(s, &s->err)) return JFNK_ERR_ARG;
   if (!s->has_prev) {
     s->err = "jfnk_set_previous must be called first";
     return JFNK_ERR_ARG;

@@ -57,6 +57,12 @@ struct StencilArgs {
   long long vstride;
   int K;
   PartSink dots_out;
+  // BiCGSTAB JVPs (gate non-null): leave at once when *gate is not
+  // kRunning, or, with gate_parts rows, when the square root of their
+  // column-0 sum is not above *gate_tol (the half-step stop test).
+  const int* gate;
+  Partials gate_parts;
+  const double* gate_tol;
 };
 
 template <bool PERIODIC>
@@ -257,6 +263,17 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           if (a.host_flags) a.host_flags[j - 1] = prev;
         }
         return;
+      }
+    }
+  }
+
+  if constexpr (OP != OP_RES) {
+    if (a.gate != nullptr) {
+      if (*a.gate != kRunning) return;
+      if (a.gate_parts.nb > 0) {
+        __shared__ double gsum[1];
+        reduce_partials(a.gate_parts, 1, gsum);
+        if (!(sqrt(gsum[0]) > *a.gate_tol)) return;  // uniform across the block
       }
     }
   }

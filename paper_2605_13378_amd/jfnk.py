@@ -22,10 +22,11 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
 ENGINES = {"auto": 0, "multi": 1, "single": 2}
+KRYLOV = {"gmres": 0, "bicgstab": 1}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
           5: "breakdown", 6: "not_converged"}
 PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
-                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9}
+                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9, "bicgstab": 10}
 
 
 class Problem(ctypes.Structure):
@@ -41,7 +42,7 @@ class Options(ctypes.Structure):
                 ("tol_krylov", ctypes.c_double), ("tol_newton", ctypes.c_double), ("ls_c", ctypes.c_double),
                 ("fd_eps", ctypes.c_double), ("breakdown_tol", ctypes.c_double),
                 ("mode", ctypes.c_int), ("eps_rule", ctypes.c_int),
-                ("history", ctypes.c_void_p), ("engine", ctypes.c_int)]
+                ("history", ctypes.c_void_p), ("engine", ctypes.c_int), ("krylov", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -97,6 +98,9 @@ _SIGNATURES = [
     ("jfnk_gmres", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(Info)]),
+    ("jfnk_bicgstab", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                     ctypes.POINTER(Info)]),
     ("jfnk_newton_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
                                          ctypes.POINTER(Info)]),
     ("jfnk_default_options", None, [ctypes.c_int, ctypes.POINTER(Options)]),
@@ -171,6 +175,8 @@ def default_options(precision: str = "f64", **kw) -> Options:
             val = EPS_RULES[val]
         elif key == "engine":
             val = ENGINES[val]
+        elif key == "krylov":
+            val = KRYLOV[val]
         elif key == "history":
             val = None if val is None else val.data_ptr()
         setattr(o, key, val)
@@ -264,6 +270,21 @@ class Solver:
                                      EPS_RULES[eps_rule], ctypes.byref(info)), allowed=(0, 4))
         d = info.as_dict()
         d["converged"] = bool(info.converged)
+        return dx, d
+
+    def bicgstab(self, x, rhs, tol=1e-8, max_iters=100, mode="ad", eps=0.0, eps_rule="paper"):
+        """BiCGSTAB solve of J(x) dx = rhs; returns (dx, info dict with 'breakdown')."""
+        x = self._vec(x, self.wdtype, "x")
+        rhs = self._vec(rhs, self.wdtype, "rhs")
+        dx = self._new()
+        info = Info()
+        rc = self._check(lib().jfnk_bicgstab(self._h, x.data_ptr(), rhs.data_ptr(), dx.data_ptr(), float(tol),
+                                             int(max_iters), MODES[mode], float(eps), EPS_RULES[eps_rule],
+                                             ctypes.byref(info)), allowed=(0, 4, 5))
+        d = info.as_dict()
+        d["converged"] = bool(info.converged)
+        d["breakdown"] = rc == 5
+        d["nonfinite"] = rc == 4
         return dx, d
 
     def newton_solve(self, x0, history: bool = False, **opts):

@@ -74,6 +74,7 @@ def test_default_options_follow_the_paper(jlib):
     assert (o64.tol_newton, o64.tol_krylov) == (1e-6, 1e-8)
     assert (o32.tol_newton, o32.tol_krylov) == (1e-4, 1e-6)
     assert o64.max_newton == 15 and o64.max_restarts == 100 and o64.m == 30
+    assert o64.krylov == jfnk.KRYLOV["gmres"] and o64.engine == jfnk.ENGINES["auto"]
 
 
 def test_invalid_create_is_rejected_without_gpu(jlib):
@@ -93,6 +94,7 @@ def test_null_handles_are_rejected(jlib):
     assert jlib.jfnk_destroy(None) == 1
     assert jlib.jfnk_residual(None, None, None) == 1
     assert jlib.jfnk_newton_solve(None, None, None, None) == 1
+    assert jlib.jfnk_bicgstab(None, None, None, None, 1e-8, 10, 0, 0.0, 0, None) == 1
 
 
 def test_product_path_does_not_import_oracle():
