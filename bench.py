@@ -351,6 +351,38 @@ def serving_bench(count, slots, budget_gib, seed=0):
     return out
 
 
+def bicgstab_rows(torch, spec, xp, x0, steps, budget_s=8.0):
+    """Newton with BiCGSTAB on the Gray-Scott workload: solves/s, iterations, per-kernel timing."""
+    rows = {}
+    for pr in ("f32", "f64"):
+        sv = make_solver(spec, pr, xp, torch)
+        for mode in ("ad", "fd"):
+            o = dict(options_for(pr, mode), krylov="bicgstab")
+            run_solves(sv, x0, torch, 1, o)
+            cnt, t_all, lat_v, inf = 0, 0.0, [], None
+            while t_all < budget_s and cnt < steps:
+                el, l1, inf = run_solves(sv, x0, torch, 1, o)
+                t_all += el
+                lat_v += l1
+                cnt += 1
+            sv.profile_reset()
+            sv.profile(True)
+            run_solves(sv, x0, torch, 1, o)
+            st = sv.profile_read()
+            sv.profile(False)
+            kern = {k: dict(launches=v["launches"], avg_us=round(v["ms"] * 1e3 / v["launches"], 3),
+                            gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0.0)
+                    for k, v in st.items() if v["launches"]}
+            rows[f"{pr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
+                                        p50_ms=round(1e3 * percentile(lat_v, 0.5), 3),
+                                        newton_iters=inf["newton_iters"], krylov_iters=inf["krylov_iters"],
+                                        lin_iters=inf["lin_iters"], converged=inf["converged"],
+                                        final_rel_res=inf["rel_res"][-1], kernels=kern)
+            log(f"[bench] bicgstab {pr}-{mode}: {rows[f'{pr}-{mode}']}")
+        sv.close()
+    return rows
+
+
 def cpu_baseline(spec, xp, prec):
     """The oracle, single-threaded, on one full Newton solve of the same workload."""
     try:
@@ -398,6 +430,7 @@ def main():
     ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
     ap.add_argument("--no-latency", action="store_true", help="skip the 1D Burgers N=256 latency rows")
+    ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
     ap.add_argument("--kerr-newton", action="store_true",
                     help="run the Helmholtz-Kerr 1024^2 Newton completion rows (minutes)")
     ap.add_argument("--completion-seeds", type=int, default=64,
@@ -543,6 +576,11 @@ def main():
             if sv is not s:
                 sv.close()
 
+    bicg = None
+    if not args.no_bicgstab:
+        log("[bench] Newton-BiCGSTAB rows (Gray-Scott 1024^2)")
+        bicg = bicgstab_rows(torch, spec, xp, x0, args.steps)
+
     c3 = None
     if args.completion_seeds > 0:
         log(f"[bench] completion sweep: 2D Burgers 2048^2, 10 steps, {args.completion_seeds} seeds")
@@ -596,6 +634,7 @@ def main():
         "jvp_kerr_1024": jvpkerr,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
+        "bicgstab_newton": bicg,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,
