@@ -9,11 +9,13 @@ Contents, each following the paper (Pasquale & Markidis, "Robust Matrix-Free
 Newton-Krylov Solvers via Automatic Differentiation"):
 
 * ``problems``: the discrete residuals F(x^k, x*) (Section 2; Section 3.2;
-  Appendix A) — 1D/2D viscous Burgers, Gray-Scott, scalar Helmholtz-Kerr.
+  Appendix A) — 1D/2D viscous Burgers, Gray-Scott, scalar Helmholtz-Kerr,
+  scalar u^3 reaction-diffusion with Dirichlet boundaries.
 * ``dual``: forward-mode dual numbers (the AD JVP of Section 2).
 * ``jvp``: AD and FD Jacobian-vector products and the FD step rules.
 * ``gmres``: restarted GMRES(m), CGS2 Arnoldi, Givens least squares.
 * ``bicgstab``: BiCGSTAB, the paper's short-recurrence nonsymmetric method.
+* ``cg``: conjugate gradients for the SPD reaction-diffusion linearization.
 * ``newton``: inexact Newton with backtracking line search and the
   failure classification of Section 3.4.
 
@@ -25,8 +27,9 @@ the paper does not fix: they are a reading, pinned only by the Armijo property
 (parity of the constants themselves unpinned).
 """
 
-from . import bicgstab, dual, gmres, jvp, newton, problems  # noqa: F401
+from . import bicgstab, cg, dual, gmres, jvp, newton, problems  # noqa: F401
 from .bicgstab import BicgstabInfo, bicgstab as bicgstab_solve  # noqa: F401
+from .cg import CgInfo, cg as cg_solve  # noqa: F401
 from .gmres import GmresInfo, gmres as gmres_solve  # noqa: F401
 from .jvp import EPS_MACH, EPS_NORMALIZED, EPS_PAPER, fd_step, jvp_ad, jvp_fd  # noqa: F401
 from .newton import NewtonInfo, NewtonOptions, newton_solve, run_failed, step_failed  # noqa: F401

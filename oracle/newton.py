@@ -25,6 +25,7 @@ import numpy as np
 
 from . import gmres as gm
 from .bicgstab import bicgstab
+from .cg import cg
 from .jvp import EPS_MACH, EPS_PAPER, fd_step, jvp_ad, jvp_fd
 from .problems import Problem, residual
 
@@ -47,7 +48,7 @@ class NewtonOptions:
     eps_mach: float = EPS_MACH["f64"]
     fd_eps: float = 0.0  # > 0: fixed FD step
     breakdown_tol: float = 1e-14
-    krylov: str = "gmres"  # 'gmres' | 'bicgstab' (its iteration cap: max_restarts)
+    krylov: str = "gmres"  # 'gmres' | 'bicgstab' | 'cg' (the last two capped at max_restarts iterations)
 
     @classmethod
     def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
@@ -114,6 +115,8 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
 
         if opts.krylov == "bicgstab":
             dx, ginfo = bicgstab(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+        elif opts.krylov == "cg":
+            dx, ginfo = cg(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
         else:
             dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
                                  max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol)

@@ -25,6 +25,12 @@ with |E|^2 = Re(E)^2 + Im(E)^2 written on the real and imaginary parts, so the
 residual is a polynomial in real unknowns and forward-mode AD differentiates
 through |E|^2 componentwise.
 
+The scalar reaction-diffusion problem (Section 3.2; Appendix A.3)
+u_t = D Lap u - u^3 with homogeneous Dirichlet conditions: N(u) = -D Lap u + u^3
+in the theta scheme above at the interior nodes, F = u at the boundary nodes
+(which hold the zero boundary value).  Its Jacobian on the interior nodes is
+I + theta dt (-D L + 3 diag(u^2)), symmetric positive definite.
+
 Layouts are those of the ``workloads`` module: 1D ``u[i]``; two-field 2D
 problems as two row-major planes of shape (ny, nx); Kerr as interleaved
 (re, im) pairs of shape (ny, nx, 2).
@@ -43,7 +49,7 @@ from .dual import Dual, concatenate, roll, stack_last
 class Problem:
     """A benchmark problem: kind, grid and physical parameters."""
 
-    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr'
+    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr' | 'rd2d'
     nx: int
     ny: int = 1
     hx: float = 1.0
@@ -51,7 +57,7 @@ class Problem:
     dt: float = 0.0
     theta: float = 1.0
     nu: float = 0.0  # Burgers viscosity
-    D: float = 0.0  # Gray-Scott diffusivity of u
+    D: float = 0.0  # Gray-Scott diffusivity of u; reaction-diffusion diffusivity
     Dv: float = 0.0  # Gray-Scott diffusivity of v
     F: float = 0.0  # Gray-Scott feed rate
     k: float = 0.0  # Gray-Scott kill rate
@@ -69,7 +75,7 @@ class Problem:
     def n(self) -> int:
         """Number of real unknowns."""
         cells = self.nx * self.ny
-        return cells if self.kind == "burgers1d" else 2 * cells
+        return cells if self.kind in ("burgers1d", "rd2d") else 2 * cells
 
     @property
     def is_ibvp(self) -> bool:
@@ -105,6 +111,8 @@ def split(p: Problem, x):
     """Flat state -> list of field arrays (or Duals)."""
     if p.kind == "burgers1d":
         return [x]
+    if p.kind == "rd2d":
+        return [x.reshape(p.ny, p.nx)]
     if p.kind == "kerr":
         e = x.reshape(p.ny, p.nx, 2)
         return [e[..., 0], e[..., 1]]
@@ -116,6 +124,8 @@ def join(p: Problem, parts):
     """List of field arrays -> flat state (inverse of ``split``)."""
     if p.kind == "burgers1d":
         return parts[0]
+    if p.kind == "rd2d":
+        return parts[0].ravel()
     if p.kind == "kerr":
         return stack_last(parts).ravel()
     return concatenate([parts[0].ravel(), parts[1].ravel()])
@@ -148,7 +158,13 @@ def N_grayscott(p: Problem, f):
             -p.Dv * lap(v, p) + uuv - p.F * (1.0 - v)]
 
 
-SPATIAL = {"burgers1d": N_burgers1d, "burgers2d": N_burgers2d, "grayscott": N_grayscott}
+def N_rd2d(p: Problem, f):
+    """Scalar reaction-diffusion: u_t = D Lap u - u^3 (Appendix A.3)."""
+    (u,) = f
+    return [-p.D * lap(u, p) + u * u * u]
+
+
+SPATIAL = {"burgers1d": N_burgers1d, "burgers2d": N_burgers2d, "grayscott": N_grayscott, "rd2d": N_rd2d}
 
 
 def N_apply(p: Problem, x):
@@ -200,6 +216,10 @@ def residual(p: Problem, x, x_prev, source=None):
         out = out + (p.dt * (1.0 - p.theta)) * N_apply(p, x_prev)
     if source is not None:
         out = out - p.dt * source
+    if p.kind == "rd2d":
+        # homogeneous Dirichlet: boundary nodes are identity rows
+        m = interior_mask(p).ravel()
+        out = m * out + (1.0 - m) * x
     return out
 
 

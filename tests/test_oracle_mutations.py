@@ -149,3 +149,46 @@ def test_bicgstab_mutations_fail_a_pin(monkeypatch, old, new):
         except AssertionError:
             failed += 1
     assert failed >= 1
+
+
+import oracle.cg as ocg  # noqa: E402
+import test_oracle_cg_rd as tc  # noqa: E402
+
+
+def _cg_mutant(old: str, new: str):
+    src = inspect.getsource(ocg)
+    assert old in src
+    ns: dict = {}
+    exec(compile(src.replace(old, new, 1), "cg_mutant", "exec"), ns)
+    return ns["cg"]
+
+
+@pytest.mark.parametrize("old,new", [
+    ("alpha = rr / pJp", "alpha = pJp / rr"),                      # inverted step length
+    ("r = r - alpha * Jp", "r = r + alpha * Jp"),                  # sign of the residual update
+    ("p = r + (rr_new / rr) * p", "p = r + (rr / rr_new) * p"),    # inverted beta
+    ("p = r + (rr_new / rr) * p", "p = r"),                        # steepest descent (dropped conjugation)
+    ("if pJp <= 0.0:", "if pJp < 0.0:"),                           # zero curvature not caught
+])
+def test_cg_mutations_fail_a_pin(monkeypatch, old, new):
+    monkeypatch.setattr(tc, "cg_solve", _cg_mutant(old, new))
+    failed = 0
+    for fn, args in ((tc.test_cg_dense_spd_solve, (80, 2)), (tc.test_cg_matches_scipy, (60, 4, 1e-8)),
+                     (tc.test_cg_reports_indefinite_breakdown, ())):
+        try:
+            fn(*args)
+        except (AssertionError, ZeroDivisionError, FloatingPointError):
+            failed += 1
+    assert failed >= 1
+
+
+def test_rd_sink_sign_wrong(monkeypatch):
+    monkeypatch.setitem(oprob.SPATIAL, "rd2d", lambda p, f: [-p.D * oprob.lap(f[0], p) - f[0] * f[0] * f[0]])
+    _expect_failure(tc.test_rd_residual_sine_modes_closed_form, 17, 13, 0.5)
+    _expect_failure(tc.test_rd_ad_jacobian_is_the_hand_derived_spd_matrix)
+
+
+def test_rd_boundary_not_held(monkeypatch):
+    orig = oprob.interior_mask
+    monkeypatch.setattr(oprob, "interior_mask", lambda p: np.ones_like(orig(p)))
+    _expect_failure(tc.test_rd_boundary_rows_are_identity)

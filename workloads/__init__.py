@@ -61,10 +61,22 @@ def kerr_spec(n: int = 1024, chi3: float = 0.1, eps_re: float = 1.0, eps_im: flo
                 k0=2.0 * math.pi / cells_per_wavelength, eps_re=eps_re, eps_im=eps_im, chi3=chi3)
 
 
+def rd2d_spec(n: int = 512, D: float = 0.01, C: float = 1.0, theta: float = 0.5, ny: int | None = None) -> dict:
+    """Scalar reaction-diffusion u_t = D Lap u - u^3 on the node grid of [0,1]^2.
+
+    Homogeneous Dirichlet boundary nodes, Crank-Nicolson, and the paper's
+    reaction-diffusion step rule dt = C h^2 / D (C = 1 by default).
+    """
+    ny = n if ny is None else ny
+    hx = 1.0 / (n - 1)
+    hy = 1.0 / (ny - 1)
+    return dict(kind="rd2d", nx=n, ny=ny, hx=hx, hy=hy, dt=C * hx * hx / D, theta=theta, D=D)
+
+
 def n_unknowns(spec: dict) -> int:
     """Number of real unknowns of a problem spec."""
     cells = spec["nx"] * spec["ny"]
-    return cells if spec["kind"] == "burgers1d" else 2 * cells
+    return cells if spec["kind"] in ("burgers1d", "rd2d") else 2 * cells
 
 
 # ---------------------------------------------------------------------------
@@ -170,6 +182,37 @@ def kerr_gaussian_source(n: int = 1024, amp: float = 0.1, sigma: float = 4.0,
     return out.ravel()
 
 
+def rd2d_initial(n: int = 512, seed: int = 0, profile: str = "multigauss", ny: int | None = None,
+                 k: int = 4) -> np.ndarray:
+    """Initial concentration of the reaction-diffusion problem, zero on the boundary nodes.
+
+    Profiles (the paper's three, Appendix A.3): ``gaussian`` (one peak at the
+    centre, sigma 0.1), ``multigauss`` (four peaks at seeded positions in
+    [0.2, 0.8]^2 with seeded widths in [0.05, 0.1]), ``sine``
+    (|sin(k pi x) sin(k pi y)|).  Unit amplitude.
+    """
+    ny = n if ny is None else ny
+    x = np.linspace(0.0, 1.0, n)[None, :]
+    y = np.linspace(0.0, 1.0, ny)[:, None]
+    if profile == "gaussian":
+        u = np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / (2 * 0.1 ** 2))
+    elif profile == "multigauss":
+        rng = np.random.default_rng(seed)
+        cx, cy = rng.uniform(0.2, 0.8, 4), rng.uniform(0.2, 0.8, 4)
+        sig = rng.uniform(0.05, 0.1, 4)
+        u = sum(np.exp(-((x - cx[q]) ** 2 + (y - cy[q]) ** 2) / (2 * sig[q] ** 2)) for q in range(4))
+    elif profile == "sine":
+        u = np.abs(np.sin(k * np.pi * x) * np.sin(k * np.pi * y))
+    else:
+        raise KeyError(profile)
+    u = np.array(u, dtype=np.float64) * np.ones((ny, n))
+    u[0, :] = 0.0
+    u[-1, :] = 0.0
+    u[:, 0] = 0.0
+    u[:, -1] = 0.0
+    return u.ravel()
+
+
 def random_vector(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """A seeded N(0, scale^2) vector (Krylov directions and generic test data)."""
     return scale * np.random.default_rng(seed).standard_normal(n)
@@ -184,7 +227,8 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
     """Return (spec, x_prev, source) for a named workload, optionally at another size.
 
     Names: ``burgers1d`` (N=256 by default), ``grayscott`` (1024^2),
-    ``burgers2d`` (2048^2), ``kerr`` (1024^2, chi3 = 0.1).
+    ``burgers2d`` (2048^2), ``kerr`` (1024^2, chi3 = 0.1), ``rd2d`` (512^2,
+    the paper's GPU reaction-diffusion grid, multi-Gaussian start).
     """
     if name == "burgers1d":
         nx = 256 if n is None else n
@@ -202,6 +246,10 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
         nn = 1024 if n is None else n
         spec = kerr_spec(nn)
         return spec, np.zeros(2 * nn * nn), kerr_gaussian_source(nn)
+    if name == "rd2d":
+        nn = 512 if n is None else n
+        spec = rd2d_spec(nn)
+        return spec, rd2d_initial(nn, seed), None
     raise KeyError(name)
 
 
