@@ -71,7 +71,8 @@ typedef enum {
   JFNK_BURGERS1D = 0,   /* u_t + u u_x = nu u_xx, periodic; n = nx (ny = 1) */
   JFNK_BURGERS2D = 1,   /* (U.grad)U = nu Lap U (Appendix A.1), periodic; n = 2 nx ny */
   JFNK_GRAYSCOTT2D = 2, /* two-species reaction-diffusion, periodic; n = 2 nx ny */
-  JFNK_KERR2D = 3       /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
+  JFNK_KERR2D = 3,      /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
+  JFNK_RD2D = 4         /* u_t = D Lap u - u^3 (Appendix A.3), Dirichlet nodes; n = nx ny */
 } jfnk_problem_id;
 
 /* Problem description.  Time-dependent problems use the theta scheme
@@ -79,9 +80,12 @@ typedef enum {
  * (theta = 1/2 is the paper's Crank-Nicolson, 1 is backward Euler) with
  * N(u) = u D_x u - nu D_xx u (1D Burgers), Adv(U) - nu Lap(U) (2D Burgers),
  * (-D Lap u - u^2 v + (F+k) u, -Dv Lap v + u^2 v - F (1 - v)) (Gray-Scott),
- * second-order central differences.  Kerr: F = -Lap E - k0^2 (eps_L +
- * chi3 |E|^2) E - f on interior nodes and F = E on the boundary nodes.
- *   p[]: Burgers {nu}; Gray-Scott {D, Dv, F, k}; Kerr {k0, eps_re, eps_im, chi3}.
+ * -D Lap u + u^3 (reaction-diffusion, interior nodes; F = u on the boundary
+ * nodes, which hold the homogeneous Dirichlet value), second-order central
+ * differences.  Kerr: F = -Lap E - k0^2 (eps_L + chi3 |E|^2) E - f on
+ * interior nodes and F = E on the boundary nodes.
+ *   p[]: Burgers {nu}; Gray-Scott {D, Dv, F, k}; Kerr {k0, eps_re, eps_im, chi3};
+ *   reaction-diffusion {D}.
  * Grid: nx columns (contiguous) by ny rows, spacings hx, hy; nx >= 3, and
  * ny >= 3 for 2D problems (ny = 1 for 1D Burgers). */
 typedef struct {
@@ -114,11 +118,13 @@ typedef struct {
 } jfnk_options;
 
 /* The Krylov method of each Newton step (paper, Section 2: GMRES(m) or
- * BiCGSTAB for nonsymmetric Jacobians).  BICGSTAB takes max_restarts as
- * its iteration cap (Section 3.3 gives both the same cap of 100), ignores m
- * and breakdown_tol, and runs on the MULTI_KERNEL engine in FP64 or FP32
- * with a solver created with m >= 5. */
-typedef enum { JFNK_KRYLOV_GMRES = 0, JFNK_KRYLOV_BICGSTAB = 1 } jfnk_krylov;
+ * BiCGSTAB for nonsymmetric Jacobians, CG for symmetric positive-definite
+ * ones such as the reaction-diffusion problem's).  BICGSTAB and CG take
+ * max_restarts as their iteration cap (Section 3.3 gives every method the
+ * same cap of 100), ignore m and breakdown_tol, and run on the MULTI_KERNEL
+ * engine in FP64 or FP32 with a solver created with m >= 5 (BiCGSTAB) or
+ * m >= 2 (CG). */
+typedef enum { JFNK_KRYLOV_GMRES = 0, JFNK_KRYLOV_BICGSTAB = 1, JFNK_KRYLOV_CG = 2 } jfnk_krylov;
 
 /* How jfnk_newton_solve runs the method (same algorithm, same options):
  *   AUTO:  SINGLE_WORKGROUP when the problem fits it, else MULTI_KERNEL;
@@ -202,6 +208,17 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
 jfnk_status jfnk_bicgstab(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters,
                           int mode, double eps, int eps_rule, jfnk_info* info);
 
+/* Solve J(x) dx = rhs by conjugate gradients (paper, Section 2: Hestenes
+ * and Stiefel's method, for symmetric positive-definite J) from dx = 0; one
+ * JVP per iteration; stops when ||r|| <= tol ||rhs||, after max_iters
+ * iterations, on (p, J p) <= 0 (J not positive definite along p: breakdown)
+ * or on a non-finite scalar.  Arguments, statuses and info as for
+ * jfnk_bicgstab (FP64 or FP32 solvers created with m >= 2; the solver's
+ * first three basis slots are its work vectors).  Synchronizes before
+ * returning. */
+jfnk_status jfnk_cg(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters, int mode,
+                    double eps, int eps_rule, jfnk_info* info);
+
 /* Newton with line search from x_inout (FP64 device array, overwritten with
  * the last iterate).  Returns JFNK_OK when converged, JFNK_ERR_NOT_CONVERGED
  * at the iteration cap, JFNK_ERR_NONFINITE on NaN/Inf; info is filled in all
@@ -224,7 +241,8 @@ const char* jfnk_last_error(const jfnk_solver* s);
  * kernel: 0 residual, 1 AD JVP, 2 FD JVP, 3 CGS pass A (V^T w), 4 CGS pass B
  * (update + dot), 5 CGS pass C (update + norm + Givens), 6 V y update,
  * 7 cycle start, 8 Newton trial update, 9 single-workgroup whole solve,
- * 10 BiCGSTAB streaming kernels (its JVPs count as 1 or 2).  Reports the
+ * 10 BiCGSTAB streaming kernels, 11 CG streaming kernels (the JVPs of both
+ * count as 1 or 2).  Reports the
  * launches timed since the last reset, their summed duration (ms) and their
  * algorithmic HBM bytes. */
 jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bicgstab.hpp"
+#include "cg.hpp"
 #include "common.hpp"
 #include "fused.hpp"
 #include "krylov.hpp"
@@ -16,7 +17,7 @@
 
 namespace jfnk {
 
-enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3 };
+enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4 };
 
 // Kernel timing: when the host driver sets g_timing around one launch, the
 // launch goes through hipExtLaunchKernelGGL with start/stop events attached
@@ -172,6 +173,11 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
 enum { BI_INIT = 0, BI_P = 1, BI_S = 2, BI_XR = 3 };
 template <class T>
 hipError_t launch_bi(int kind, const BiArgs<T>& a, double tol, int grid, hipStream_t s);
+
+// CG streaming kernels (cg.hpp) on `grid` blocks of kStreamThreads.
+enum { CG_INIT = 0, CG_P = 1, CG_XR = 2 };
+template <class T>
+hipError_t launch_cg(int kind, const CgArgs<T>& a, double tol, int grid, hipStream_t s);
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);

@@ -76,6 +76,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
       return stencil_for_problem<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kKerr:
       return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+    case kRD2D:
+      return stencil_for_problem<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;
   }
@@ -178,6 +180,26 @@ hipError_t launch_bi(int kind, const BiArgs<T>& a, double tol, int grid, hipStre
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_cg(int kind, const CgArgs<T>& a, double tol, int grid, hipStream_t s) {
+  constexpr int VEC = krylov_vec<T>();
+  const dim3 g(grid), b(kStreamThreads);
+  switch (kind) {
+    case CG_INIT:
+      JFNK_LAUNCH((cg_init_kernel<T, VEC>), g, b, s, a);
+      break;
+    case CG_P:
+      JFNK_LAUNCH((cg_p_kernel<T, VEC>), g, b, s, a, tol);
+      break;
+    case CG_XR:
+      JFNK_LAUNCH((cg_xr_kernel<T, VEC>), g, b, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class P, class T>
 static hipError_t fused_for_problem(const FusedArgs<T>& a, size_t lds, hipStream_t s) {
   const auto k = fused_solve_kernel<P, T>;
@@ -199,6 +221,8 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
       return fused_for_problem<GrayScottOp, T>(a, lds, s);
     case kKerr:
       return fused_for_problem<KerrOp, T>(a, lds, s);
+    case kRD2D:
+      return fused_for_problem<RD2DOp, T>(a, lds, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -218,6 +242,7 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
   template hipError_t launch_norm2<T>(long long, const T*, PartSink, int, hipStream_t);                         \
   template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);                                     \
   template hipError_t launch_fused_solve<T>(int, const FusedArgs<T>&, size_t, hipStream_t);                 \
-  template hipError_t launch_bi<T>(int, const BiArgs<T>&, double, int, hipStream_t);
+  template hipError_t launch_bi<T>(int, const BiArgs<T>&, double, int, hipStream_t);                        \
+  template hipError_t launch_cg<T>(int, const CgArgs<T>&, double, int, hipStream_t);
 
 }  // namespace jfnk

@@ -12,6 +12,8 @@
 //   Gray-Scott:   N = (-D Lap u - u^2 v + (F+k) u, -Dv Lap v + u^2 v - F (1-v))
 //   Kerr:         N = -Lap E - k0^2 (eps_L + chi3 |E|^2) E on (re, im),
 //                 |E|^2 = re^2 + im^2; PEC boundary nodes are identity rows.
+//   RD:           N = -D Lap u + u^3                    (Appendix A.3)
+//                 homogeneous Dirichlet boundary nodes are identity rows.
 #pragma once
 
 #include "common.hpp"
@@ -133,6 +135,31 @@ struct KerrOp {
     const S a = k.er + k.chi * (re.c * re.c + im.c * im.c);
     out[0] = -lre - k.k2 * (a * re.c - k.ei * im.c);
     out[1] = -lim - k.k2 * (a * im.c + k.ei * re.c);
+  }
+  __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
+    return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+  }
+};
+
+struct RD2DOp {
+  static constexpr int NF = 1;
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = false;
+  static constexpr bool kInterleaved = false;
+  // c: 0 = D/hx^2, 1 = D/hy^2
+  template <class T>
+  struct K {
+    T dx, dy;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[1], S (&out)[1]) {
+    const Nbr<S>& u = f[0];
+    const S lu = k.dx * ((u.r - T(2) * u.c) + u.l) + k.dy * ((u.u - T(2) * u.c) + u.d);
+    out[0] = (u.c * u.c) * u.c - lu;
   }
   __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
     return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;

@@ -32,10 +32,10 @@ thread_local KernelTiming* g_timing = nullptr;
 
 namespace {
 
-constexpr int kNumProf = 11;
+constexpr int kNumProf = 12;
 enum ProfKernel {
   PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8, PK_FUSED = 9,
-  PK_BI = 10
+  PK_BI = 10, PK_CG = 11
 };
 
 struct ProfRec {
@@ -88,6 +88,8 @@ struct jfnk_solver {
   FusedInfo* hinfo = nullptr;   // pinned host copy
   BiCtl* dbi = nullptr;         // BiCGSTAB scalars (device)
   BiCtl* hbi = nullptr;         // pinned host copy
+  CgCtl* dcg = nullptr;         // CG scalars (device)
+  CgCtl* hcg = nullptr;         // pinned host copy
   bool has_prev = false;
   std::string err;
   bool prof = false;
@@ -580,6 +582,86 @@ struct Impl {
     return JFNK_OK;
   }
 
+  // Conjugate gradients on J(x) dx = sign * R (R internal, padded) from
+  // dx = 0, dx internal; r, p, q = J p occupy basis slots 0..2.  The host
+  // loop and the flag protocol are those of bicgstab() with three kernels per
+  // iteration.
+  static jfnk_status cg(jfnk_solver* s, const T* x, const T* R, double sign, double tol, int maxiter, int mode,
+                        double fixed_eps, int eps_rule, BOut& bo) {
+    static_assert(std::is_same<T, VT>::value, "CG keeps its vectors in the working precision");
+    bo = BOut{};
+    T* r = basis(s, 0);
+    T* p = basis(s, 1);
+    T* q = basis(s, 2);
+    const int sgrid = stream_grid(s, KVEC);
+    CgArgs<T> a{};
+    a.n = s->npad;
+    a.c = s->dcg;
+    a.R = R;
+    a.sign = sign;
+    a.r = r;
+    a.p = p;
+    a.q = q;
+    a.x = static_cast<T*>(s->dx);
+    a.host_flags = s->dflags;
+    EpsSpec eps_p = eps_spec(s, fixed_eps, eps_rule, nullptr);
+    if (eps_rule == JFNK_EPS_NORMALIZED) eps_p.vparts = parts(s, 1, sgrid);  // ||p||^2 from the p kernel
+    const double vec_bytes = (double)s->n * sizeof(T);
+    // partial-sum regions: 0 xr / init, 1 p, 2 JVP
+    s->cur_step = -1;
+    a.out = sink(s, 0);
+    {
+      ProfScope ps(s, PK_CG, 3.0 * vec_bytes);
+      JFNK_HIP(s, launch_cg<T>(CG_INIT, a, tol, sgrid, s->stream));
+    }
+    volatile int* flags = reinterpret_cast<volatile int*>(s->hflags);
+    constexpr int kRing = kMaxM + 1;
+    int last = 0;
+    for (int it = 1; it <= maxiter; ++it) {
+      s->cur_step = it - 1;
+      a.it = it;
+      a.check_only = 0;
+      a.flag_slot = it % kRing;
+      flags[a.flag_slot] = -1;
+      a.in = parts(s, 0, sgrid);
+      a.out = sink(s, 1);
+      {
+        ProfScope ps(s, PK_CG, (it == 1 ? 2.0 : 3.0) * vec_bytes);
+        JFNK_HIP(s, launch_cg<T>(CG_P, a, tol, sgrid, s->stream));
+      }
+      int nb_q = 0;
+      JFNK_TRY(jvp_bi(s, x, p, q, mode, eps_p, p, 2, &s->dcg->state_p, Partials{nullptr, 0, 0}, nullptr, &nb_q));
+      a.in = parts(s, 2, nb_q);
+      a.out = sink(s, 0);
+      {
+        ProfScope ps(s, PK_CG, 6.0 * vec_bytes);
+        JFNK_HIP(s, launch_cg<T>(CG_XR, a, tol, sgrid, s->stream));
+      }
+      last = it;
+      if (it >= 2) {
+        const int ps = (it - 1) % kRing;
+        if (!wait_flag(s, flags, ps) || flags[ps] != kRunning) break;
+      }
+    }
+    s->cur_step = -1;
+    a.it = last + 1;
+    a.check_only = 1;
+    a.flag_slot = (last + 1) % kRing;
+    a.in = parts(s, 0, sgrid);
+    JFNK_HIP(s, launch_cg<T>(CG_P, a, tol, sgrid, s->stream));
+    JFNK_HIP(s, hipMemcpyAsync(s->hcg, s->dcg, sizeof(CgCtl), hipMemcpyDeviceToHost, s->stream));
+    JFNK_HIP(s, hipStreamSynchronize(s->stream));
+    const CgCtl& h = *s->hcg;
+    if (s->prof) prof_harvest(s, h.iters + 1);
+    bo.iters = h.iters;
+    bo.bnorm = h.bnorm;
+    bo.res = h.res;
+    bo.converged = h.state_p == kConverged;
+    bo.nonfinite = h.state_p == kNonfinite;
+    bo.breakdown = h.state_p == kBreakdown;
+    return JFNK_OK;
+  }
+
   // The whole solve in one workgroup (small problems, FP64/FP32).
   static bool fused_fits(const jfnk_solver* s, int m) {
     return std::is_same<T, VT>::value && fused_lds_bytes<T>(s->n, m) <= s->lds_max;
@@ -680,11 +762,15 @@ struct Impl {
         break;
       }
       GOut go;
-      if (o.krylov == JFNK_KRYLOV_BICGSTAB) {
+      if (o.krylov == JFNK_KRYLOV_BICGSTAB || o.krylov == JFNK_KRYLOV_CG) {
         if constexpr (std::is_same<T, VT>::value) {
           BOut bo;
-          JFNK_TRY(bicgstab(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.tol_krylov, o.max_restarts, o.mode,
-                            o.fd_eps, o.eps_rule, bo));
+          if (o.krylov == JFNK_KRYLOV_BICGSTAB)
+            JFNK_TRY(bicgstab(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.tol_krylov, o.max_restarts, o.mode,
+                              o.fd_eps, o.eps_rule, bo));
+          else
+            JFNK_TRY(cg(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.tol_krylov, o.max_restarts, o.mode,
+                        o.fd_eps, o.eps_rule, bo));
           go.iters = bo.iters;
           go.nonfinite = bo.nonfinite;
         }
@@ -766,6 +852,10 @@ jfnk_status fill_problem(jfnk_solver* s) {
       c.c[4] = p.p[2] + p.p[3];
       c.c[5] = p.p[2];
       break;
+    case JFNK_RD2D:
+      c.c[0] = p.p[0] / (p.hx * p.hx);
+      c.c[1] = p.p[0] / (p.hy * p.hy);
+      break;
     case JFNK_KERR2D:
       c.c[0] = 1.0 / (p.hx * p.hx);
       c.c[1] = 1.0 / (p.hy * p.hy);
@@ -795,7 +885,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
     if (why) *why = "null problem";
     return false;
   }
-  if (p->id < JFNK_BURGERS1D || p->id > JFNK_KERR2D) {
+  if (p->id < JFNK_BURGERS1D || p->id > JFNK_RD2D) {
     if (why) *why = "unknown problem id";
     return false;
   }
@@ -820,7 +910,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
 
 long long problem_n(const jfnk_problem* p) {
   const long long cells = (long long)p->nx * p->ny;
-  return p->id == JFNK_BURGERS1D ? cells : 2 * cells;
+  return (p->id == JFNK_BURGERS1D || p->id == JFNK_RD2D) ? cells : 2 * cells;
 }
 
 // Upper bound on the blocks of any reducing launch: persistent stencil
@@ -839,7 +929,7 @@ size_t footprint(const jfnk_problem* p, int prec, int m, int cu) {
   bytes += 8 * (size_t)npad * t;                            // w R dx F Ft xw xwt b
   bytes += 3 * (size_t)npad * 8;                            // x64 x64t tmp64
   bytes += 6 * max_blocks(p, cu) * kMaxCols * 8;            // partial sums
-  bytes += sizeof(Ctl) + sizeof(FusedInfo) + sizeof(BiCtl);
+  bytes += sizeof(Ctl) + sizeof(FusedInfo) + sizeof(BiCtl) + sizeof(CgCtl);
   return bytes;
 }
 
@@ -869,6 +959,8 @@ void release(jfnk_solver* s) {
   if (s->hinfo) (void)hipHostFree(s->hinfo);
   if (s->dbi) (void)hipFree(s->dbi);
   if (s->hbi) (void)hipHostFree(s->hbi);
+  if (s->dcg) (void)hipFree(s->dcg);
+  if (s->hcg) (void)hipHostFree(s->hcg);
   for (hipEvent_t e : s->pool)
     if (e) (void)hipEventDestroy(e);
   for (ProfRec& r : s->recs) {
@@ -924,13 +1016,16 @@ jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, do
   return go.nonfinite ? JFNK_ERR_NONFINITE : JFNK_OK;
 }
 template <class T>
-jfnk_status bicgstab_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, double tol, int max_iters, int mode,
-                         double eps, int rule, jfnk_info* info) {
+jfnk_status short_recurrence_api(jfnk_solver* s, int krylov, const T* x, const T* rhs, T* dx, double tol,
+                                 int max_iters, int mode, double eps, int rule, jfnk_info* info) {
   const long long n = s->n;
   JFNK_HIP(s, hipMemcpyAsync(s->R, rhs, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
   typename Impl<T, T>::BOut bo;
-  JFNK_TRY(Impl<T, T>::bicgstab(s, x, static_cast<const T*>(s->R), 1.0, tol, max_iters, mode, eps, rule, bo));
+  if (krylov == JFNK_KRYLOV_CG)
+    JFNK_TRY(Impl<T, T>::cg(s, x, static_cast<const T*>(s->R), 1.0, tol, max_iters, mode, eps, rule, bo));
+  else
+    JFNK_TRY(Impl<T, T>::bicgstab(s, x, static_cast<const T*>(s->R), 1.0, tol, max_iters, mode, eps, rule, bo));
   JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   JFNK_HIP(s, hipStreamSynchronize(s->stream));
   const jfnk_status st = bo.nonfinite ? JFNK_ERR_NONFINITE : (bo.breakdown ? JFNK_ERR_BREAKDOWN : JFNK_OK);
@@ -944,17 +1039,50 @@ jfnk_status bicgstab_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, double
   return st;
 }
 
-// BiCGSTAB keeps r^, r, p, v, s, t in the first six basis slots.
-bool bicgstab_fits(const jfnk_solver* s, std::string* why) {
+// BiCGSTAB keeps r^, r, p, v, s, t in the first six basis slots, CG r, p,
+// J p in the first three.
+bool short_recurrence_fits(const jfnk_solver* s, int krylov, std::string* why) {
+  const char* name = krylov == JFNK_KRYLOV_CG ? "CG" : "BiCGSTAB";
   if (s->prec == JFNK_F16S) {
-    *why = "BiCGSTAB runs in FP64 or FP32 (FP16 storage applies to the GMRES basis only)";
+    *why = std::string(name) + " runs in FP64 or FP32 (FP16 storage applies to the GMRES basis only)";
     return false;
   }
-  if (s->m < 5) {
-    *why = "BiCGSTAB needs a solver created with m >= 5 (six work vectors)";
+  const int need = krylov == JFNK_KRYLOV_CG ? 2 : 5;
+  if (s->m < need) {
+    *why = std::string(name) + " needs a solver created with m >= " + std::to_string(need) + " (" +
+           std::to_string(need + 1) + " work vectors)";
     return false;
   }
   return true;
+}
+}  // namespace
+
+namespace {
+jfnk_status short_recurrence_entry(jfnk_solver* s, int krylov, const void* x, const void* rhs, void* dx,
+                                   double tol, int max_iters, int mode, double eps, int eps_rule, jfnk_info* info) {
+  if (!s || !x || !rhs || !dx) return JFNK_ERR_ARG;
+  if (max_iters < 0 || !(tol >= 0.0)) {
+    s->err = "max_iters >= 0 and tol >= 0 are required";
+    return JFNK_ERR_ARG;
+  }
+  if ((mode != JFNK_JVP_AD && mode != JFNK_JVP_FD) || (eps_rule != JFNK_EPS_PAPER && eps_rule != JFNK_EPS_NORMALIZED))
+    return JFNK_ERR_ARG;
+  if (!s->has_prev) {
+    s->err = "jfnk_set_previous must be called first";
+    return JFNK_ERR_ARG;
+  }
+  if (!short_recurrence_fits(s, krylov, &s->err)) return JFNK_ERR_ARG;
+  if (info) std::memset(info, 0, sizeof(*info));
+  const auto t0 = std::chrono::steady_clock::now();
+  jfnk_status st;
+  if (s->prec == JFNK_F64)
+    st = short_recurrence_api<double>(s, krylov, (const double*)x, (const double*)rhs, (double*)dx, tol, max_iters,
+                                      mode, eps, eps_rule, info);
+  else
+    st = short_recurrence_api<float>(s, krylov, (const float*)x, (const float*)rhs, (float*)dx, tol, max_iters,
+                                     mode, eps, eps_rule, info);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
 }
 }  // namespace
 
@@ -1064,6 +1192,16 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   if (st == JFNK_OK) st = malloc_dev(s, &s->ctl, sizeof(Ctl));
   if (st == JFNK_OK) st = malloc_dev(s, &s->dinfo, sizeof(FusedInfo));
   if (st == JFNK_OK) st = malloc_dev(s, &s->dbi, sizeof(BiCtl));
+  if (st == JFNK_OK) st = malloc_dev(s, &s->dcg, sizeof(CgCtl));
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(CgCtl), hipHostMallocDefault) != hipSuccess) {
+      s->err = "hipHostMalloc (CG scalars) failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hcg = static_cast<CgCtl*>(h);
+    }
+  }
   if (st == JFNK_OK) {
     void* h = nullptr;
     if (hipHostMalloc(&h, sizeof(BiCtl), hipHostMallocDefault) != hipSuccess) {
@@ -1236,31 +1374,15 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
   return st;
 }
 
+
 jfnk_status jfnk_bicgstab(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters,
                           int mode, double eps, int eps_rule, jfnk_info* info) {
-  if (!s || !x || !rhs || !dx) return JFNK_ERR_ARG;
-  if (max_iters < 0 || !(tol >= 0.0)) {
-    s->err = "max_iters >= 0 and tol >= 0 are required";
-    return JFNK_ERR_ARG;
-  }
-  if ((mode != JFNK_JVP_AD && mode != JFNK_JVP_FD) || (eps_rule != JFNK_EPS_PAPER && eps_rule != JFNK_EPS_NORMALIZED))
-    return JFNK_ERR_ARG;
-  if (!s->has_prev) {
-    s->err = "jfnk_set_previous must be called first";
-    return JFNK_ERR_ARG;
-  }
-  if (!bicgstab_fits(s, &s->err)) return JFNK_ERR_ARG;
-  if (info) std::memset(info, 0, sizeof(*info));
-  const auto t0 = std::chrono::steady_clock::now();
-  jfnk_status st;
-  if (s->prec == JFNK_F64)
-    st = bicgstab_api<double>(s, (const double*)x, (const double*)rhs, (double*)dx, tol, max_iters, mode, eps,
-                              eps_rule, info);
-  else
-    st = bicgstab_api<float>(s, (const float*)x, (const float*)rhs, (float*)dx, tol, max_iters, mode, eps, eps_rule,
-                             info);
-  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return st;
+  return short_recurrence_entry(s, JFNK_KRYLOV_BICGSTAB, x, rhs, dx, tol, max_iters, mode, eps, eps_rule, info);
+}
+
+jfnk_status jfnk_cg(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters, int mode,
+                    double eps, int eps_rule, jfnk_info* info) {
+  return short_recurrence_entry(s, JFNK_KRYLOV_CG, x, rhs, dx, tol, max_iters, mode, eps, eps_rule, info);
 }
 
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts, jfnk_info* info) {
@@ -1270,11 +1392,11 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
       o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
       (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0) ||
       o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP ||
-      (o.krylov != JFNK_KRYLOV_GMRES && o.krylov != JFNK_KRYLOV_BICGSTAB)) {
+      o.krylov < JFNK_KRYLOV_GMRES || o.krylov > JFNK_KRYLOV_CG) {
     s->err = "invalid options";
     return JFNK_ERR_ARG;
   }
-  if (o.krylov == JFNK_KRYLOV_BICGSTAB && !bicgstab_fits(s, &s->err)) return JFNK_ERR_ARG;
+  if (o.krylov != JFNK_KRYLOV_GMRES && !short_recurrence_fits(s, o.krylov, &s->err)) return JFNK_ERR_ARG;
   if (!s->has_prev) {
     s->err = "jfnk_set_previous must be called first";
     return JFNK_ERR_ARG;

@@ -17,16 +17,16 @@ LIB_PATH = os.path.join(HERE, "libjfnk.so")
 
 MAX_ITERS = 64
 
-PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3}
+PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d": 4}
 PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
 ENGINES = {"auto": 0, "multi": 1, "single": 2}
-KRYLOV = {"gmres": 0, "bicgstab": 1}
+KRYLOV = {"gmres": 0, "bicgstab": 1, "cg": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
           5: "breakdown", 6: "not_converged"}
 PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
-                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9, "bicgstab": 10}
+                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9, "bicgstab": 10, "cg": 11}
 
 
 class Problem(ctypes.Structure):
@@ -101,6 +101,9 @@ _SIGNATURES = [
     ("jfnk_bicgstab", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                      ctypes.POINTER(Info)]),
+    ("jfnk_cg", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                               ctypes.POINTER(Info)]),
     ("jfnk_newton_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
                                          ctypes.POINTER(Info)]),
     ("jfnk_default_options", None, [ctypes.c_int, ctypes.POINTER(Options)]),
@@ -158,6 +161,8 @@ def make_problem(spec: dict) -> Problem:
         vals = [spec["nu"]]
     elif kind == "grayscott":
         vals = [spec["D"], spec["Dv"], spec["F"], spec["k"]]
+    elif kind == "rd2d":
+        vals = [spec["D"]]
     else:
         vals = [spec["k0"], spec.get("eps_re", 1.0), spec.get("eps_im", 0.0), spec["chi3"]]
     for i, v in enumerate(vals):
@@ -274,13 +279,19 @@ class Solver:
 
     def bicgstab(self, x, rhs, tol=1e-8, max_iters=100, mode="ad", eps=0.0, eps_rule="paper"):
         """BiCGSTAB solve of J(x) dx = rhs; returns (dx, info dict with 'breakdown')."""
+        return self._short_recurrence(lib().jfnk_bicgstab, x, rhs, tol, max_iters, mode, eps, eps_rule)
+
+    def cg(self, x, rhs, tol=1e-8, max_iters=100, mode="ad", eps=0.0, eps_rule="paper"):
+        """Conjugate-gradient solve of J(x) dx = rhs (SPD J); returns (dx, info dict with 'breakdown')."""
+        return self._short_recurrence(lib().jfnk_cg, x, rhs, tol, max_iters, mode, eps, eps_rule)
+
+    def _short_recurrence(self, fn, x, rhs, tol, max_iters, mode, eps, eps_rule):
         x = self._vec(x, self.wdtype, "x")
         rhs = self._vec(rhs, self.wdtype, "rhs")
         dx = self._new()
         info = Info()
-        rc = self._check(lib().jfnk_bicgstab(self._h, x.data_ptr(), rhs.data_ptr(), dx.data_ptr(), float(tol),
-                                             int(max_iters), MODES[mode], float(eps), EPS_RULES[eps_rule],
-                                             ctypes.byref(info)), allowed=(0, 4, 5))
+        rc = self._check(fn(self._h, x.data_ptr(), rhs.data_ptr(), dx.data_ptr(), float(tol), int(max_iters),
+                            MODES[mode], float(eps), EPS_RULES[eps_rule], ctypes.byref(info)), allowed=(0, 4, 5))
         d = info.as_dict()
         d["converged"] = bool(info.converged)
         d["breakdown"] = rc == 5
