@@ -383,6 +383,33 @@ def bicgstab_rows(torch, spec, xp, x0, steps, budget_s=8.0):
     return rows
 
 
+def rd_rows(torch, steps, budget_s=3.0):
+    """The paper's SPD problem (u^3 reaction-diffusion, 512^2, Crank-Nicolson, paper FD step):
+    Newton with CG, BiCGSTAB and GMRES(30), AD and FD, FP32 and FP64."""
+    import workloads as W
+
+    spec, xp, _ = W.config("rd2d")
+    x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
+    rows = {}
+    for pr in ("f32", "f64"):
+        sv = make_solver(spec, pr, xp, torch)
+        for kr in ("cg", "bicgstab", "gmres"):
+            for mode in ("ad", "fd"):
+                o = dict(mode=mode, eps_rule="paper", krylov=kr)
+                run_solves(sv, x0, torch, 1, o)
+                cnt, t_all, inf = 0, 0.0, None
+                while t_all < budget_s and cnt < steps:
+                    el, _, inf = run_solves(sv, x0, torch, 1, o)
+                    t_all += el
+                    cnt += 1
+                rows[f"{pr}-{kr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
+                                                 newton_iters=inf["newton_iters"], lin_iters=inf["lin_iters"],
+                                                 converged=inf["converged"], final_rel_res=inf["rel_res"][-1])
+                log(f"[bench] rd2d 512^2 {pr}-{kr}-{mode}: {rows[f'{pr}-{kr}-{mode}']}")
+        sv.close()
+    return rows
+
+
 def cpu_baseline(spec, xp, prec):
     """The oracle, single-threaded, on one full Newton solve of the same workload."""
     try:
@@ -431,6 +458,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
     ap.add_argument("--no-latency", action="store_true", help="skip the 1D Burgers N=256 latency rows")
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
+    ap.add_argument("--no-rd", action="store_true", help="skip the reaction-diffusion Krylov-method rows")
     ap.add_argument("--kerr-newton", action="store_true",
                     help="run the Helmholtz-Kerr 1024^2 Newton completion rows (minutes)")
     ap.add_argument("--completion-seeds", type=int, default=64,
@@ -581,6 +609,11 @@ def main():
         log("[bench] Newton-BiCGSTAB rows (Gray-Scott 1024^2)")
         bicg = bicgstab_rows(torch, spec, xp, x0, args.steps)
 
+    rd = None
+    if not args.no_rd:
+        log("[bench] reaction-diffusion 512^2 rows (CG / BiCGSTAB / GMRES)")
+        rd = rd_rows(torch, args.steps)
+
     c3 = None
     if args.completion_seeds > 0:
         log(f"[bench] completion sweep: 2D Burgers 2048^2, 10 steps, {args.completion_seeds} seeds")
@@ -635,6 +668,7 @@ def main():
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
         "bicgstab_newton": bicg,
+        "reaction_diffusion_512": rd,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,
