@@ -49,6 +49,7 @@ class NewtonOptions:
     fd_eps: float = 0.0  # > 0: fixed FD step
     breakdown_tol: float = 1e-14
     krylov: str = "gmres"  # 'gmres' | 'bicgstab' | 'cg' (the last two capped at max_restarts iterations)
+    orth: str = "cgs2"  # GMRES Gram-Schmidt: 'cgs2' or 'dcgs2' (second pass delayed one step)
 
     @classmethod
     def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
@@ -119,7 +120,7 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
             dx, ginfo = cg(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
         else:
             dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
-                                 max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol)
+                                 max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol, orth=opts.orth)
             info.restarts += ginfo.cycles
         info.krylov_iters += ginfo.iters
         info.lin_iters.append(ginfo.iters)

@@ -192,3 +192,34 @@ def test_rd_boundary_not_held(monkeypatch):
     orig = oprob.interior_mask
     monkeypatch.setattr(oprob, "interior_mask", lambda p: np.ones_like(orig(p)))
     _expect_failure(tc.test_rd_boundary_rows_are_identity)
+
+
+def _dcgs2_mutant(monkeypatch, old: str, new: str):
+    src = inspect.getsource(ogm)
+    assert old in src
+    ns: dict = {}
+    exec(compile(src.replace(old, new, 1), "gmres_mutant", "exec"), ns)
+    monkeypatch.setattr(tg, "gmres_solve", ns["gmres"])
+
+
+@pytest.mark.parametrize("old,new", [
+    ("vj = vj - ah[i] * V[i]", "vj = vj + ah[i] * V[i]"),          # sign of the reorthogonalization
+    ("h[:j] = b - Ha[:j]", "h[:j] = b"),                            # Arnoldi-relation term dropped
+    ("u = w - gamma * uh", "u = w + gamma * uh"),                   # sign of the projection on u^
+    ("a = np.array([np.dot(V[i], u) for i in range(col + 1)])",
+     "a = np.array([np.dot(V[i], u) for i in range(col)] + [0.0])"),  # second pass misses the newest vector
+    ("Hraw[: j + 1, j] = h", "Hraw[: j + 1, j] = -h"),              # sign of the stored column
+    ("u = u - (Ha[i] + h[i] - gamma * ah[i]) * V[i]", "u = u - (h[i] - gamma * ah[i]) * V[i]"),  # dropped term
+])
+def test_dcgs2_mutations_fail_a_pin(monkeypatch, old, new):
+    # (the second-pass coefficients a vanish in exact arithmetic, so mistakes confined to
+    # how they enter H or beta change results only at rounding level and no pin can see them)
+    _dcgs2_mutant(monkeypatch, old, new)
+    failed = 0
+    for fn, args in ((tg.test_dcgs2_single_cycle_equals_cgs2, (25, 2)),
+                     (tg.test_dcgs2_keeps_orthogonality_where_one_pass_loses_it, ())):
+        try:
+            fn(*args)
+        except (AssertionError, ValueError, ZeroDivisionError):
+            failed += 1
+    assert failed >= 1
