@@ -115,7 +115,21 @@ typedef struct {
                             receives every Newton iterate x_k (k = 0, 1, ...) */
   int engine;            /* jfnk_engine */
   int krylov;            /* jfnk_krylov: the linear solver of each Newton step */
+  int orth;              /* jfnk_orth: Gram-Schmidt form of GMRES on the MULTI_KERNEL engine */
 } jfnk_options;
+
+/* Gram-Schmidt form of the GMRES Arnoldi step (the paper fixes none; both
+ * orthogonalize twice):
+ *   CGS2:  w = J v_j is projected on the basis twice, in three passes over
+ *          it (the first fused into the JVP);
+ *   DCGS2: the second projection of each new vector is delayed by one step
+ *          and fused into the next step's passes (its norm follows from
+ *          ||u||^2 - ||V^T u||^2, the next JVP is applied to the once-
+ *          projected vector and corrected through the Arnoldi relation):
+ *          two passes over the basis per step.  Same basis and Hessenberg
+ *          matrix in exact arithmetic.  FP64 and FP32 only (FP16 storage
+ *          keeps CGS2); the SINGLE_WORKGROUP engine always runs CGS2. */
+typedef enum { JFNK_ORTH_CGS2 = 0, JFNK_ORTH_DCGS2 = 1 } jfnk_orth;
 
 /* The Krylov method of each Newton step (paper, Section 2: GMRES(m) or
  * BiCGSTAB for nonsymmetric Jacobians, CG for symmetric positive-definite
@@ -226,6 +240,11 @@ jfnk_status jfnk_cg(jfnk_solver* s, const void* x, const void* rhs, void* dx, do
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts,
                               jfnk_info* info);
 
+/* Gram-Schmidt form (jfnk_orth) of later jfnk_gmres calls on this solver
+ * (default CGS2); jfnk_newton_solve takes it from its options instead.
+ * DCGS2 on an FP16S solver returns JFNK_ERR_ARG. */
+jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth);
+
 /* Move a solver to another stream (a hipStream_t; NULL = the default stream)
  * for its later calls.  The caller orders any work still pending on the old
  * stream (the solver keeps no pointer to it). */
@@ -242,7 +261,7 @@ const char* jfnk_last_error(const jfnk_solver* s);
  * (update + dot), 5 CGS pass C (update + norm + Givens), 6 V y update,
  * 7 cycle start, 8 Newton trial update, 9 single-workgroup whole solve,
  * 10 BiCGSTAB streaming kernels, 11 CG streaming kernels (the JVPs of both
- * count as 1 or 2).  Reports the
+ * count as 1 or 2), 12 update pass of the DCGS2 Arnoldi step.  Reports the
  * launches timed since the last reset, their summed duration (ms) and their
  * algorithmic HBM bytes. */
 jfnk_status jfnk_profile_enable(jfnk_solver* s, int on);

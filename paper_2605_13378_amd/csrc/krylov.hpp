@@ -133,6 +133,55 @@ __device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Pa
   return out;
 }
 
+// Delayed second pass (the alternative Arnoldi form): column c is completed
+// by the kernel after the update pass of step c, from that pass's partial
+// sums pd = [V_0..V_c . u, u . u] of the pending vector u (once projected):
+// a = V^T u, beta = sqrt(u.u - a.a), column = (first projection + a, beta),
+// then the Givens update as for CGS2.  Block 0 commits the unrotated column,
+// the rotation, a / beta and 1 / beta (the tangent scale of step c + 1).
+__device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, const Partials& pd, int* host_flags,
+                                                 double* col) {
+  __shared__ double tot[kMaxM + 2];
+  __shared__ GivensIn in;
+  __shared__ GivensOut out;
+  __shared__ double ucol[kMaxM + 2];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int ld = kMaxM + 1;
+  if (tid <= c) in.h[tid] = ctl->Hu[c * ld + tid];
+  if (tid < c) {
+    in.cs[tid] = ctl->cs[tid];
+    in.sn[tid] = ctl->sn[tid];
+  }
+  if (tid == 0) {
+    in.gp = ctl->gp[c];
+    in.tol_abs = ctl->tol_abs;
+    in.brk_tol = ctl->brk_tol;
+    in.jvn2 = ctl->jvn2c[c];
+    in.sig = 1.0;
+  }
+  reduce_partials(pd, c + 2, tot);  // ends with a barrier: `in` is complete too
+  if (tid == 0) {
+    double aa = 0.0;
+    for (int i = 0; i <= c; ++i) aa += tot[i] * tot[i];
+    const double uu = tot[c + 1];
+    const double b2 = uu - aa;
+    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    for (int i = 0; i <= c; ++i) in.h[i] += tot[i];
+    out = givens_column(in, c, b2 > 0.0 ? b2 : 0.0, col);  // its norm is sqrt(b2) = beta
+    if (!isfinite(uu)) out.done = kNonfinite;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      for (int i = 0; i <= c; ++i) ucol[i] = in.h[i];
+      ucol[c + 1] = beta;
+      givens_commit(ctl, c, out, col, host_flags);
+      for (int i = 0; i <= c + 1; ++i) ctl->Hu[c * ld + i] = ucol[i];
+      for (int i = 0; i <= c; ++i) ctl->ahat[i] = tot[i] / beta;
+      ctl->tscale[c + 1] = out.vs;
+    }
+  }
+  __syncthreads();
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // CGS passes
 // ---------------------------------------------------------------------------
@@ -304,6 +353,129 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   block_partials<KMAX + 1>(acc, nr, a.out.part, a.out.ld, lds);
 }
 
+// Update pass of the delayed-second-pass Arnoldi step j (K = j + 1 slots:
+// final V_0..V_{j-1} and the pending U_j, the JVP tangent of step j, with
+// w = J (tscale_j U_j) from the Arnoldi JVP).  With a^ the second-pass
+// coefficients of U_j and H the completed columns 0..j-1, every block forms in
+// FP64 from the JVP's partial sums P = [V_0..V_j . w, w . w]:
+//   b_i = P_i (i < j), d = tscale_j P_j, gamma = d - a^.b,
+//   h_i = b_i - (H a^)_i, h_j = gamma - (H a^)_j        (first projection of J v_j)
+// and streams
+//   V_j     <- tscale_j U_j - sum_i a^_i V_i           (v_j, unit norm)
+//   U_{j+1} <- w - sum_i ((H a^)_i + h_i - gamma a^_i) V_i - gamma tscale_j U_j
+// with partial sums [V_0..V_j . U_{j+1}, ||U_{j+1}||^2] for the next column's
+// completion.  Block 0 commits h to the unrotated Hessenberg, scale_j = 1 and
+// ||w||^2.  One read of the basis per step, where CGS2 takes two.
+template <class T, class VT, int KMAX, int VEC>
+__global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
+  Ctl* ctl = a.ctl;
+  const int K = a.K;
+  const int j = K - 1;
+  const long long step = (long long)gridDim.x * blockDim.x * VEC;
+  long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  T w[VEC];
+  T vv[KMAX][VEC];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
+  if (ctl->done_col[j] != kRunning) return;  // state after column j-1
+
+  __shared__ double tot[KMAX + 1];
+  __shared__ double sh_ah[KMAX], sh_b[KMAX], sh_ha[KMAX + 1];
+  __shared__ double sh_cv[KMAX], sh_cw[KMAX];
+  reduce_partials(a.in, K + 1, tot);
+  const int tid = threadIdx.x;
+  const int ld = kMaxM + 1;
+  if (tid < j) {
+    sh_ah[tid] = ctl->ahat[tid];
+    sh_b[tid] = tot[tid] * ctl->scale[tid];
+  }
+  __syncthreads();
+  if (tid <= j) {
+    // (H a^)_i over the completed columns 0..j-1 (row j only has column j-1)
+    double s = 0.0;
+    for (int l = 0; l < j; ++l) s += ctl->Hu[l * ld + tid] * sh_ah[l];
+    sh_ha[tid] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double ts = ctl->tscale[j];
+    const double d = ts * tot[j];
+    double ab = 0.0;
+    for (int l = 0; l < j; ++l) ab += sh_ah[l] * sh_b[l];
+    const double gamma = d - ab;
+    for (int l = 0; l < j; ++l) {
+      const double h = sh_b[l] - sh_ha[l];
+      sh_cv[l] = -sh_ah[l] * ctl->scale[l];
+      sh_cw[l] = (sh_ha[l] + h - gamma * sh_ah[l]) * ctl->scale[l];
+      if (blockIdx.x == 0) ctl->Hu[j * ld + l] = h;
+    }
+    sh_cv[j] = ts;
+    sh_cw[j] = gamma * ts;
+    if (blockIdx.x == 0) {
+      ctl->Hu[j * ld + j] = gamma - sh_ha[j];
+      ctl->scale[j] = 1.0;
+      ctl->jvn2c[j] = tot[K];
+    }
+  }
+  __syncthreads();
+  T cv[KMAX], cw[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    cv[k] = uniform(k < K ? T(sh_cv[k]) : T(0));
+    cw[k] = uniform(k < K ? T(sh_cw[k]) : T(0));
+  }
+  double acc[KMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
+  double accv = 0.0;
+  VT* vj_out = a.wout - a.vstride;  // slot j (wout is slot j + 1)
+  for (; i < a.n; i += step) {
+    T vn[VEC], wn[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      T x = T(0);
+      T y = w[e];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        x = x + cv[k] * vv[k][e];
+        y = y - cw[k] * vv[k][e];
+      }
+      vn[e] = x;
+      wn[e] = y;
+    }
+    // groups of four slots behind one uniform branch; slot j's product (with
+    // U_j) is replaced by the one with the new v_j below
+#pragma unroll
+    for (int kb = 0; kb < KMAX; kb += 4)
+      if (kb < K)
+#pragma unroll
+        for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], wn);
+    accv += group_dot<T, VEC>(vn, wn);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];
+    VT o1[VEC], o2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      o1[e] = to_s<VT>(vn[e]);
+      o2[e] = to_s<VT>(wn[e]);
+    }
+    store_vec<VT, VEC>(vj_out + i, o1);
+    store_vec<VT, VEC>(a.wout + i, o2);
+    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC>(a, i + step, K, w, vv);
+  }
+  // [V_0..V_{j-1} . U_{j+1}, v_j . U_{j+1}, ||U_{j+1}||^2] (static indices keep acc in registers)
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k == j) acc[k] = accv;
+    if (k == K) acc[k] = acc[KMAX];
+  }
+  __shared__ double lds[(KMAX + 1) * 8];
+  block_partials<KMAX + 1>(acc, K + 1, a.out.part, a.out.ld, lds);
+}
+
 // Start of a restart cycle: V_0 = sign * R - w (w nullable) and its partial
 // norms; cycle_begin_kernel then fixes beta, g, scale[0] and the flags.
 template <class T, class VT>
@@ -365,6 +537,7 @@ __global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in,
     ctl->gp[0] = beta;
     ctl->scale[0] = 1.0 / (beta * sig);
     ctl->k = 0;
+    ctl->tscale[0] = ctl->scale[0];
     ctl->done_col[0] = !isfinite(beta) ? kNonfinite : (beta <= ctl->tol_abs ? kConverged : kRunning);
   }
   if (threadIdx.x >= 1 && threadIdx.x <= m) ctl->done_col[threadIdx.x] = kRunning;
@@ -398,9 +571,10 @@ struct VyArgs {
   int first;    // 1: dx = V y (dx not read)
   int jmax;     // last Arnoldi step enqueued in this cycle (-1: none)
   Ctl* ctl;
-  Partials pc;  // partial norms of the last pass C
+  Partials pc;  // partial norms of the last pass C (delayed form: of the last update pass)
   PartSink out;  // partial sums of ||dx||^2
   int* host_flags;
+  int lagged;    // 1: the basis comes from the delayed-second-pass Arnoldi steps
 };
 
 template <class T, class VT, int KMAX, int VEC>
@@ -436,7 +610,8 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   const bool pending = a.jmax >= 0 && k == a.jmax + 1;
   __shared__ int lastdone;
   if (pending) {
-    const GivensOut g = finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
+    const GivensOut g = a.lagged ? finish_column_lagged(ctl, a.jmax, a.pc, a.host_flags, lastcol)
+                                 : finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
     if (tid == 0) {
       lastgr = g.gr;
       lastdone = g.done;

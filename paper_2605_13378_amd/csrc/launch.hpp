@@ -141,6 +141,10 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
 template <class T, class VT>
 hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s);
 
+// Update pass of the delayed-second-pass Arnoldi step (K = j + 1).
+template <class T, class VT>
+hipError_t launch_dcgs(const KArgs<T, VT>& a, int grid, hipStream_t s);
+
 template <class T, class VT>
 hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s);
 

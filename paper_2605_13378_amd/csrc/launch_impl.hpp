@@ -105,6 +105,24 @@ hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) 
 }
 
 template <class T, class VT>
+hipError_t launch_dcgs(const KArgs<T, VT>& a, int grid, hipStream_t s) {
+  const dim3 b(kKrylovThreads);
+  if constexpr (!std::is_same<T, VT>::value) {
+    return hipErrorInvalidValue;  // FP16 storage keeps CGS2
+  } else {
+    if (a.K <= 4)
+      JFNK_LAUNCH((dcgs_kernel<T, VT, 4, cgs_vec<T, 4>()>), dim3(grid), b, s, a);
+    else if (a.K <= 8)
+      JFNK_LAUNCH((dcgs_kernel<T, VT, 8, cgs_vec<T, 8>()>), dim3(grid), b, s, a);
+    else if (a.K <= 16)
+      JFNK_LAUNCH((dcgs_kernel<T, VT, 16, cgs_vec<T, 16>()>), dim3(grid), b, s, a);
+    else
+      JFNK_LAUNCH((dcgs_kernel<T, VT, 32, cgs_vec<T, 32>()>), dim3(grid), b, s, a);
+    return hipGetLastError();
+  }
+}
+
+template <class T, class VT>
 hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s) {
   constexpr int VEC = krylov_vec<T>();
   JFNK_LAUNCH((init_cycle_kernel<T, VT, VEC>), dim3(grid), dim3(kStreamThreads), s, a);
@@ -233,6 +251,7 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
                                             hipStream_t, int*);                                                 \
   template hipError_t launch_cgs<T, VT>(int, const KArgs<T, VT>&, int, hipStream_t);                            \
   template hipError_t launch_init<T, VT>(const InitArgs<T, VT>&, int, hipStream_t);                             \
+  template hipError_t launch_dcgs<T, VT>(const KArgs<T, VT>&, int, hipStream_t);                                \
   template hipError_t launch_vy<T, VT>(const VyArgs<T, VT>&, int, int, hipStream_t);                            \
   template hipError_t launch_store_basis0<T, VT>(long long, const T*, VT*, const Ctl*, int, hipStream_t);
 

@@ -32,10 +32,10 @@ thread_local KernelTiming* g_timing = nullptr;
 
 namespace {
 
-constexpr int kNumProf = 12;
+constexpr int kNumProf = 13;
 enum ProfKernel {
   PK_RES = 0, PK_AD = 1, PK_FD = 2, PK_A = 3, PK_B = 4, PK_C = 5, PK_VY = 6, PK_INIT = 7, PK_TRIAL = 8, PK_FUSED = 9,
-  PK_BI = 10, PK_CG = 11
+  PK_BI = 10, PK_CG = 11, PK_D = 12
 };
 
 struct ProfRec {
@@ -91,6 +91,7 @@ struct jfnk_solver {
   CgCtl* dcg = nullptr;         // CG scalars (device)
   CgCtl* hcg = nullptr;         // pinned host copy
   bool has_prev = false;
+  int orth = 0;                 // Gram-Schmidt form of jfnk_gmres calls (jfnk_orth)
   std::string err;
   bool prof = false;
   int cur_step = -1;
@@ -284,7 +285,7 @@ struct Impl {
   // *nb_out receives their row count).
   template <class W>
   static jfnk_status jvp(jfnk_solver* s, const T* x, const W* v, const double* vscale, T* Jv, T* Fout, int mode,
-                         const EpsSpec& eps, int arn_j = -1, int* nb_out = nullptr) {
+                         const EpsSpec& eps, int arn_j = -1, int* nb_out = nullptr, bool lagged = false) {
     StencilArgs<T, W> a{};
     a.nx = s->prob.nx;
     a.ny = s->prob.ny;
@@ -303,7 +304,9 @@ struct Impl {
     if (arn_j >= 0) {
       a.ctl = s->ctl;
       a.arn_j = arn_j;
-      a.pc = parts(s, 2, cgs_grid(s, arn_j > 0 ? arn_j : 1));
+      a.lagged = lagged ? 1 : 0;
+      // the sums that complete column arn_j - 1: pass C's (CGS2) or the update pass's (DCGS2)
+      a.pc = lagged ? parts(s, 1, cgs_grid(s, arn_j > 0 ? arn_j : 1)) : parts(s, 2, cgs_grid(s, arn_j > 0 ? arn_j : 1));
       a.host_flags = s->dflags;
       a.Vb = reinterpret_cast<const W*>(basis(s, 0));
       a.vstride = s->npad;
@@ -333,8 +336,9 @@ struct Impl {
 
   // Restarted GMRES(m) on J(x) dx = sign * R (R internal, padded), dx internal.
   static jfnk_status gmres(jfnk_solver* s, const T* x, const T* R, double sign, int m, double tol, int max_restarts,
-                           int mode, double fixed_eps, int eps_rule, double brk, GOut& go) {
+                           int mode, double fixed_eps, int eps_rule, double brk, GOut& go, bool lagged = false) {
     go = GOut{};
+    if constexpr (!std::is_same<T, VT>::value) lagged = false;  // FP16 storage keeps CGS2
     T* dxi = static_cast<T*>(s->dx);
     T* w = static_cast<T*>(s->w);
     const int kgrid = krylov_grid(s, KVEC);
@@ -398,22 +402,29 @@ struct Impl {
       // prologue of step j+1's JVP and reports its stop flag to mapped host
       // memory.  After enqueueing step j the host waits until step j-1's JVP
       // has published column j-2's flag: at most two enqueued steps are
-      // skipped, and no marker is placed in the stream between steps.
+      // skipped, and no marker is placed in the stream between steps.  The
+      // delayed-second-pass form runs two kernels per step (JVP with the
+      // first projection and the completion of column j-1 in its prologue,
+      // then one update pass) with the same flag protocol.
       int jmax = -1;
       for (int j = 0; j < m; ++j) {
         s->cur_step = j;
         const int K = j + 1;
         if (j >= 1) flags[j - 1] = -1;
         int nb_jvp = 0;  // the JVP carries the first projection (pass A)
-        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp));
+        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged));
         KArgs<T, VT> ka{s->npad, basis(s, 0), s->npad, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1)};
-        {
-          ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
-          JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, cgs_grid(s, K), s->stream));
-        }
-        ka.in = parts(s, 1, cgs_grid(s, K));
-        ka.out = sink(s, 2);
-        {
+        if (lagged) {
+          // one update pass: v_j completed, the next vector projected once
+          ProfScope ps(s, PK_D, (double)s->n * ((K + 2) * sizeof(VT) + sizeof(T)));
+          JFNK_HIP(s, launch_dcgs<T, VT>(ka, cgs_grid(s, K), s->stream));
+        } else {
+          {
+            ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
+            JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, cgs_grid(s, K), s->stream));
+          }
+          ka.in = parts(s, 1, cgs_grid(s, K));
+          ka.out = sink(s, 2);
           ProfScope ps(s, PK_C, (double)s->n * (K * sizeof(VT) + sizeof(T) + sizeof(VT)));
           JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, cgs_grid(s, K), s->stream));
         }
@@ -424,7 +435,8 @@ struct Impl {
       flags[jmax] = -1;
       {
         VyArgs<T, VT> va{s->npad, basis(s, 0), s->npad, dxi, updated ? 0 : 1, jmax, s->ctl,
-                         parts(s, 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)), sink(s, 4), s->dflags};
+                         parts(s, lagged ? 1 : 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)), sink(s, 4), s->dflags,
+                         lagged ? 1 : 0};
         ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
         JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
       }
@@ -776,7 +788,7 @@ struct Impl {
         }
       } else {
         JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
-                       o.fd_eps, o.eps_rule, o.breakdown_tol, go));
+                       o.fd_eps, o.eps_rule, o.breakdown_tol, go, o.orth == JFNK_ORTH_DCGS2));
       }
       info->krylov_iters += go.iters;
       info->restarts += go.cycles;
@@ -1002,7 +1014,8 @@ jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, do
   if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<T>(s, x, &s->ctl->xnorm2));
   const double brk = s->prec == JFNK_F64 ? 1e-14 : 1e-6;
   typename Impl<T, VT>::GOut go;
-  JFNK_TRY(Impl<T, VT>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go));
+  JFNK_TRY(Impl<T, VT>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go,
+                              s->orth == JFNK_ORTH_DCGS2));
   JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   JFNK_HIP(s, hipStreamSynchronize(s->stream));
   if (info) {
@@ -1259,6 +1272,20 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   return JFNK_OK;
 }
 
+jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth) {
+  if (!s) return JFNK_ERR_ARG;
+  if (orth != JFNK_ORTH_CGS2 && orth != JFNK_ORTH_DCGS2) {
+    s->err = "unknown Gram-Schmidt form";
+    return JFNK_ERR_ARG;
+  }
+  if (orth == JFNK_ORTH_DCGS2 && s->prec == JFNK_F16S) {
+    s->err = "DCGS2 runs in FP64 or FP32 (FP16 storage keeps CGS2)";
+    return JFNK_ERR_ARG;
+  }
+  s->orth = orth;
+  return JFNK_OK;
+}
+
 jfnk_status jfnk_set_stream(jfnk_solver* s, void* hip_stream) {
   if (!s) return JFNK_ERR_ARG;
   s->stream = static_cast<hipStream_t>(hip_stream);
@@ -1392,8 +1419,13 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
       o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
       (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0) ||
       o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP ||
-      o.krylov < JFNK_KRYLOV_GMRES || o.krylov > JFNK_KRYLOV_CG) {
+      o.krylov < JFNK_KRYLOV_GMRES || o.krylov > JFNK_KRYLOV_CG || o.orth < JFNK_ORTH_CGS2 ||
+      o.orth > JFNK_ORTH_DCGS2) {
     s->err = "invalid options";
+    return JFNK_ERR_ARG;
+  }
+  if (o.orth == JFNK_ORTH_DCGS2 && s->prec == JFNK_F16S) {
+    s->err = "DCGS2 runs in FP64 or FP32 (FP16 storage keeps CGS2)";
     return JFNK_ERR_ARG;
   }
   if (o.krylov != JFNK_KRYLOV_GMRES && !short_recurrence_fits(s, o.krylov, &s->err)) return JFNK_ERR_ARG;

@@ -47,6 +47,7 @@ struct StencilArgs {
   // is done, and takes the basis scale from that update.
   Ctl* ctl;
   int arn_j;
+  int lagged;            // delayed-second-pass Arnoldi: pc holds the update pass's sums
   Partials pc;
   int* host_flags;
   PartSink part_out;     // RES: partial sums of sum(out^2) and sum(x^2)
@@ -286,7 +287,8 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         vscale = a.ctl->scale[0];
       } else {
         __shared__ double gcol[kMaxM + 1];
-        const GivensOut g = finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
+        const GivensOut g = a.lagged ? finish_column_lagged(a.ctl, j - 1, a.pc, a.host_flags, gcol)
+                                     : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
         if (g.done != kRunning) return;  // uniform: every block computed the same update
         vscale = g.vs;
       }

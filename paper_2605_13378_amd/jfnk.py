@@ -23,10 +23,11 @@ MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
 ENGINES = {"auto": 0, "multi": 1, "single": 2}
 KRYLOV = {"gmres": 0, "bicgstab": 1, "cg": 2}
+ORTH = {"cgs2": 0, "dcgs2": 1}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
           5: "breakdown", 6: "not_converged"}
 PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
-                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9, "bicgstab": 10, "cg": 11}
+                   "cycle_start": 7, "newton_trial": 8, "fused_solve": 9, "bicgstab": 10, "cg": 11, "dcgs_update": 12}
 
 
 class Problem(ctypes.Structure):
@@ -42,7 +43,8 @@ class Options(ctypes.Structure):
                 ("tol_krylov", ctypes.c_double), ("tol_newton", ctypes.c_double), ("ls_c", ctypes.c_double),
                 ("fd_eps", ctypes.c_double), ("breakdown_tol", ctypes.c_double),
                 ("mode", ctypes.c_int), ("eps_rule", ctypes.c_int),
-                ("history", ctypes.c_void_p), ("engine", ctypes.c_int), ("krylov", ctypes.c_int)]
+                ("history", ctypes.c_void_p), ("engine", ctypes.c_int), ("krylov", ctypes.c_int),
+                ("orth", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -114,6 +116,7 @@ _SIGNATURES = [
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("jfnk_profile_reset", ctypes.c_int, [ctypes.c_void_p]),
     ("jfnk_set_stream", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("jfnk_set_orthogonalization", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("jfnk_batch_create", ctypes.c_int, [ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_void_p)]),
     ("jfnk_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("jfnk_batch_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
@@ -182,6 +185,8 @@ def default_options(precision: str = "f64", **kw) -> Options:
             val = ENGINES[val]
         elif key == "krylov":
             val = KRYLOV[val]
+        elif key == "orth":
+            val = ORTH[val]
         elif key == "history":
             val = None if val is None else val.data_ptr()
         setattr(o, key, val)
@@ -264,6 +269,10 @@ class Solver:
                                    None if F is None else F.data_ptr(), MODES[mode], float(eps),
                                    EPS_RULES[eps_rule]))
         return (jv, F) if want_F else jv
+
+    def set_orthogonalization(self, orth: str):
+        """Gram-Schmidt form of later gmres() calls: 'cgs2' (default) or 'dcgs2'."""
+        self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
 
     def gmres(self, x, rhs, m=None, tol=1e-8, max_restarts=100, mode="ad", eps=0.0, eps_rule="paper"):
         x = self._vec(x, self.wdtype, "x")
