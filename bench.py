@@ -36,9 +36,9 @@ CONFIG_NAME = "grayscott-1024x1024-backward-euler"
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarized in profiles/, valid only for the
 # kernel sources they were taken with (hash of the device headers).
 MEASURED_TRAFFIC = {
-    "jvp_ad": {"sources": "4d83bb2e850cd764", "ratio": 0.955},
-    "cgs_b": {"sources": "4d83bb2e850cd764", "ratio": 0.891},
-    "cgs_c": {"sources": "4d83bb2e850cd764", "ratio": 0.888},
+    "jvp_ad": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.955},
+    "cgs_b": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.891},
+    "cgs_c": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.888},
 }
 
 def kernel_sources_hash() -> str:
@@ -72,9 +72,12 @@ def make_solver(spec, prec, xp, torch):  # prec: f64 | f32 | f16s
     return s
 
 
+ORTH = "dcgs2"  # GMRES Gram-Schmidt form of the headline and variant rows (--orth)
+
+
 def options_for(prec: str, mode: str) -> dict:
-    # the Gray-Scott workload takes the normalized FD step rule
-    return dict(mode=mode, eps_rule="normalized")
+    # the Gray-Scott workload takes the normalized FD step rule; FP16 storage keeps CGS2
+    return dict(mode=mode, eps_rule="normalized", orth="cgs2" if prec == "f16s" else ORTH)
 
 
 def run_solves(s, x0, torch, count, opts, sync_each=True):
@@ -457,6 +460,8 @@ def main():
     ap.add_argument("--no-jvp-rows", action="store_true", help="skip the standalone JVP bandwidth rows")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching serving run")
     ap.add_argument("--no-latency", action="store_true", help="skip the 1D Burgers N=256 latency rows")
+    ap.add_argument("--orth", default="dcgs2", choices=["cgs2", "dcgs2"],
+                    help="GMRES Gram-Schmidt form: CGS2 (three passes per Arnoldi step) or DCGS2 (two)")
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
     ap.add_argument("--no-rd", action="store_true", help="skip the reaction-diffusion Krylov-method rows")
     ap.add_argument("--kerr-newton", action="store_true",
@@ -470,6 +475,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run a plain device copy of MB megabytes 3 times first (HBM counter calibration)")
     args = ap.parse_args()
+    global ORTH
+    ORTH = args.orth
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the JFNK hot path of this "
@@ -538,7 +545,7 @@ def main():
     bpl = dom["bytes"] / max(1, dom["launches"])
     meas = MEASURED_TRAFFIC.get(dom_name)
     traffic = None
-    if meas is not None and meas["sources"] == kernel_sources_hash():
+    if meas is not None and meas["sources"] == kernel_sources_hash() and meas["orth"] == ORTH:
         traffic = round(meas["ratio"] * bpl)  # HBM bytes per launch, calibrated counters
     roofline = dict(bound="hbm", kernel=dom_name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic, avg_us=round(dom_avg_us, 3),
@@ -654,7 +661,7 @@ def main():
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": CONFIG_NAME, "grid": [1024, 1024], "unknowns": n, "jvp": "ad",
-                   "krylov": "GMRES(30) CGS2, FP64 Givens", "tol_newton": 1e-4 if prec == "f32" else 1e-6,
+                   "krylov": f"GMRES(30) {args.orth.upper()}, FP64 Givens", "tol_newton": 1e-4 if prec == "f32" else 1e-6,
                    "tol_krylov": 1e-6 if prec == "f32" else 1e-8, "seed": 0},
         "latency_ms": {"p50": round(1e3 * percentile(lat, 0.5), 3), "p99": round(1e3 * percentile(lat, 0.99), 3)},
         "newton_iters": info["newton_iters"],

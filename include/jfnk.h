@@ -128,7 +128,8 @@ typedef struct {
  *          projected vector and corrected through the Arnoldi relation):
  *          two passes over the basis per step.  Same basis and Hessenberg
  *          matrix in exact arithmetic.  FP64 and FP32 only (FP16 storage
- *          keeps CGS2); the SINGLE_WORKGROUP engine always runs CGS2. */
+ *          keeps CGS2); the SINGLE_WORKGROUP engine always runs CGS2.
+ * The defaults are DCGS2 in FP64 and FP32 and CGS2 with FP16 storage. */
 typedef enum { JFNK_ORTH_CGS2 = 0, JFNK_ORTH_DCGS2 = 1 } jfnk_orth;
 
 /* The Krylov method of each Newton step (paper, Section 2: GMRES(m) or
@@ -241,7 +242,8 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
                               jfnk_info* info);
 
 /* Gram-Schmidt form (jfnk_orth) of later jfnk_gmres calls on this solver
- * (default CGS2); jfnk_newton_solve takes it from its options instead.
+ * (default DCGS2 in FP64 and FP32, CGS2 with FP16 storage); jfnk_newton_solve
+ * takes it from its options instead (jfnk_default_options: the same).
  * DCGS2 on an FP16S solver returns JFNK_ERR_ARG. */
 jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth);
 

@@ -1126,6 +1126,7 @@ void jfnk_default_options(int precision, jfnk_options* o) {
   o->mode = JFNK_JVP_AD;
   o->eps_rule = JFNK_EPS_PAPER;
   o->engine = JFNK_ENGINE_AUTO;
+  o->orth = precision == JFNK_F16S ? JFNK_ORTH_CGS2 : JFNK_ORTH_DCGS2;
   if (precision == JFNK_F64) {
     o->tol_newton = 1e-6;
     o->tol_krylov = 1e-8;
@@ -1181,6 +1182,7 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   s->npad = round_up(s->n, 256);
   s->tsize = elem_size(precision);
   s->vsize = basis_elem_size(precision);
+  s->orth = precision == JFNK_F16S ? JFNK_ORTH_CGS2 : JFNK_ORTH_DCGS2;
   int dev = 0;
   hipDeviceProp_t prop{};
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&

@@ -271,7 +271,7 @@ class Solver:
         return (jv, F) if want_F else jv
 
     def set_orthogonalization(self, orth: str):
-        """Gram-Schmidt form of later gmres() calls: 'cgs2' (default) or 'dcgs2'."""
+        """Gram-Schmidt form of later gmres() calls: 'cgs2' or 'dcgs2' (default in FP64/FP32)."""
         self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
 
     def gmres(self, x, rhs, m=None, tol=1e-8, max_restarts=100, mode="ad", eps=0.0, eps_rule="paper"):
