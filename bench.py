@@ -36,9 +36,8 @@ CONFIG_NAME = "grayscott-1024x1024-backward-euler"
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarized in profiles/, valid only for the
 # kernel sources they were taken with (hash of the device headers).
 MEASURED_TRAFFIC = {
-    "jvp_ad": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.955},
-    "cgs_b": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.891},
-    "cgs_c": {"sources": "4d83bb2e850cd764", "orth": "cgs2", "ratio": 0.888},
+    "jvp_ad": {"sources": "2659a7a332bd8373", "orth": "dcgs2", "ratio": 0.958},
+    "dcgs_update": {"sources": "2659a7a332bd8373", "orth": "dcgs2", "ratio": 0.893},
 }
 
 def kernel_sources_hash() -> str:
