@@ -383,33 +383,42 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   if (ctl->done_col[j] != kRunning) return;  // state after column j-1
 
   __shared__ double tot[KMAX + 1];
-  __shared__ double sh_ah[KMAX], sh_b[KMAX], sh_ha[KMAX + 1];
+  __shared__ double sh_ah[KMAX], sh_sc[KMAX], sh_b[KMAX], sh_ha[KMAX + 1];
   __shared__ double sh_cv[KMAX], sh_cw[KMAX];
-  reduce_partials(a.in, K + 1, tot);
+  __shared__ double sh_hu[KMAX * KMAX];  // completed columns 0..j-1, rows 0..j (stride j + 1)
+  __shared__ double sh_ts;
   const int tid = threadIdx.x;
   const int ld = kMaxM + 1;
+  // control-block inputs staged into LDS by all threads at once, their loads
+  // in flight together with the partial-sum reduction
+  for (int idx = tid; idx < j * (j + 1); idx += blockDim.x) {
+    const int l = idx / (j + 1), r = idx - l * (j + 1);
+    sh_hu[idx] = ctl->Hu[l * ld + r];
+  }
   if (tid < j) {
     sh_ah[tid] = ctl->ahat[tid];
-    sh_b[tid] = tot[tid] * ctl->scale[tid];
+    sh_sc[tid] = ctl->scale[tid];
   }
-  __syncthreads();
+  if (tid == 0) sh_ts = ctl->tscale[j];
+  reduce_partials(a.in, K + 1, tot);  // ends with a barrier
+  if (tid < j) sh_b[tid] = tot[tid] * sh_sc[tid];
   if (tid <= j) {
     // (H a^)_i over the completed columns 0..j-1 (row j only has column j-1)
     double s = 0.0;
-    for (int l = 0; l < j; ++l) s += ctl->Hu[l * ld + tid] * sh_ah[l];
+    for (int l = 0; l < j; ++l) s += sh_hu[l * (j + 1) + tid] * sh_ah[l];
     sh_ha[tid] = s;
   }
   __syncthreads();
   if (tid == 0) {
-    const double ts = ctl->tscale[j];
+    const double ts = sh_ts;
     const double d = ts * tot[j];
     double ab = 0.0;
     for (int l = 0; l < j; ++l) ab += sh_ah[l] * sh_b[l];
     const double gamma = d - ab;
     for (int l = 0; l < j; ++l) {
       const double h = sh_b[l] - sh_ha[l];
-      sh_cv[l] = -sh_ah[l] * ctl->scale[l];
-      sh_cw[l] = (sh_ha[l] + h - gamma * sh_ah[l]) * ctl->scale[l];
+      sh_cv[l] = -sh_ah[l] * sh_sc[l];
+      sh_cw[l] = (sh_ha[l] + h - gamma * sh_ah[l]) * sh_sc[l];
       if (blockIdx.x == 0) ctl->Hu[j * ld + l] = h;
     }
     sh_cv[j] = ts;
