@@ -206,7 +206,11 @@ def completion_c3(torch, seeds, steps=10, n=2048, modes=("ad", "fd"), precisions
                 x = torch.tensor(inits[sd], dtype=torch.float64, device="cuda")
                 bad = 0
                 nonfinite = False
+                done = 0
                 for _ in range(steps):
+                    if time.perf_counter() - t0 > budget_s:
+                        break  # FD in FP32 stagnates (hundreds of thousands of Krylov iterations)
+                    done += 1
                     s.set_previous(x)
                     torch.cuda.synchronize()
                     t1 = time.perf_counter()
@@ -412,6 +416,49 @@ def rd_rows(torch, steps, budget_s=3.0):
     return rows
 
 
+def paper_burgers_rows(torch, steps=100, n=256, budget_s=12.0):
+    """The paper's JVP-cost experiment (its Table 1: 256^2 Burgers TGV, 100 time steps) and the
+    double shear layer at the same size: per combination of JVP and precision, the average
+    event-timed JVP duration, the JVPs' share of the solve time, iterations and completion."""
+    import workloads as W
+    from paper_2605_13378_amd import Solver
+
+    rows = {}
+    for case in ("tgv", "dsl"):
+        spec, x0 = W.burgers2d_paper_case(case, n)
+        for pr in ("f32", "f64"):
+            for mode in ("ad", "fd"):
+                s = Solver(spec, pr, m=30)
+                x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+                s.profile_reset()
+                s.profile(True)
+                newton = krylov = ok = 0
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                done = 0
+                for _ in range(steps):
+                    if time.perf_counter() - t0 > budget_s:
+                        break  # FD in FP32 stagnates (hundreds of thousands of Krylov iterations)
+                    done += 1
+                    s.set_previous(x)
+                    x, info = s.newton_solve(x, mode=mode, eps_rule="paper")
+                    newton += info["newton_iters"]
+                    krylov += info["krylov_iters"]
+                    ok += 1 if info["rel_res"][-1] <= 100 * (1e-4 if pr == "f32" else 1e-6) else 0
+                torch.cuda.synchronize()
+                wall_ms = 1e3 * (time.perf_counter() - t0)
+                st = s.profile_read()
+                s.profile(False)
+                j = st["jvp_" + mode]
+                rows[f"{case}-{pr}-{mode}"] = dict(
+                    steps=done, completed_steps=ok, newton_iters=newton, krylov_iters=krylov,
+                    jvp_launches=j["launches"], jvp_avg_us=round(j["ms"] * 1e3 / max(1, j["launches"]), 3),
+                    jvp_share_of_solve=round(j["ms"] / wall_ms, 4), solve_ms_per_step=round(wall_ms / done, 3))
+                log(f"[bench] burgers2d {n}^2 {case}-{pr}-{mode}: {rows[f'{case}-{pr}-{mode}']}")
+                s.close()
+    return rows
+
+
 def cpu_baseline(spec, xp, prec):
     """The oracle, single-threaded, on one full Newton solve of the same workload."""
     try:
@@ -463,6 +510,8 @@ def main():
                     help="GMRES Gram-Schmidt form: CGS2 (three passes per Arnoldi step) or DCGS2 (two)")
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
     ap.add_argument("--no-rd", action="store_true", help="skip the reaction-diffusion Krylov-method rows")
+    ap.add_argument("--no-paper-burgers", action="store_true",
+                    help="skip the 256^2 Burgers TGV/DSL rows (the paper's JVP-cost experiment)")
     ap.add_argument("--kerr-newton", action="store_true",
                     help="run the Helmholtz-Kerr 1024^2 Newton completion rows (minutes)")
     ap.add_argument("--completion-seeds", type=int, default=64,
@@ -620,6 +669,11 @@ def main():
         log("[bench] reaction-diffusion 512^2 rows (CG / BiCGSTAB / GMRES)")
         rd = rd_rows(torch, args.steps)
 
+    pb = None
+    if not args.no_paper_burgers:
+        log("[bench] 256^2 Burgers TGV / DSL rows (100 Crank-Nicolson steps each)")
+        pb = paper_burgers_rows(torch)
+
     c3 = None
     if args.completion_seeds > 0:
         log(f"[bench] completion sweep: 2D Burgers 2048^2, 10 steps, {args.completion_seeds} seeds")
@@ -675,6 +729,7 @@ def main():
         "variants": variants,
         "bicgstab_newton": bicg,
         "reaction_diffusion_512": rd,
+        "burgers2d_256_tgv_dsl": pb,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,

@@ -163,6 +163,41 @@ def taylor_green(n: int) -> np.ndarray:
     return np.concatenate([u.ravel(), v.ravel()])
 
 
+def double_shear_layer(n: int, rho: float = 30.0, delta: float = 0.05) -> np.ndarray:
+    """Double shear layer on [0,2pi)^2 (Appendix A.1): u = tanh(rho (y - pi/2)) for y <= pi,
+    tanh(rho (3 pi/2 - y)) above; v = delta sin x."""
+    h = 2.0 * np.pi / n
+    c = np.arange(n) * h
+    X = c[None, :]
+    Y = c[:, None]
+    u = np.where(Y <= np.pi, np.tanh(rho * (Y - np.pi / 2)), np.tanh(rho * (1.5 * np.pi - Y))) * np.ones_like(X)
+    v = delta * np.sin(X) * np.ones_like(Y)
+    return np.concatenate([u.ravel(), v.ravel()])
+
+
+def burgers2d_cfl_dt(x: np.ndarray, n: int, nu: float, C: float = 1.0) -> float:
+    """The paper's Burgers step rule (Appendix A.1) on the state x of an n x n grid of [0,2pi)^2:
+    dt = C min(h / max|u|, h / max|v|, 1 / (2 nu (2 / h^2)))."""
+    h = 2.0 * np.pi / n
+    u = np.abs(x[: n * n]).max()
+    v = np.abs(x[n * n:]).max()
+    cands = [1.0 / (2.0 * nu * (2.0 / (h * h)))]
+    if u > 0:
+        cands.append(h / u)
+    if v > 0:
+        cands.append(h / v)
+    return C * min(cands)
+
+
+def burgers2d_paper_case(name: str, n: int = 256, nu: float = 0.05, C: float = 1.0) -> tuple[dict, np.ndarray]:
+    """(spec, U^0) of the paper's periodic Burgers set-ups: ``tgv`` (Taylor-Green vortex) or
+    ``dsl`` (double shear layer), Crank-Nicolson, nu = 0.05 (the paper's TGV figure), the time
+    step from the CFL rule on the initial state."""
+    x0 = taylor_green(n) if name == "tgv" else double_shear_layer(n)
+    spec = burgers2d_spec(n, nu=nu, dt=burgers2d_cfl_dt(x0, n, nu, C), theta=0.5)
+    return spec, x0
+
+
 def kerr_gaussian_source(n: int = 1024, amp: float = 0.1, sigma: float = 4.0,
                          center: tuple[float, float] | None = None, ny: int | None = None) -> np.ndarray:
     """Real Gaussian source f on the node grid, zero on the PEC boundary, interleaved complex."""
