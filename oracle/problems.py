@@ -31,6 +31,12 @@ in the theta scheme above at the interior nodes, F = u at the boundary nodes
 (which hold the zero boundary value).  Its Jacobian on the interior nodes is
 I + theta dt (-D L + 3 diag(u^2)), symmetric positive definite.
 
+The Su-Olson non-equilibrium radiation diffusion system (Appendix A.2),
+U_t = (1/3) Lap U - (U - V) + Q, V_t = xi (U - V): N = (-(1/3) Lap U + (U - V),
+-xi (U - V)), source (Q, 0), Dirichlet boundary nodes (F = x there).  The
+residual is affine in the state, so the FD difference quotient equals the
+Jacobian product up to rounding.
+
 Layouts are those of the ``workloads`` module: 1D ``u[i]``; two-field 2D
 problems as two row-major planes of shape (ny, nx); Kerr as interleaved
 (re, im) pairs of shape (ny, nx, 2).
@@ -49,7 +55,7 @@ from .dual import Dual, concatenate, roll, stack_last
 class Problem:
     """A benchmark problem: kind, grid and physical parameters."""
 
-    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr' | 'rd2d'
+    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr' | 'rd2d' | 'suolson'
     nx: int
     ny: int = 1
     hx: float = 1.0
@@ -65,6 +71,7 @@ class Problem:
     eps_re: float = 1.0  # Kerr linear permittivity (real part)
     eps_im: float = 0.0  # Kerr linear permittivity (imaginary part)
     chi3: float = 0.0  # Kerr coefficient
+    xi: float = 0.0  # Su-Olson material coupling
 
     @classmethod
     def from_spec(cls, spec: dict) -> "Problem":
@@ -164,7 +171,15 @@ def N_rd2d(p: Problem, f):
     return [-p.D * lap(u, p) + u * u * u]
 
 
-SPATIAL = {"burgers1d": N_burgers1d, "burgers2d": N_burgers2d, "grayscott": N_grayscott, "rd2d": N_rd2d}
+def N_suolson(p: Problem, f):
+    """Su-Olson: U_t = (1/3) Lap U - (U - V), V_t = xi (U - V) (Appendix A.2; the source enters as s)."""
+    U, V = f
+    d = U - V
+    return [-(1.0 / 3.0) * lap(U, p) + d, -p.xi * d]
+
+
+SPATIAL = {"burgers1d": N_burgers1d, "burgers2d": N_burgers2d, "grayscott": N_grayscott, "rd2d": N_rd2d,
+           "suolson": N_suolson}
 
 
 def N_apply(p: Problem, x):
@@ -219,6 +234,9 @@ def residual(p: Problem, x, x_prev, source=None):
     if p.kind == "rd2d":
         # homogeneous Dirichlet: boundary nodes are identity rows
         m = interior_mask(p).ravel()
+        out = m * out + (1.0 - m) * x
+    elif p.kind == "suolson":
+        m = np.tile(interior_mask(p).ravel(), 2)
         out = m * out + (1.0 - m) * x
     return out
 

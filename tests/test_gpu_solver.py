@@ -122,6 +122,13 @@ def test_newton_f64_ad(kind, nx, ny):
     compare_newton(spec, xp, src, "f64", "ad", 1e-12)
 
 
+@pytest.mark.parametrize("name", ["tgv", "dsl"])
+def test_newton_paper_burgers_cases(name):
+    # the paper's periodic Burgers set-ups (Taylor-Green vortex, double shear layer), CFL step
+    spec, x0 = W.burgers2d_paper_case(name, 64)
+    compare_newton(spec, x0, None, "f64", "ad", 1e-12)
+
+
 @pytest.mark.parametrize("engine", ["multi", "single"])
 @pytest.mark.parametrize("cpw,chi,tol,slack", [(64.0, 0.3, 1e-10, None), (32.0, 1.0, 1e-10, 0.15)])
 def test_newton_kerr_f64_ad(cpw, chi, tol, slack, engine):

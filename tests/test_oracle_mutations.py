@@ -223,3 +223,17 @@ def test_dcgs2_mutations_fail_a_pin(monkeypatch, old, new):
         except (AssertionError, ValueError, ZeroDivisionError):
             failed += 1
     assert failed >= 1
+
+
+import test_oracle_suolson as tso  # noqa: E402
+
+
+@pytest.mark.parametrize("bad", [
+    lambda p, f: [-(1.0 / 3.0) * oprob.lap(f[0], p) + (f[1] - f[0]), -p.xi * (f[0] - f[1])],  # coupling sign
+    lambda p, f: [-(1.0 / 3.0) * oprob.lap(f[0], p) + (f[0] - f[1]), -(f[0] - f[1])],         # xi dropped
+    lambda p, f: [-oprob.lap(f[0], p) + (f[0] - f[1]), -p.xi * (f[0] - f[1])],                # 1/3 dropped
+])
+def test_suolson_mistakes_fail_a_pin(monkeypatch, bad):
+    monkeypatch.setitem(oprob.SPATIAL, "suolson", bad)
+    _expect_failure(tso.test_suolson_sine_modes_closed_form, 17, 13, 0.5, False)
+    _expect_failure(tso.test_suolson_jacobian_is_the_constant_hand_derived_matrix)

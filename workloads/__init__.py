@@ -73,6 +73,36 @@ def rd2d_spec(n: int = 512, D: float = 0.01, C: float = 1.0, theta: float = 0.5,
     return dict(kind="rd2d", nx=n, ny=ny, hx=hx, hy=hy, dt=C * hx * hx / D, theta=theta, D=D)
 
 
+def suolson_spec(n: int = 512, xi: float = 0.1, C: float = 1.0, theta: float = 0.5, L: float = 10.0,
+                 ny: int | None = None) -> dict:
+    """Su-Olson radiation diffusion on the node grid of [-L/2, L/2]^2 (Appendix A.2): Dirichlet
+    boundary nodes, Crank-Nicolson, dt = min(C h^2 / D, C / xi) with D = 1/3."""
+    ny = n if ny is None else ny
+    hx = L / (n - 1)
+    hy = L / (ny - 1)
+    dt = min(C * min(hx, hy) ** 2 / (1.0 / 3.0), C / xi)
+    return dict(kind="suolson", nx=n, ny=ny, hx=hx, hy=hy, dt=dt, theta=theta, xi=xi)
+
+
+def suolson_initial(n: int = 512, seed: int = 0, ny: int | None = None, L: float = 10.0, Q0: float = 1.0,
+                    sigma: float = 0.4, R: float = 2.0) -> tuple[np.ndarray, np.ndarray]:
+    """(x^0, source) of the dynamic Su-Olson configuration: decaying concentric rings in U (radii
+    1, 2, 3, amplitudes 1, 1/2, 1/4, width 0.2) with V = U / 2, and the Gaussian source of
+    amplitude Q0 and width sigma at a seeded angle on the orbit of radius R; zero on the boundary."""
+    ny = n if ny is None else ny
+    x = np.linspace(-L / 2, L / 2, n)[None, :]
+    y = np.linspace(-L / 2, L / 2, ny)[:, None]
+    r = np.sqrt(x * x + y * y)
+    U = sum(a * np.exp(-((r - rk) ** 2) / (2 * 0.2 ** 2)) for rk, a in ((1.0, 1.0), (2.0, 0.5), (3.0, 0.25)))
+    ang = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi)
+    Q = Q0 * np.exp(-((x - R * np.cos(ang)) ** 2 + (y - R * np.sin(ang)) ** 2) / (2 * sigma ** 2)) * np.ones((ny, n))
+    V = 0.5 * U
+    for F in (U, V, Q):
+        F[0, :] = F[-1, :] = 0.0
+        F[:, 0] = F[:, -1] = 0.0
+    return np.concatenate([U.ravel(), V.ravel()]), np.concatenate([Q.ravel(), np.zeros(n * ny)])
+
+
 def n_unknowns(spec: dict) -> int:
     """Number of real unknowns of a problem spec."""
     cells = spec["nx"] * spec["ny"]
@@ -285,6 +315,10 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
         nn = 512 if n is None else n
         spec = rd2d_spec(nn)
         return spec, rd2d_initial(nn, seed), None
+    if name == "suolson":
+        nn = 512 if n is None else n
+        x0, src = suolson_initial(nn, seed)
+        return suolson_spec(nn), x0, src
     raise KeyError(name)
 
 
