@@ -72,7 +72,8 @@ typedef enum {
   JFNK_BURGERS2D = 1,   /* (U.grad)U = nu Lap U (Appendix A.1), periodic; n = 2 nx ny */
   JFNK_GRAYSCOTT2D = 2, /* two-species reaction-diffusion, periodic; n = 2 nx ny */
   JFNK_KERR2D = 3,      /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
-  JFNK_RD2D = 4         /* u_t = D Lap u - u^3 (Appendix A.3), Dirichlet nodes; n = nx ny */
+  JFNK_RD2D = 4,        /* u_t = D Lap u - u^3 (Appendix A.3), Dirichlet nodes; n = nx ny */
+  JFNK_SUOLSON2D = 5    /* Su-Olson radiation diffusion (Appendix A.2), Dirichlet nodes; n = 2 nx ny */
 } jfnk_problem_id;
 
 /* Problem description.  Time-dependent problems use the theta scheme
@@ -85,7 +86,9 @@ typedef enum {
  * differences.  Kerr: F = -Lap E - k0^2 (eps_L + chi3 |E|^2) E - f on
  * interior nodes and F = E on the boundary nodes.
  *   p[]: Burgers {nu}; Gray-Scott {D, Dv, F, k}; Kerr {k0, eps_re, eps_im, chi3};
- *   reaction-diffusion {D}.
+ *   reaction-diffusion {D}; Su-Olson {xi}.
+ * Su-Olson: N = (-(1/3) Lap U + (U - V), -xi (U - V)) on (U, V) planes at the
+ * interior nodes, F = x at the boundary nodes; the source (Q, 0) enters as s.
  * Grid: nx columns (contiguous) by ny rows, spacings hx, hy; nx >= 3, and
  * ny >= 3 for 2D problems (ny = 1 for 1D Burgers). */
 typedef struct {

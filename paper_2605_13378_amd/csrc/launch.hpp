@@ -17,7 +17,7 @@
 
 namespace jfnk {
 
-enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4 };
+enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4, kSuOlson = 5 };
 
 // Kernel timing: when the host driver sets g_timing around one launch, the
 // launch goes through hipExtLaunchKernelGGL with start/stop events attached

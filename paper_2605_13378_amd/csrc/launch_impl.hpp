@@ -78,6 +78,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
       return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kRD2D:
       return stencil_for_problem<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+    case kSuOlson:
+      return stencil_for_problem<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;
   }
@@ -241,6 +243,8 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
       return fused_for_problem<KerrOp, T>(a, lds, s);
     case kRD2D:
       return fused_for_problem<RD2DOp, T>(a, lds, s);
+    case kSuOlson:
+      return fused_for_problem<SuOlsonOp, T>(a, lds, s);
     default:
       return hipErrorInvalidValue;
   }

@@ -14,6 +14,8 @@
 //                 |E|^2 = re^2 + im^2; PEC boundary nodes are identity rows.
 //   RD:           N = -D Lap u + u^3                    (Appendix A.3)
 //                 homogeneous Dirichlet boundary nodes are identity rows.
+//   Su-Olson:     N = (-(1/3) Lap U + (U - V), -xi (U - V))  (Appendix A.2)
+//                 Dirichlet boundary nodes are identity rows.
 #pragma once
 
 #include "common.hpp"
@@ -160,6 +162,33 @@ struct RD2DOp {
     const Nbr<S>& u = f[0];
     const S lu = k.dx * ((u.r - T(2) * u.c) + u.l) + k.dy * ((u.u - T(2) * u.c) + u.d);
     out[0] = (u.c * u.c) * u.c - lu;
+  }
+  __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
+    return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+  }
+};
+
+struct SuOlsonOp {
+  static constexpr int NF = 2;
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = false;
+  static constexpr bool kInterleaved = false;
+  // c: 0 = 1/(3 hx^2), 1 = 1/(3 hy^2), 2 = xi
+  template <class T>
+  struct K {
+    T dx, dy, xi;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1]), T(c.c[2])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[2], S (&out)[2]) {
+    const Nbr<S>& u = f[0];
+    const S d = u.c - f[1].c;
+    const S lu = k.dx * ((u.r - T(2) * u.c) + u.l) + k.dy * ((u.u - T(2) * u.c) + u.d);
+    out[0] = d - lu;
+    out[1] = -(k.xi * d);
   }
   __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
     return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;

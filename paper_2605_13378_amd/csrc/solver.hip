@@ -868,6 +868,11 @@ jfnk_status fill_problem(jfnk_solver* s) {
       c.c[0] = p.p[0] / (p.hx * p.hx);
       c.c[1] = p.p[0] / (p.hy * p.hy);
       break;
+    case JFNK_SUOLSON2D:
+      c.c[0] = 1.0 / (3.0 * p.hx * p.hx);
+      c.c[1] = 1.0 / (3.0 * p.hy * p.hy);
+      c.c[2] = p.p[0];
+      break;
     case JFNK_KERR2D:
       c.c[0] = 1.0 / (p.hx * p.hx);
       c.c[1] = 1.0 / (p.hy * p.hy);
@@ -897,7 +902,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
     if (why) *why = "null problem";
     return false;
   }
-  if (p->id < JFNK_BURGERS1D || p->id > JFNK_RD2D) {
+  if (p->id < JFNK_BURGERS1D || p->id > JFNK_SUOLSON2D) {
     if (why) *why = "unknown problem id";
     return false;
   }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libjfnk.so")
 
 MAX_ITERS = 64
 
-PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d": 4}
+PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d": 4, "suolson": 5}
 PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
@@ -166,6 +166,8 @@ def make_problem(spec: dict) -> Problem:
         vals = [spec["D"], spec["Dv"], spec["F"], spec["k"]]
     elif kind == "rd2d":
         vals = [spec["D"]]
+    elif kind == "suolson":
+        vals = [spec["xi"]]
     else:
         vals = [spec["k0"], spec.get("eps_re", 1.0), spec.get("eps_im", 0.0), spec["chi3"]]
     for i, v in enumerate(vals):

@@ -55,6 +55,9 @@ def case(kind: str, nx: int, ny: int | None = None, seed: int = 0):
     if kind == "rd2d":
         spec = W.rd2d_spec(nx, ny=ny)
         return spec, W.rd2d_initial(nx, seed, ny=ny), None
+    if kind == "suolson":
+        x0, src = W.suolson_initial(nx, seed, ny=ny)
+        return W.suolson_spec(nx, ny=ny), x0, src
     if kind == "kerr":
         spec = dict(W.kerr_spec(nx, chi3=0.3, cells_per_wavelength=8.0, eps_im=0.05), ny=ny)
         src = W.kerr_gaussian_source(nx, amp=1.0, sigma=max(1.0, nx / 8), ny=ny)
