@@ -416,6 +416,36 @@ def rd_rows(torch, steps, budget_s=3.0):
     return rows
 
 
+def suolson_rows(torch, steps, budget_s=3.0):
+    """The paper's Su-Olson radiation diffusion at 512^2 (affine: FD equals AD up to rounding):
+    one Crank-Nicolson step with GMRES(30) and BiCGSTAB, AD and FD (paper step), FP32 and FP64."""
+    import workloads as W
+
+    spec, xp, src = W.config("suolson")
+    x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
+    rows = {}
+    for pr in ("f32", "f64"):
+        from paper_2605_13378_amd import Solver
+
+        sv = Solver(spec, pr, m=30)
+        sv.set_previous(x0, torch.tensor(src, dtype=torch.float64, device="cuda"))
+        for kr in ("gmres", "bicgstab"):
+            for mode in ("ad", "fd"):
+                o = dict(mode=mode, eps_rule="paper", krylov=kr)
+                run_solves(sv, x0, torch, 1, o)
+                cnt, t_all, inf = 0, 0.0, None
+                while t_all < budget_s and cnt < steps:
+                    el, _, inf = run_solves(sv, x0, torch, 1, o)
+                    t_all += el
+                    cnt += 1
+                rows[f"{pr}-{kr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
+                                                 newton_iters=inf["newton_iters"], lin_iters=inf["lin_iters"],
+                                                 converged=inf["converged"], final_rel_res=inf["rel_res"][-1])
+                log(f"[bench] suolson 512^2 {pr}-{kr}-{mode}: {rows[f'{pr}-{kr}-{mode}']}")
+        sv.close()
+    return rows
+
+
 def paper_burgers_rows(torch, steps=100, n=256, budget_s=12.0):
     """The paper's JVP-cost experiment (its Table 1: 256^2 Burgers TGV, 100 time steps) and the
     double shear layer at the same size: per combination of JVP and precision, the average
@@ -509,7 +539,8 @@ def main():
     ap.add_argument("--orth", default="dcgs2", choices=["cgs2", "dcgs2"],
                     help="GMRES Gram-Schmidt form: CGS2 (three passes per Arnoldi step) or DCGS2 (two)")
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
-    ap.add_argument("--no-rd", action="store_true", help="skip the reaction-diffusion Krylov-method rows")
+    ap.add_argument("--no-rd", action="store_true",
+                    help="skip the reaction-diffusion and Su-Olson Krylov-method rows")
     ap.add_argument("--no-paper-burgers", action="store_true",
                     help="skip the 256^2 Burgers TGV/DSL rows (the paper's JVP-cost experiment)")
     ap.add_argument("--kerr-newton", action="store_true",
@@ -669,6 +700,11 @@ def main():
         log("[bench] reaction-diffusion 512^2 rows (CG / BiCGSTAB / GMRES)")
         rd = rd_rows(torch, args.steps)
 
+    so = None
+    if not args.no_rd:
+        log("[bench] Su-Olson 512^2 rows")
+        so = suolson_rows(torch, args.steps)
+
     pb = None
     if not args.no_paper_burgers:
         log("[bench] 256^2 Burgers TGV / DSL rows (100 Crank-Nicolson steps each)")
@@ -730,6 +766,7 @@ def main():
         "bicgstab_newton": bicg,
         "reaction_diffusion_512": rd,
         "burgers2d_256_tgv_dsl": pb,
+        "suolson_512": so,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,
