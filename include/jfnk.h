@@ -73,7 +73,8 @@ typedef enum {
   JFNK_GRAYSCOTT2D = 2, /* two-species reaction-diffusion, periodic; n = 2 nx ny */
   JFNK_KERR2D = 3,      /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
   JFNK_RD2D = 4,        /* u_t = D Lap u - u^3 (Appendix A.3), Dirichlet nodes; n = nx ny */
-  JFNK_SUOLSON2D = 5    /* Su-Olson radiation diffusion (Appendix A.2), Dirichlet nodes; n = 2 nx ny */
+  JFNK_SUOLSON2D = 5,   /* Su-Olson radiation diffusion (Appendix A.2), Dirichlet nodes; n = 2 nx ny */
+  JFNK_MAXWELL2D = 6    /* 2D TE Maxwell-Kerr (Appendix A.4), PEC nodes; n = 4 nx ny */
 } jfnk_problem_id;
 
 /* Problem description.  Time-dependent problems use the theta scheme
@@ -89,6 +90,11 @@ typedef enum {
  *   reaction-diffusion {D}; Su-Olson {xi}.
  * Su-Olson: N = (-(1/3) Lap U + (U - V), -xi (U - V)) on (U, V) planes at the
  * interior nodes, F = x at the boundary nodes; the source (Q, 0) enters as s.
+ * Maxwell TE (planes Re Ex, Im Ex, Re Ey, Im Ey; mu0 = eps0 = 1):
+ *   F = curl curl E - omega^2 (1 - i loss)(1 + chi |E|) E - f inside, F = E on
+ *   the boundary nodes, with the mixed derivative from the diagonal
+ *   neighbours and the AD tangent of |E| taken as 0 at E = 0;
+ *   p[] = {omega, loss, chi}; f = i omega J is the source argument.
  * Grid: nx columns (contiguous) by ny rows, spacings hx, hy; nx >= 3, and
  * ny >= 3 for 2D problems (ny = 1 for 1D Burgers). */
 typedef struct {

@@ -31,6 +31,20 @@ in the theta scheme above at the interior nodes, F = u at the boundary nodes
 (which hold the zero boundary value).  Its Jacobian on the interior nodes is
 I + theta dt (-D L + 3 diag(u^2)), symmetric positive definite.
 
+The paper-form Maxwell-Kerr boundary value problem (Appendix A.4): the 2D TE
+field E = (Ex, Ey) (complex) with mu0 = eps0 = 1, frequency omega (the field
+k0), source f = i omega J:
+
+    interior:  F = curl curl E - omega^2 eps(E) E - f,
+               eps(E) = (1 - i loss) (1 + chi |E|),  |E| = sqrt(|Ex|^2 + |Ey|^2)
+    boundary:  F = E (PEC nodes held)
+
+with (curl curl E)_x = D_x D_y Ey - D_yy Ex and (curl curl E)_y = D_x D_y Ex -
+D_xx Ey (central differences; D_x D_y reaches the four diagonal neighbours),
+loss = 0.05 (the field eps_im) and chi the field chi3.  |E| is not
+differentiable at E = 0: the AD tangent of |E| is taken as 0 there (the guard),
+so the JVP at E = 0 is the linear (Born) operator.
+
 The Su-Olson non-equilibrium radiation diffusion system (Appendix A.2),
 U_t = (1/3) Lap U - (U - V) + Q, V_t = xi (U - V): N = (-(1/3) Lap U + (U - V),
 -xi (U - V)), source (Q, 0), Dirichlet boundary nodes (F = x there).  The
@@ -55,7 +69,7 @@ from .dual import Dual, concatenate, roll, stack_last
 class Problem:
     """A benchmark problem: kind, grid and physical parameters."""
 
-    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr' | 'rd2d' | 'suolson'
+    kind: str  # 'burgers1d' | 'burgers2d' | 'grayscott' | 'kerr' | 'rd2d' | 'suolson' | 'maxwell'
     nx: int
     ny: int = 1
     hx: float = 1.0
@@ -82,11 +96,13 @@ class Problem:
     def n(self) -> int:
         """Number of real unknowns."""
         cells = self.nx * self.ny
+        if self.kind == "maxwell":
+            return 4 * cells
         return cells if self.kind in ("burgers1d", "rd2d") else 2 * cells
 
     @property
     def is_ibvp(self) -> bool:
-        return self.kind != "kerr"
+        return self.kind not in ("kerr", "maxwell")
 
 
 # ---------------------------------------------------------------------------
@@ -120,6 +136,9 @@ def split(p: Problem, x):
         return [x]
     if p.kind == "rd2d":
         return [x.reshape(p.ny, p.nx)]
+    if p.kind == "maxwell":
+        planes = x.reshape(4, p.ny, p.nx)
+        return [planes[0], planes[1], planes[2], planes[3]]
     if p.kind == "kerr":
         e = x.reshape(p.ny, p.nx, 2)
         return [e[..., 0], e[..., 1]]
@@ -133,6 +152,8 @@ def join(p: Problem, parts):
         return parts[0]
     if p.kind == "rd2d":
         return parts[0].ravel()
+    if p.kind == "maxwell":
+        return concatenate([q.ravel() for q in parts])
     if p.kind == "kerr":
         return stack_last(parts).ravel()
     return concatenate([parts[0].ravel(), parts[1].ravel()])
@@ -213,6 +234,40 @@ def kerr_residual(p: Problem, x, source):
 
 
 # ---------------------------------------------------------------------------
+# Maxwell-Kerr, 2D TE
+# ---------------------------------------------------------------------------
+
+
+def guarded_norm(s):
+    """|E| = sqrt(s) for s = |Ex|^2 + |Ey|^2; on duals the tangent is 0 where s = 0."""
+    if isinstance(s, Dual):
+        v = np.sqrt(s.val)
+        pos = v > 0
+        return Dual(v, np.where(pos, s.tan / (2.0 * np.where(pos, v, 1.0)), 0.0))
+    return np.sqrt(s)
+
+
+def maxwell_residual(p: Problem, x, source):
+    """F = curl curl E - omega^2 eps(E) E - f inside, F = E on the boundary."""
+    exr, exi, eyr, eyi = split(p, x)
+    fxr, fxi, fyr, fyi = split(p, source) if source is not None else (0.0, 0.0, 0.0, 0.0)
+
+    def dxdy(f):
+        return d1(d1(f, p.hx, 1), p.hy, 0)
+
+    w2 = p.k0 * p.k0
+    loss = p.eps_im
+    m = 1.0 + p.chi3 * guarded_norm(exr * exr + exi * exi + eyr * eyr + eyi * eyi)
+    nxr = dxdy(eyr) - d2(exr, p.hy, 0) - w2 * (m * (exr + loss * exi)) - fxr
+    nxi = dxdy(eyi) - d2(exi, p.hy, 0) - w2 * (m * (exi - loss * exr)) - fxi
+    nyr = dxdy(exr) - d2(eyr, p.hx, 1) - w2 * (m * (eyr + loss * eyi)) - fyr
+    nyi = dxdy(exi) - d2(eyi, p.hx, 1) - w2 * (m * (eyi - loss * eyr)) - fyi
+    mk = interior_mask(p)
+    return join(p, [mk * nxr + (1.0 - mk) * exr, mk * nxi + (1.0 - mk) * exi,
+                    mk * nyr + (1.0 - mk) * eyr, mk * nyi + (1.0 - mk) * eyi])
+
+
+# ---------------------------------------------------------------------------
 # The residual F(x; x*)
 # ---------------------------------------------------------------------------
 
@@ -226,6 +281,8 @@ def residual(p: Problem, x, x_prev, source=None):
     """
     if p.kind == "kerr":
         return kerr_residual(p, x, source)
+    if p.kind == "maxwell":
+        return maxwell_residual(p, x, source)
     out = x - x_prev + (p.dt * p.theta) * N_apply(p, x)
     if p.theta != 1.0:
         out = out + (p.dt * (1.0 - p.theta)) * N_apply(p, x_prev)

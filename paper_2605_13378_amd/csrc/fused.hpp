@@ -148,6 +148,16 @@ __device__ __forceinline__ void gather(const T* a, int c, int nx, int ny, int ce
     o[f].d = a[at<P, T>(f, cd, cells)];
     o[f].u = a[at<P, T>(f, cu, cells)];
   }
+  if constexpr (P::kCorners) {
+    const int jd = cd / nx, ju = cu / nx;
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) {
+      o[f].dl = a[at<P, T>(f, jd * nx + il, cells)];
+      o[f].dr = a[at<P, T>(f, jd * nx + ir, cells)];
+      o[f].ul = a[at<P, T>(f, ju * nx + il, cells)];
+      o[f].ur = a[at<P, T>(f, ju * nx + ir, cells)];
+    }
+  }
 }
 
 // out = F(x) (OP_RES), J(x) v (OP_AD) or (F(x + eps v) - F(x)) / eps (OP_FD),
@@ -178,13 +188,7 @@ __device__ void eval(const typename P::template K<T>& k, const FusedArgs<T>& a, 
       gather<P, T>(v, c, a.nx, a.ny, a.cells, vn);
       Nbr<dual<T>> dn[P::NF];
 #pragma unroll
-      for (int f = 0; f < P::NF; ++f) {
-        dn[f].c = {xn[f].c, vn[f].c};
-        dn[f].l = {xn[f].l, vn[f].l};
-        dn[f].r = {xn[f].r, vn[f].r};
-        dn[f].d = {xn[f].d, vn[f].d};
-        dn[f].u = {xn[f].u, vn[f].u};
-      }
+      for (int f = 0; f < P::NF; ++f) nbr_dual<P, T>(xn[f], vn[f], dn[f]);
       dual<T> nv[P::NF];
       P::template N<T, dual<T>>(k, dn, nv);
 #pragma unroll
@@ -194,13 +198,7 @@ __device__ void eval(const typename P::template K<T>& k, const FusedArgs<T>& a, 
       gather<P, T>(v, c, a.nx, a.ny, a.cells, vn);
       Nbr<T> yn[P::NF];
 #pragma unroll
-      for (int f = 0; f < P::NF; ++f) {
-        yn[f].c = xn[f].c + eps_s * vn[f].c;
-        yn[f].l = xn[f].l + eps_s * vn[f].l;
-        yn[f].r = xn[f].r + eps_s * vn[f].r;
-        yn[f].d = xn[f].d + eps_s * vn[f].d;
-        yn[f].u = xn[f].u + eps_s * vn[f].u;
-      }
+      for (int f = 0; f < P::NF; ++f) nbr_axpy<P, T>(xn[f], eps_s, vn[f], yn[f]);
       T n0[P::NF], n1[P::NF];
       P::template N<T, T>(k, xn, n0);
       P::template N<T, T>(k, yn, n1);

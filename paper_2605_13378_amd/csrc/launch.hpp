@@ -17,7 +17,7 @@
 
 namespace jfnk {
 
-enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4, kSuOlson = 5 };
+enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4, kSuOlson = 5, kMaxwell = 6 };
 
 // Kernel timing: when the host driver sets g_timing around one launch, the
 // launch goes through hipExtLaunchKernelGGL with start/stop events attached
@@ -50,7 +50,9 @@ extern thread_local KernelTiming* g_timing;
 // Elements per thread of the stencil kernel's vector path (16-byte accesses).
 template <class T>
 constexpr int stencil_vec(int pid) {
-  return pid == kKerr ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
+  // 8-byte accesses for the interleaved Kerr pairs and the four-plane Maxwell
+  // field (whose corner halos would not fit the registers at 16 bytes)
+  return (pid == kKerr || pid == kMaxwell) ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
 }
 // Elements per thread of the streaming Krylov kernels (16-byte accesses; the
 // FP64 passes over 17..32 basis vectors use 8-byte accesses so that the

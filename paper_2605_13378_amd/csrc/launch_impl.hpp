@@ -51,7 +51,7 @@ static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a,
 template <class P, class T, class VT>
 static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
                                       const Coefs& c, int cap, hipStream_t s, int* nblocks) {
-  constexpr int V = P::kInterleaved ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
+  constexpr int V = (P::kInterleaved || P::kCorners) ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
   const int vec = vectorized ? V : 1;
   const StencilPlan p = stencil_plan(pid, a.nx, a.ny, vec, cap);
   if (nblocks) *nblocks = p.grid;
@@ -80,6 +80,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
       return stencil_for_problem<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kSuOlson:
       return stencil_for_problem<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+    case kMaxwell:
+      return stencil_for_problem<MaxwellTEOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;
   }
@@ -245,6 +247,8 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
       return fused_for_problem<RD2DOp, T>(a, lds, s);
     case kSuOlson:
       return fused_for_problem<SuOlsonOp, T>(a, lds, s);
+    case kMaxwell:
+      return fused_for_problem<MaxwellTEOp, T>(a, lds, s);
     default:
       return hipErrorInvalidValue;
   }

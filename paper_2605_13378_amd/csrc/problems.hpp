@@ -16,6 +16,9 @@
 //                 homogeneous Dirichlet boundary nodes are identity rows.
 //   Su-Olson:     N = (-(1/3) Lap U + (U - V), -xi (U - V))  (Appendix A.2)
 //                 Dirichlet boundary nodes are identity rows.
+//   Maxwell TE:   N = curl curl E - omega^2 eps(E) E on (Re Ex, Im Ex, Re Ey, Im Ey)
+//                 (Appendix A.4), eps = (1 - i loss)(1 + chi |E|), the mixed
+//                 derivative D_x D_y from the diagonal neighbours; PEC nodes held.
 #pragma once
 
 #include "common.hpp"
@@ -24,8 +27,52 @@ namespace jfnk {
 
 template <class S>
 struct Nbr {
-  S c, l, r, d, u;  // centre, x-1, x+1, y-1, y+1
+  S c, l, r, d, u;     // centre, x-1, x+1, y-1, y+1
+  S dl, dr, ul, ur;    // (x-1, y-1), (x+1, y-1), (x-1, y+1), (x+1, y+1): operators with kCorners only
 };
+
+// Dual-number neighbourhood (value x, tangent v) and the FD trial point x + e v.
+template <class P, class T>
+__device__ __forceinline__ void nbr_dual(const Nbr<T>& x, const Nbr<T>& v, Nbr<dual<T>>& o) {
+  o.c = {x.c, v.c};
+  o.l = {x.l, v.l};
+  o.r = {x.r, v.r};
+  o.d = {x.d, v.d};
+  o.u = {x.u, v.u};
+  if constexpr (P::kCorners) {
+    o.dl = {x.dl, v.dl};
+    o.dr = {x.dr, v.dr};
+    o.ul = {x.ul, v.ul};
+    o.ur = {x.ur, v.ur};
+  }
+}
+
+template <class P, class T>
+__device__ __forceinline__ void nbr_axpy(const Nbr<T>& x, T e, const Nbr<T>& v, Nbr<T>& o) {
+  o.c = x.c + e * v.c;
+  o.l = x.l + e * v.l;
+  o.r = x.r + e * v.r;
+  o.d = x.d + e * v.d;
+  o.u = x.u + e * v.u;
+  if constexpr (P::kCorners) {
+    o.dl = x.dl + e * v.dl;
+    o.dr = x.dr + e * v.dr;
+    o.ul = x.ul + e * v.ul;
+    o.ur = x.ur + e * v.ur;
+  }
+}
+
+// |E| = sqrt(s) with the AD guard of the Maxwell-Kerr permittivity: the
+// tangent of |E| is 0 where s = 0 (sqrt is not differentiable there).
+template <class T>
+__device__ __forceinline__ T guarded_norm(T s) {
+  return sqrt(s);
+}
+template <class T>
+__device__ __forceinline__ dual<T> guarded_norm(dual<T> s) {
+  const T v = sqrt(s.v);
+  return {v, v > T(0) ? s.t / (T(2) * v) : T(0)};
+}
 
 // Host-filled coefficient block (double); kernels convert to T.
 struct Coefs {
@@ -37,6 +84,7 @@ struct Burgers1DOp {
   static constexpr bool kDim2 = false;
   static constexpr bool kPeriodic = true;
   static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = false;
   // c: 0 = 1/(2h), 1 = nu/h^2
   template <class T>
   struct K {
@@ -61,6 +109,7 @@ struct Burgers2DOp {
   static constexpr bool kDim2 = true;
   static constexpr bool kPeriodic = true;
   static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = false;
   // c: 0 = 1/(2hx), 1 = 1/(2hy), 2 = nu/hx^2, 3 = nu/hy^2
   template <class T>
   struct K {
@@ -92,6 +141,7 @@ struct GrayScottOp {
   static constexpr bool kDim2 = true;
   static constexpr bool kPeriodic = true;
   static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = false;
   // c: 0 = D/hx^2, 1 = D/hy^2, 2 = Dv/hx^2, 3 = Dv/hy^2, 4 = F + k, 5 = F
   template <class T>
   struct K {
@@ -119,6 +169,7 @@ struct KerrOp {
   static constexpr bool kDim2 = true;
   static constexpr bool kPeriodic = false;
   static constexpr bool kInterleaved = true;
+  static constexpr bool kCorners = false;
   // c: 0 = 1/hx^2, 1 = 1/hy^2, 2 = k0^2, 3 = eps_re, 4 = eps_im, 5 = chi3
   template <class T>
   struct K {
@@ -148,6 +199,7 @@ struct RD2DOp {
   static constexpr bool kDim2 = true;
   static constexpr bool kPeriodic = false;
   static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = false;
   // c: 0 = D/hx^2, 1 = D/hy^2
   template <class T>
   struct K {
@@ -173,6 +225,7 @@ struct SuOlsonOp {
   static constexpr bool kDim2 = true;
   static constexpr bool kPeriodic = false;
   static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = false;
   // c: 0 = 1/(3 hx^2), 1 = 1/(3 hy^2), 2 = xi
   template <class T>
   struct K {
@@ -189,6 +242,43 @@ struct SuOlsonOp {
     const S lu = k.dx * ((u.r - T(2) * u.c) + u.l) + k.dy * ((u.u - T(2) * u.c) + u.d);
     out[0] = d - lu;
     out[1] = -(k.xi * d);
+  }
+  __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
+    return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+  }
+};
+
+struct MaxwellTEOp {
+  static constexpr int NF = 4;  // planes Re Ex, Im Ex, Re Ey, Im Ey
+  static constexpr bool kDim2 = true;
+  static constexpr bool kPeriodic = false;
+  static constexpr bool kInterleaved = false;
+  static constexpr bool kCorners = true;
+  // c: 0 = 1/hx^2, 1 = 1/hy^2, 2 = 1/(4 hx hy), 3 = omega^2, 4 = loss, 5 = chi
+  template <class T>
+  struct K {
+    T ixx, iyy, ixy, w2, loss, chi;
+  };
+  template <class T>
+  __host__ __device__ static K<T> make(const Coefs& c) {
+    return {T(c.c[0]), T(c.c[1]), T(c.c[2]), T(c.c[3]), T(c.c[4]), T(c.c[5])};
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static S dxdy(const K<T>& k, const Nbr<S>& q) {
+    return k.ixy * ((q.ur - q.ul) - (q.dr - q.dl));
+  }
+  template <class T, class S>
+  __device__ __forceinline__ static void N(const K<T>& k, const Nbr<S> (&f)[4], S (&out)[4]) {
+    const S xr = f[0].c, xi = f[1].c, yr = f[2].c, yi = f[3].c;
+    const S m = T(1) + k.chi * guarded_norm(((xr * xr + xi * xi) + yr * yr) + yi * yi);
+    const S dyy0 = k.iyy * ((f[0].u - T(2) * xr) + f[0].d);
+    const S dyy1 = k.iyy * ((f[1].u - T(2) * xi) + f[1].d);
+    const S dxx2 = k.ixx * ((f[2].r - T(2) * yr) + f[2].l);
+    const S dxx3 = k.ixx * ((f[3].r - T(2) * yi) + f[3].l);
+    out[0] = (dxdy(k, f[2]) - dyy0) - k.w2 * (m * (xr + k.loss * xi));
+    out[1] = (dxdy(k, f[3]) - dyy1) - k.w2 * (m * (xi - k.loss * xr));
+    out[2] = (dxdy(k, f[0]) - dxx2) - k.w2 * (m * (yr + k.loss * yi));
+    out[3] = (dxdy(k, f[1]) - dxx3) - k.w2 * (m * (yi - k.loss * yr));
   }
   __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
     return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;

@@ -873,6 +873,14 @@ jfnk_status fill_problem(jfnk_solver* s) {
       c.c[1] = 1.0 / (3.0 * p.hy * p.hy);
       c.c[2] = p.p[0];
       break;
+    case JFNK_MAXWELL2D:
+      c.c[0] = 1.0 / (p.hx * p.hx);
+      c.c[1] = 1.0 / (p.hy * p.hy);
+      c.c[2] = 1.0 / (4.0 * p.hx * p.hy);
+      c.c[3] = p.p[0] * p.p[0];
+      c.c[4] = p.p[1];
+      c.c[5] = p.p[2];
+      break;
     case JFNK_KERR2D:
       c.c[0] = 1.0 / (p.hx * p.hx);
       c.c[1] = 1.0 / (p.hy * p.hy);
@@ -885,7 +893,7 @@ jfnk_status fill_problem(jfnk_solver* s) {
       s->err = "unknown problem id";
       return JFNK_ERR_ARG;
   }
-  if (p.id == JFNK_KERR2D) {
+  if (p.id == JFNK_KERR2D || p.id == JFNK_MAXWELL2D) {
     s->alpha = 0.0;
     s->cN = 1.0;
     s->beta = -1.0;
@@ -902,7 +910,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
     if (why) *why = "null problem";
     return false;
   }
-  if (p->id < JFNK_BURGERS1D || p->id > JFNK_SUOLSON2D) {
+  if (p->id < JFNK_BURGERS1D || p->id > JFNK_MAXWELL2D) {
     if (why) *why = "unknown problem id";
     return false;
   }
@@ -918,7 +926,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
     if (why) *why = "grid spacing must be positive";
     return false;
   }
-  if (p->id != JFNK_KERR2D && (!(p->dt > 0.0) || !(p->theta > 0.0) || p->theta > 1.0)) {
+  if (p->id != JFNK_KERR2D && p->id != JFNK_MAXWELL2D && (!(p->dt > 0.0) || !(p->theta > 0.0) || p->theta > 1.0)) {
     if (why) *why = "time-dependent problems need dt > 0 and 0 < theta <= 1";
     return false;
   }
@@ -927,6 +935,7 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
 
 long long problem_n(const jfnk_problem* p) {
   const long long cells = (long long)p->nx * p->ny;
+  if (p->id == JFNK_MAXWELL2D) return 4 * cells;
   return (p->id == JFNK_BURGERS1D || p->id == JFNK_RD2D) ? cells : 2 * cells;
 }
 
@@ -1312,7 +1321,7 @@ jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double
   const jfnk_problem& p = s->prob;
   const long long n = s->n;
   const int sgrid = stream_grid(s, 2);
-  if (p.id == JFNK_KERR2D) {
+  if (p.id == JFNK_KERR2D || p.id == JFNK_MAXWELL2D) {
     // b = f (the source), cast to the working precision
     if (source == nullptr) {
       if (s->prec == JFNK_F64)

@@ -129,9 +129,15 @@ template <class P, class T, int VEC, int RY>
 struct Tile {
   static constexpr int NR = P::kDim2 ? RY + 2 : 1;
   static constexpr int RC = P::kDim2 ? RY : 1;
+  // rows with left/right halo words: the centre rows, or every loaded row
+  // when the operator reaches the diagonal neighbours
+  static constexpr int RH = P::kCorners ? NR : RC;
   T a[P::NF][NR][VEC];
-  T lh[P::NF][RC];
-  T rh[P::NF][RC];
+  T lh[P::NF][RH];
+  T rh[P::NF][RH];
+
+  // loaded row of halo row hh, and halo row of loaded row t
+  static __device__ __forceinline__ int halo_row(int hh) { return P::kCorners ? hh : (P::kDim2 ? hh + 1 : 0); }
 
   // Issue the loads: rows r0-1 .. r0+RY, and the left/right halo words of
   // lanes at a wavefront or grid edge (the rest come from exchange()).
@@ -153,12 +159,12 @@ struct Tile {
     const bool need_l = (lane == 0) || (col0 == 0);
     const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
 #pragma unroll
-    for (int tt = 0; tt < RC; ++tt) {
-      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 + tt, ny) : 0;
+    for (int hh = 0; hh < RH; ++hh) {
+      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + halo_row(hh), ny) : 0;
 #pragma unroll
       for (int f = 0; f < P::NF; ++f) {
-        lh[f][tt] = need_l ? to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) : T(0);
-        rh[f][tt] = need_r ? to_c<T>(load_node<P, S>(base, plane, nx, r, cr, f)) : T(0);
+        lh[f][hh] = need_l ? to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) : T(0);
+        rh[f][hh] = need_r ? to_c<T>(load_node<P, S>(base, plane, nx, r, cr, f)) : T(0);
       }
     }
   }
@@ -168,14 +174,14 @@ struct Tile {
     const bool need_l = (lane == 0) || (col0 == 0);
     const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
 #pragma unroll
-    for (int tt = 0; tt < RC; ++tt) {
-      const int t = P::kDim2 ? tt + 1 : 0;
+    for (int hh = 0; hh < RH; ++hh) {
+      const int t = halo_row(hh);
 #pragma unroll
       for (int f = 0; f < P::NF; ++f) {
         const T lv = __shfl_up(a[f][t][VEC - 1], 1, kWave);
         const T rv = __shfl_down(a[f][t][0], 1, kWave);
-        if (!need_l) lh[f][tt] = lv;
-        if (!need_r) rh[f][tt] = rv;
+        if (!need_l) lh[f][hh] = lv;
+        if (!need_r) rh[f][hh] = rv;
       }
     }
   }
@@ -188,22 +194,29 @@ struct Tile {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) a[f][t][e] *= s;
 #pragma unroll
-      for (int tt = 0; tt < RC; ++tt) {
-        lh[f][tt] *= s;
-        rh[f][tt] *= s;
+      for (int hh = 0; hh < RH; ++hh) {
+        lh[f][hh] *= s;
+        rh[f][hh] *= s;
       }
     }
   }
 
   __device__ __forceinline__ void nbr(int tt, int e, Nbr<T> (&o)[P::NF]) const {
     const int t = P::kDim2 ? tt + 1 : 0;
+    const int hc = P::kCorners ? t : tt;  // halo row of loaded row t
 #pragma unroll
     for (int f = 0; f < P::NF; ++f) {
       o[f].c = a[f][t][e];
-      o[f].l = e > 0 ? a[f][t][e - 1] : lh[f][tt];
-      o[f].r = e < VEC - 1 ? a[f][t][e + 1] : rh[f][tt];
+      o[f].l = e > 0 ? a[f][t][e - 1] : lh[f][hc];
+      o[f].r = e < VEC - 1 ? a[f][t][e + 1] : rh[f][hc];
       o[f].d = P::kDim2 ? a[f][t - 1][e] : a[f][t][e];
       o[f].u = P::kDim2 ? a[f][t + 1][e] : a[f][t][e];
+      if constexpr (P::kCorners) {
+        o[f].dl = e > 0 ? a[f][t - 1][e - 1] : lh[f][t - 1];
+        o[f].dr = e < VEC - 1 ? a[f][t - 1][e + 1] : rh[f][t - 1];
+        o[f].ul = e > 0 ? a[f][t + 1][e - 1] : lh[f][t + 1];
+        o[f].ur = e < VEC - 1 ? a[f][t + 1][e + 1] : rh[f][t + 1];
+      }
     }
   }
 };
@@ -360,13 +373,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           Vt.nbr(tt, e, vn);
           Nbr<dual<T>> dn[NF];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            dn[f].c = {xn[f].c, vn[f].c};
-            dn[f].l = {xn[f].l, vn[f].l};
-            dn[f].r = {xn[f].r, vn[f].r};
-            dn[f].d = {xn[f].d, vn[f].d};
-            dn[f].u = {xn[f].u, vn[f].u};
-          }
+          for (int f = 0; f < NF; ++f) nbr_dual<P, T>(xn[f], vn[f], dn[f]);
           dual<T> n[NF];
           P::template N<T, dual<T>>(k, dn, n);
 #pragma unroll
@@ -379,13 +386,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           Vt.nbr(tt, e, vn);
           Nbr<T> yn[NF];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            yn[f].c = xn[f].c + eps_s * vn[f].c;
-            yn[f].l = xn[f].l + eps_s * vn[f].l;
-            yn[f].r = xn[f].r + eps_s * vn[f].r;
-            yn[f].d = xn[f].d + eps_s * vn[f].d;
-            yn[f].u = xn[f].u + eps_s * vn[f].u;
-          }
+          for (int f = 0; f < NF; ++f) nbr_axpy<P, T>(xn[f], eps_s, vn[f], yn[f]);
           T n0[NF], n1[NF];
           P::template N<T, T>(k, xn, n0);
           P::template N<T, T>(k, yn, n1);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libjfnk.so")
 
 MAX_ITERS = 64
 
-PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d": 4, "suolson": 5}
+PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d": 4, "suolson": 5, "maxwell": 6}
 PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
@@ -168,6 +168,8 @@ def make_problem(spec: dict) -> Problem:
         vals = [spec["D"]]
     elif kind == "suolson":
         vals = [spec["xi"]]
+    elif kind == "maxwell":
+        vals = [spec["k0"], spec["eps_im"], spec["chi3"]]
     else:
         vals = [spec["k0"], spec.get("eps_re", 1.0), spec.get("eps_im", 0.0), spec["chi3"]]
     for i, v in enumerate(vals):

@@ -237,3 +237,34 @@ def test_suolson_mistakes_fail_a_pin(monkeypatch, bad):
     monkeypatch.setitem(oprob.SPATIAL, "suolson", bad)
     _expect_failure(tso.test_suolson_sine_modes_closed_form, 17, 13, 0.5, False)
     _expect_failure(tso.test_suolson_jacobian_is_the_constant_hand_derived_matrix)
+
+
+import test_oracle_maxwell as tmx  # noqa: E402
+
+
+def test_maxwell_guard_removed(monkeypatch):
+    from oracle.dual import Dual
+
+    def unguarded(s):
+        if isinstance(s, Dual):
+            v = np.sqrt(s.val)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                return Dual(v, s.tan / (2.0 * v))
+        return np.sqrt(s)
+
+    monkeypatch.setattr(oprob, "guarded_norm", unguarded)
+    _expect_failure(tmx.test_maxwell_guard_gives_the_born_operator_at_zero)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("nxr = dxdy(eyr) - d2(exr, p.hy, 0)", "nxr = -dxdy(eyr) - d2(exr, p.hy, 0)"),      # mixed-derivative sign
+    ("(m * (exi - loss * exr))", "(m * (exi + loss * exr))"),                           # sign of the loss
+    ("nyr = dxdy(exr) - d2(eyr, p.hx, 1)", "nyr = dxdy(exr) - d2(eyr, p.hy, 0)"),      # wrong direction
+])
+def test_maxwell_mistakes_fail_a_pin(monkeypatch, old, new):
+    src = inspect.getsource(oprob.maxwell_residual)
+    assert old in src
+    ns = dict(vars(oprob))
+    exec(compile(src.replace(old, new, 1), "maxwell_mutant", "exec"), ns)
+    monkeypatch.setattr(oprob, "maxwell_residual", ns["maxwell_residual"])
+    _expect_failure(tmx.test_maxwell_sine_modes_closed_form, 17, 13, 0.05)

@@ -103,9 +103,40 @@ def suolson_initial(n: int = 512, seed: int = 0, ny: int | None = None, L: float
     return np.concatenate([U.ravel(), V.ravel()]), np.concatenate([Q.ravel(), np.zeros(n * ny)])
 
 
+def maxwell_spec(n: int = 512, omega: float = 2.5, chi: float = 0.05, loss: float = 0.05,
+                 ny: int | None = None) -> dict:
+    """Paper-form Maxwell-Kerr (2D TE, Appendix A.4) on the node grid of [0,1]^2 with PEC
+    boundary nodes; mu0 = eps0 = 1, so the frequency omega is stored as k0."""
+    ny = n if ny is None else ny
+    return dict(kind="maxwell", nx=n, ny=ny, hx=1.0 / (n - 1), hy=1.0 / (ny - 1), dt=0.0, theta=1.0,
+                k0=omega, eps_im=loss, chi3=chi)
+
+
+def maxwell_source(n: int = 512, omega: float = 2.5, kind: str = "dipole", sigma: float = 0.05,
+                   x0: float = 0.5, ys: tuple = (0.4, 0.6), ny: int | None = None) -> np.ndarray:
+    """f = i omega J for the paper's two currents (J_y = 0): a Gaussian J_x at (x0, ys[0]) or the
+    antisymmetric dipole (Gaussians at (x0, ys[0]) minus (x0, ys[1])); zero on the boundary nodes.
+    Planes (Re fx, Im fx, Re fy, Im fy)."""
+    ny = n if ny is None else ny
+    x = np.linspace(0.0, 1.0, n)[None, :]
+    y = np.linspace(0.0, 1.0, ny)[:, None]
+
+    def g(yc):
+        return np.exp(-((x - x0) ** 2 + (y - yc) ** 2) / (2 * sigma * sigma))
+
+    J = g(ys[0]) if kind == "gaussian" else g(ys[0]) - g(ys[1])
+    J = J * np.ones((ny, n))
+    J[0, :] = J[-1, :] = 0.0
+    J[:, 0] = J[:, -1] = 0.0
+    z = np.zeros(n * ny)
+    return np.concatenate([z, (omega * J).ravel(), z, z])
+
+
 def n_unknowns(spec: dict) -> int:
     """Number of real unknowns of a problem spec."""
     cells = spec["nx"] * spec["ny"]
+    if spec["kind"] == "maxwell":
+        return 4 * cells
     return cells if spec["kind"] in ("burgers1d", "rd2d") else 2 * cells
 
 
