@@ -55,6 +55,9 @@ def case(kind: str, nx: int, ny: int | None = None, seed: int = 0):
     if kind == "rd2d":
         spec = W.rd2d_spec(nx, ny=ny)
         return spec, W.rd2d_initial(nx, seed, ny=ny), None
+    if kind == "maxwell":
+        spec = W.maxwell_spec(nx, ny=ny)
+        return spec, np.zeros(4 * nx * ny), W.maxwell_source(nx, ny=ny)
     if kind == "suolson":
         x0, src = W.suolson_initial(nx, seed, ny=ny)
         return W.suolson_spec(nx, ny=ny), x0, src

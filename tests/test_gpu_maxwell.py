@@ -1,0 +1,50 @@
+"""GPU parity of the paper-form 2D TE Maxwell-Kerr problem (Appendix A.4).
+
+Element-wise residual/JVP parity runs in test_gpu_kernels (the Maxwell rows,
+incl. 512^2); here: the guard (the AD JVP at E = 0 is finite and equals the
+oracle's Born operator), and Newton from E = 0 (the first step is the Born
+solve) per iterate against the oracle on a 16 x 16 grid.  The unpreconditioned
+GMRES(30) needs hundreds of restart cycles per step on this indefinite
+curl-curl operator; each Newton correction is fixed only to the Krylov
+tolerance (1e-8 relative residual) times the conditioning of J, and two
+implementations that sum in different orders stop at different points inside
+that band, so iterates and residual ratios are compared at 1e-6 and Krylov
+counts within 10%.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import dev, gpu_available, host, wdtype
+from oracle import Problem, jvp_ad
+from test_gpu_solver import compare_newton, solver
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_maxwell_guard_born_operator(prec, tol):
+    spec, x0, src = W.config("maxwell", n=96)
+    p = Problem.from_spec(spec)
+    v = W.random_vector(p.n, 8)
+    s = solver(spec, prec, x0, src)
+    jv = host(s.jvp(dev(np.zeros(p.n), wdtype(prec)), dev(v, wdtype(prec)), mode="ad"))
+    _, ref = jvp_ad(p, np.zeros(p.n), v, None, src)
+    assert np.all(np.isfinite(jv))
+    assert np.max(np.abs(jv - ref)) <= tol * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_newton_maxwell_from_born(orth):
+    spec = W.maxwell_spec(16, omega=2.5)
+    src = W.maxwell_source(16, omega=2.5)
+    info, ref = compare_newton(spec, np.zeros(4 * 16 * 16), src, "f64", "ad", 1e-6, orth=orth, krylov_slack=0.1,
+                               max_newton=20)
+    assert info["converged"]

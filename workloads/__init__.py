@@ -346,6 +346,9 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
         nn = 512 if n is None else n
         spec = rd2d_spec(nn)
         return spec, rd2d_initial(nn, seed), None
+    if name == "maxwell":
+        nn = 512 if n is None else n
+        return maxwell_spec(nn), np.zeros(4 * nn * nn), maxwell_source(nn)
     if name == "suolson":
         nn = 512 if n is None else n
         x0, src = suolson_initial(nn, seed)
