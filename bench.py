@@ -446,6 +446,46 @@ def suolson_rows(torch, steps, budget_s=3.0):
     return rows
 
 
+def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50, budget_s=25.0):
+    """Paper-form Maxwell-Kerr (2D TE): JVP bandwidth at 512^2 and a frequency sweep at n^2 with
+    continuation: the first frequency starts from the Born guess (E = 0, whose first Newton step
+    is the Born solve), each later one from the previous converged field; a frequency fails when
+    Newton does not reach tol_Newton within max_newton iterations, and the next one then starts
+    again from the Born guess."""
+    import workloads as W
+    from paper_2605_13378_amd import Solver
+
+    out = {"jvp_512": {}, "sweep": []}
+    spec, x0, src = W.config("maxwell")
+    nn = W.n_unknowns(spec)
+    for pr in ("f32", "f64"):
+        s = Solver(spec, pr, m=30)
+        s.set_previous(None, torch.tensor(src, dtype=torch.float64, device="cuda"))
+        for mode in ("ad", "fd"):
+            out["jvp_512"][f"{pr}-{mode}"] = jvp_bandwidth(s, torch, nn, pr, mode)
+        log(f"[bench] maxwell jvp 512^2 {pr}: {out['jvp_512']}")
+        s.close()
+    x = torch.zeros(4 * n * n, dtype=torch.float64, device="cuda")
+    t_start = time.perf_counter()
+    for om in omegas:
+        if time.perf_counter() - t_start > budget_s:
+            break
+        s = Solver(W.maxwell_spec(n, omega=om), "f64", m=30)
+        s.set_previous(None, torch.tensor(W.maxwell_source(n, omega=om), dtype=torch.float64, device="cuda"))
+        t0 = time.perf_counter()
+        xn, info = s.newton_solve(x, max_newton=max_newton)
+        el = time.perf_counter() - t0
+        ok = info["converged"]
+        row = dict(omega=om, converged=ok, newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                   final_rel_res=info["rel_res"][-1], seconds=round(el, 3),
+                   start="previous" if bool(x.abs().sum() > 0) else "born")
+        out["sweep"].append(row)
+        log(f"[bench] maxwell sweep {n}^2: {row}")
+        x = xn if ok else torch.zeros_like(x)
+        s.close()
+    return out
+
+
 def paper_burgers_rows(torch, steps=100, n=256, budget_s=12.0):
     """The paper's JVP-cost experiment (its Table 1: 256^2 Burgers TGV, 100 time steps) and the
     double shear layer at the same size: per combination of JVP and precision, the average
@@ -541,6 +581,7 @@ def main():
     ap.add_argument("--no-bicgstab", action="store_true", help="skip the Newton-BiCGSTAB rows")
     ap.add_argument("--no-rd", action="store_true",
                     help="skip the reaction-diffusion and Su-Olson Krylov-method rows")
+    ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell-Kerr TE rows")
     ap.add_argument("--no-paper-burgers", action="store_true",
                     help="skip the 256^2 Burgers TGV/DSL rows (the paper's JVP-cost experiment)")
     ap.add_argument("--kerr-newton", action="store_true",
@@ -700,6 +741,11 @@ def main():
         log("[bench] reaction-diffusion 512^2 rows (CG / BiCGSTAB / GMRES)")
         rd = rd_rows(torch, args.steps)
 
+    mx = None
+    if not args.no_maxwell:
+        log("[bench] Maxwell-Kerr TE rows")
+        mx = maxwell_rows(torch)
+
     so = None
     if not args.no_rd:
         log("[bench] Su-Olson 512^2 rows")
@@ -767,6 +813,7 @@ def main():
         "reaction_diffusion_512": rd,
         "burgers2d_256_tgv_dsl": pb,
         "suolson_512": so,
+        "maxwell_te": mx,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,
