@@ -248,6 +248,10 @@ struct Impl {
     return (int)std::max<long long>(1, std::min<long long>(need, (two ? 2LL : 1LL) * s->cu));
   }
 
+  // Grid of the DCGS2 update pass (and the row count of its partial sums,
+  // which the next Arnoldi JVP and the V y kernel reduce).
+  static int dcgs_grid(const jfnk_solver* s, int K) { return cgs_grid(s, K <= 16 ? 32 : K); }
+
   static double* part(jfnk_solver* s, int region) { return s->parts + (size_t)region * s->part_rows * kMaxCols; }
   static PartSink sink(jfnk_solver* s, int region) { return PartSink{part(s, region), (int)s->part_rows}; }
   static Partials parts(jfnk_solver* s, int region, int nb) { return Partials{part(s, region), nb, (int)s->part_rows}; }
@@ -306,7 +310,7 @@ struct Impl {
       a.arn_j = arn_j;
       a.lagged = lagged ? 1 : 0;
       // the sums that complete column arn_j - 1: pass C's (CGS2) or the update pass's (DCGS2)
-      a.pc = lagged ? parts(s, 1, cgs_grid(s, arn_j > 0 ? arn_j : 1)) : parts(s, 2, cgs_grid(s, arn_j > 0 ? arn_j : 1));
+      a.pc = lagged ? parts(s, 1, dcgs_grid(s, arn_j > 0 ? arn_j : 1)) : parts(s, 2, cgs_grid(s, arn_j > 0 ? arn_j : 1));
       a.host_flags = s->dflags;
       a.Vb = reinterpret_cast<const W*>(basis(s, 0));
       a.vstride = s->npad;
@@ -417,7 +421,7 @@ struct Impl {
         if (lagged) {
           // one update pass: v_j completed, the next vector projected once
           ProfScope ps(s, PK_D, (double)s->n * ((K + 2) * sizeof(VT) + sizeof(T)));
-          JFNK_HIP(s, launch_dcgs<T, VT>(ka, cgs_grid(s, K), s->stream));
+          JFNK_HIP(s, launch_dcgs<T, VT>(ka, dcgs_grid(s, K), s->stream));
         } else {
           {
             ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
@@ -435,7 +439,9 @@ struct Impl {
       flags[jmax] = -1;
       {
         VyArgs<T, VT> va{s->npad, basis(s, 0), s->npad, dxi, updated ? 0 : 1, jmax, s->ctl,
-                         parts(s, lagged ? 1 : 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)), sink(s, 4), s->dflags,
+                         lagged ? parts(s, 1, dcgs_grid(s, jmax >= 0 ? jmax + 1 : 1))
+                                : parts(s, 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)),
+                         sink(s, 4), s->dflags,
                          lagged ? 1 : 0};
         ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
         JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
