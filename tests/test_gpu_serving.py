@@ -143,3 +143,47 @@ def test_submit_rejects_oversized_and_invalid():
     with pytest.raises(JfnkError):
         b.submit(bad, np.zeros(0))
     b.close()
+
+
+def mixed_kind_requests():
+    """Every problem kind and Krylov method in one stream (FP64)."""
+    reqs = []
+    spec, xp = W.rd2d_spec(48), W.rd2d_initial(48, 1)
+    reqs.append((spec, xp, None, dict(krylov="cg")))
+    xs, src = W.suolson_initial(40, 2)
+    reqs.append((W.suolson_spec(40), xs, src, dict(krylov="bicgstab")))
+    spec, xp = dict(W.grayscott_spec(64)), W.grayscott_initial(64, 3, side_frac=1 / 8, patches=6)
+    reqs.append((spec, xp, None, dict(orth="dcgs2")))
+    reqs.append((W.maxwell_spec(16, omega=2.5), np.zeros(4 * 16 * 16), W.maxwell_source(16, omega=2.5),
+                 dict(max_newton=20)))
+    spec, x0 = W.burgers2d_paper_case("dsl", 32)
+    reqs.append((spec, x0, None, dict(orth="cgs2")))
+    reqs.append((W.rd2d_spec(32), W.rd2d_initial(32, 4), None, dict(krylov="bicgstab")))
+    return reqs
+
+
+def test_mixed_problem_kinds_and_methods_alone_equals_mix():
+    from paper_2605_13378_amd import Batch
+
+    reqs = mixed_kind_requests()
+    alone = []
+    b1 = Batch("f64", m=30, max_slots=1)
+    for spec, xp, src, o in reqs:
+        alone.append(b1.wait(b1.submit(spec, xp, src, **o)))
+    b1.close()
+    b8 = Batch("f64", m=30, max_slots=8)
+    tickets = [b8.submit(spec, xp, src, **o) for spec, xp, src, o in reqs]
+    mixed = [b8.wait(t) for t in tickets]
+    b8.close()
+    for (spec, xp, src, o), (xa, ia), (xm, im) in zip(reqs, alone, mixed):
+        assert np.array_equal(xa, xm), spec["kind"]
+        assert ia["krylov_iters"] == im["krylov_iters"] and ia["newton_iters"] == im["newton_iters"]
+        assert ia["converged"], (spec["kind"], ia)
+        # against the oracle with the same method and Gram-Schmidt form
+        p = Problem.from_spec(spec)
+        opts = NewtonOptions.for_precision("f64", krylov=o.get("krylov", "gmres"), orth=o.get("orth", "dcgs2"),
+                                           max_newton=o.get("max_newton", 15))
+        xr, ir = newton_solve(p, xp, opts, source=src)
+        assert ir.converged and ir.newton_iters == ia["newton_iters"], (spec["kind"], ir.newton_iters, ia)
+        tol = 1e-6 if spec["kind"] == "maxwell" else 1e-10
+        assert np.linalg.norm(xa - xr) <= tol * max(1.0, np.linalg.norm(xr)), spec["kind"]
