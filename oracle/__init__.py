@@ -16,6 +16,8 @@ Newton-Krylov Solvers via Automatic Differentiation"):
 * ``gmres``: restarted GMRES(m), CGS2 Arnoldi, Givens least squares.
 * ``bicgstab``: BiCGSTAB, the paper's short-recurrence nonsymmetric method.
 * ``cg``: conjugate gradients for the SPD reaction-diffusion linearization.
+* ``precond``: the block-diagonal CSLP preconditioner of the Maxwell-Kerr
+  problem (Appendix A.4), applied on the right of GMRES.
 * ``newton``: inexact Newton with backtracking line search and the
   failure classification of Section 3.4.
 
@@ -27,10 +29,11 @@ the paper does not fix: they are a reading, pinned only by the Armijo property
 (parity of the constants themselves unpinned).
 """
 
-from . import bicgstab, cg, dual, gmres, jvp, newton, problems  # noqa: F401
+from . import bicgstab, cg, dual, gmres, jvp, newton, precond, problems  # noqa: F401
 from .bicgstab import BicgstabInfo, bicgstab as bicgstab_solve  # noqa: F401
 from .cg import CgInfo, cg as cg_solve  # noqa: F401
 from .gmres import GmresInfo, gmres as gmres_solve  # noqa: F401
 from .jvp import EPS_MACH, EPS_NORMALIZED, EPS_PAPER, fd_step, jvp_ad, jvp_fd  # noqa: F401
 from .newton import NewtonInfo, NewtonOptions, newton_solve, run_failed, step_failed  # noqa: F401
+from .precond import cslp_diagonal, cslp_solve  # noqa: F401
 from .problems import Problem, residual  # noqa: F401

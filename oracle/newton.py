@@ -27,6 +27,7 @@ from . import gmres as gm
 from .bicgstab import bicgstab
 from .cg import cg
 from .jvp import EPS_MACH, EPS_PAPER, fd_step, jvp_ad, jvp_fd
+from .precond import cslp_solve
 from .problems import Problem, residual
 
 OK = "ok"
@@ -50,6 +51,7 @@ class NewtonOptions:
     breakdown_tol: float = 1e-14
     krylov: str = "gmres"  # 'gmres' | 'bicgstab' | 'cg' (the last two capped at max_restarts iterations)
     orth: str = "cgs2"  # GMRES Gram-Schmidt: 'cgs2' or 'dcgs2' (second pass delayed one step)
+    precond: str = "none"  # 'none' | 'cslp' (Maxwell-Kerr, GMRES only: right preconditioning)
 
     @classmethod
     def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
@@ -114,7 +116,24 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
                 eps = opts.fd_eps if opts.fd_eps > 0.0 else fd_step(opts.eps_rule, opts.eps_mach, _x, v)
                 return jvp_fd(p, _x, v, eps, x_prev, source, Fx=_F)
 
-        if opts.krylov == "bicgstab":
+        if opts.precond == "cslp":
+            # right preconditioning (Appendix A.4): GMRES on J M^{-1}, dx = M^{-1} z
+            if opts.krylov != "gmres":
+                raise ValueError("the CSLP preconditioner is applied with GMRES")
+
+            def minv(v, _x=x):
+                return cslp_solve(p, _x, v)
+
+            def pmatvec(z, _mv=matvec, _minv=minv):
+                return _mv(_minv(z))
+
+            z, ginfo = gm.gmres(pmatvec, -F, m=opts.m, tol=opts.tol_krylov, max_restarts=opts.max_restarts,
+                                breakdown_tol=opts.breakdown_tol, orth=opts.orth)
+            dx = minv(z)
+            info.restarts += ginfo.cycles
+        elif opts.precond != "none":
+            raise ValueError(opts.precond)
+        elif opts.krylov == "bicgstab":
             dx, ginfo = bicgstab(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
         elif opts.krylov == "cg":
             dx, ginfo = cg(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)

@@ -268,3 +268,42 @@ def test_maxwell_mistakes_fail_a_pin(monkeypatch, old, new):
     exec(compile(src.replace(old, new, 1), "maxwell_mutant", "exec"), ns)
     monkeypatch.setattr(oprob, "maxwell_residual", ns["maxwell_residual"])
     _expect_failure(tmx.test_maxwell_sine_modes_closed_form, 17, 13, 0.05)
+
+
+import oracle.newton as onewton  # noqa: E402
+import oracle.precond as oprec  # noqa: E402
+import test_oracle_cslp as tcs  # noqa: E402
+
+
+@pytest.mark.parametrize("old,new,pin", [
+    ("2.0 / (p.hy * p.hy) - w2 * eps_p", "2.0 / (p.hx * p.hx) - w2 * eps_p", "born"),         # hx / hy swapped
+    ("(1.0 - 1j * p.eps_im)", "(1.0 + 1j * p.eps_im)", "born"),                                # sign of the loss
+    ("(1.0 + p.chi3 * absE)", "(1.0 + p.chi3 * absE * absE)", "field"),                       # |E|^2 for |E|
+    ("eps_p = eps * (1.0 - 1j * damping)", "eps_p = eps", "damping"),                         # damping dropped
+    ("np.where(inner, 2.0 / (p.hx * p.hx) - w2 * eps_p, 1.0 + 0j)",
+     "2.0 / (p.hx * p.hx) - w2 * eps_p", "boundary"),                                          # boundary not identity
+])
+def test_cslp_mistakes_fail_a_pin(monkeypatch, old, new, pin):
+    src = inspect.getsource(oprec.cslp_diagonal)
+    assert old in src
+    ns = dict(vars(oprec))
+    exec(compile(src.replace(old, new, 1), "cslp_mutant", "exec"), ns)
+    monkeypatch.setattr(oprec, "cslp_diagonal", ns["cslp_diagonal"])
+    monkeypatch.setattr(tcs, "cslp_diagonal", ns["cslp_diagonal"])
+    if pin == "born":
+        _expect_failure(tcs.test_undamped_cslp_is_the_born_jacobian_diagonal, 9, 7)
+    elif pin == "field":
+        _expect_failure(tcs.test_undamped_cslp_follows_the_local_field, 0)
+    elif pin == "damping":
+        _expect_failure(tcs.test_damping_scales_the_permittivity_term_only)
+    else:
+        _expect_failure(tcs.test_boundary_nodes_are_identity)
+
+
+def test_cslp_update_left_in_the_preconditioned_space(monkeypatch):
+    src = inspect.getsource(onewton.newton_solve)
+    assert "dx = minv(z)" in src
+    ns = dict(vars(onewton))
+    exec(compile(src.replace("dx = minv(z)", "dx = z", 1), "newton_mutant", "exec"), ns)
+    monkeypatch.setattr(tcs, "newton_solve", ns["newton_solve"])
+    _expect_failure(tcs.test_newton_with_cslp_reaches_the_same_field)
