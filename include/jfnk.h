@@ -125,7 +125,23 @@ typedef struct {
   int engine;            /* jfnk_engine */
   int krylov;            /* jfnk_krylov: the linear solver of each Newton step */
   int orth;              /* jfnk_orth: Gram-Schmidt form of GMRES on the MULTI_KERNEL engine */
+  int precond;           /* jfnk_precond: right preconditioner of GMRES (default NONE) */
 } jfnk_options;
+
+/* Right preconditioner of GMRES (paper, Appendix A.4).  CSLP: the
+ * block-diagonal complex shifted-Laplacian preconditioner of the Maxwell-Kerr
+ * problem.  At each interior node the Ex pair (Re, Im) is divided, as one
+ * complex number, by M_xx = 2/hy^2 - omega^2 eps_p and the Ey pair by
+ * M_yy = 2/hx^2 - omega^2 eps_p, with the damped permittivity
+ * eps_p = (1 - loss i)(1 + chi |E|)(1 - 0.5 i) of the current Newton iterate
+ * (frozen for the linear solve); boundary nodes are left as they are.  GMRES
+ * runs on J M^{-1} and returns dx = M^{-1} z, so its residual, tolerance and
+ * reported norms are those of J dx = rhs.  Applied inside the JVP kernel (no
+ * extra pass over memory) and once to the final update.  Only for
+ * JFNK_MAXWELL2D, with GMRES on the MULTI_KERNEL engine (AUTO picks it), and
+ * with the FD JVP only under the paper's step rule or a fixed step; other
+ * combinations return JFNK_ERR_ARG. */
+typedef enum { JFNK_PRECOND_NONE = 0, JFNK_PRECOND_CSLP = 1 } jfnk_precond;
 
 /* Gram-Schmidt form of the GMRES Arnoldi step (the paper fixes none; both
  * orthogonalize twice):
@@ -255,6 +271,13 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
  * takes it from its options instead (jfnk_default_options: the same).
  * DCGS2 on an FP16S solver returns JFNK_ERR_ARG. */
 jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth);
+
+/* Preconditioner (jfnk_precond) of later jfnk_gmres calls on this solver
+ * (default NONE); jfnk_newton_solve takes it from its options instead.
+ * CSLP on a problem other than JFNK_MAXWELL2D returns JFNK_ERR_ARG, and a
+ * later jfnk_gmres call with the FD JVP under the normalized step rule does
+ * too. */
+jfnk_status jfnk_set_preconditioner(jfnk_solver* s, int precond);
 
 /* Move a solver to another stream (a hipStream_t; NULL = the default stream)
  * for its later calls.  The caller orders any work still pending on the old

@@ -140,6 +140,10 @@ template <class T, class VT>
 hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
                           const Coefs& c, int cap, hipStream_t s, int* nblocks = nullptr);
 
+// z = M^{-1} z in place for the problem's diagonal preconditioner, frozen at
+// x (problems that define one only; others return hipErrorInvalidValue).
+template <class T>
+hipError_t launch_cslp_apply(int pid, const T* x, T* z, int nx, int ny, const Coefs& c, int grid, hipStream_t s);
 template <class T, class VT>
 hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s);
 

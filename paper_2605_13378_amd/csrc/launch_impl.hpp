@@ -87,6 +87,14 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
   }
 }
 
+template <class T>
+hipError_t launch_cslp_apply(int pid, const T* x, T* z, int nx, int ny, const Coefs& c, int grid, hipStream_t s) {
+  if (pid != kMaxwell) return hipErrorInvalidValue;
+  JFNK_LAUNCH((cslp_apply_kernel<MaxwellTEOp, T>), dim3(grid), dim3(kStreamThreads), s, x, z, nx, ny,
+              (long long)nx * ny, c);
+  return hipGetLastError();
+}
+
 template <class T, class VT, int KMAX>
 static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
   constexpr int VEC = cgs_vec<T, KMAX>();
@@ -268,6 +276,7 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
   template hipError_t launch_cast<T>(long long, const double*, T*, int, hipStream_t);                           \
   template hipError_t launch_norm2<T>(long long, const T*, PartSink, int, hipStream_t);                         \
   template hipError_t launch_fill_zero<T>(long long, T*, int, hipStream_t);                                     \
+  template hipError_t launch_cslp_apply<T>(int, const T*, T*, int, int, const Coefs&, int, hipStream_t);        \
   template hipError_t launch_fused_solve<T>(int, const FusedArgs<T>&, size_t, hipStream_t);                 \
   template hipError_t launch_bi<T>(int, const BiArgs<T>&, double, int, hipStream_t);                        \
   template hipError_t launch_cg<T>(int, const CgArgs<T>&, double, int, hipStream_t);

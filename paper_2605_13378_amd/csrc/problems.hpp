@@ -283,6 +283,40 @@ struct MaxwellTEOp {
   __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
     return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
   }
+  // Block-diagonal complex shifted-Laplacian preconditioner (Appendix A.4),
+  // frozen at the state x of an interior node: v's Ex pair (Re, Im) is
+  // divided, as a complex number, by M_xx = 2/hy^2 - omega^2 eps_p and its
+  // Ey pair by M_yy = 2/hx^2 - omega^2 eps_p, with the damped permittivity
+  // eps_p = (1 - loss i)(1 + chi |E|)(1 - 0.5 i).  (Boundary nodes: identity,
+  // left to the caller.)
+  static constexpr bool kCslp = true;
+  template <class T>
+  __device__ __forceinline__ static void cslp_inv(const K<T>& k, const T (&x)[4], T (&v)[4]) {
+    const T m = T(1) + k.chi * sqrt(((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]) + x[3] * x[3]);
+    // omega^2 eps_p = w2 m ((1 - loss/2) - (loss + 1/2) i)
+    const T pr = k.w2 * m * (T(1) - T(0.5) * k.loss);
+    const T pi = -(k.w2 * m * (k.loss + T(0.5)));
+    const T mi = -pi;                       // Im M_xx = Im M_yy
+    const T mxr = T(2) * k.iyy - pr;        // Re M_xx
+    const T myr = T(2) * k.ixx - pr;        // Re M_yy
+    const T dx = T(1) / (mxr * mxr + mi * mi);
+    const T dy = T(1) / (myr * myr + mi * mi);
+    const T a0 = v[0], a1 = v[1], b0 = v[2], b1 = v[3];
+    v[0] = (a0 * mxr + a1 * mi) * dx;
+    v[1] = (a1 * mxr - a0 * mi) * dx;
+    v[2] = (b0 * myr + b1 * mi) * dy;
+    v[3] = (b1 * myr - b0 * mi) * dy;
+  }
+};
+
+// Operators with a diagonal right preconditioner (P::cslp_inv) set kCslp.
+template <class P, class = void>
+struct has_cslp {
+  static constexpr bool value = false;
+};
+template <class P>
+struct has_cslp<P, decltype((void)P::kCslp)> {
+  static constexpr bool value = P::kCslp;
 };
 
 }  // namespace jfnk

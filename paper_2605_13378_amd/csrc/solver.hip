@@ -92,6 +92,7 @@ struct jfnk_solver {
   CgCtl* hcg = nullptr;         // pinned host copy
   bool has_prev = false;
   int orth = 0;                 // Gram-Schmidt form of jfnk_gmres calls (jfnk_orth)
+  int precond = 0;              // preconditioner of jfnk_gmres calls (jfnk_precond)
   std::string err;
   bool prof = false;
   int cur_step = -1;
@@ -289,7 +290,8 @@ struct Impl {
   // *nb_out receives their row count).
   template <class W>
   static jfnk_status jvp(jfnk_solver* s, const T* x, const W* v, const double* vscale, T* Jv, T* Fout, int mode,
-                         const EpsSpec& eps, int arn_j = -1, int* nb_out = nullptr, bool lagged = false) {
+                         const EpsSpec& eps, int arn_j = -1, int* nb_out = nullptr, bool lagged = false,
+                         bool pre = false) {
     StencilArgs<T, W> a{};
     a.nx = s->prob.nx;
     a.ny = s->prob.ny;
@@ -305,6 +307,7 @@ struct Impl {
     a.beta = s->beta;
     a.vscale = vscale;
     a.eps = eps;
+    a.precond = pre ? 1 : 0;
     if (arn_j >= 0) {
       a.ctl = s->ctl;
       a.arn_j = arn_j;
@@ -339,8 +342,14 @@ struct Impl {
   static VT* basis(jfnk_solver* s, int i) { return static_cast<VT*>(s->V) + (long long)i * s->npad; }
 
   // Restarted GMRES(m) on J(x) dx = sign * R (R internal, padded), dx internal.
+  // With `pre` (right preconditioning by the problem's diagonal M, frozen at
+  // x) every JVP of the solve is applied to M^{-1} times its vector, so the
+  // iterate z and the basis live in the preconditioned space and the
+  // residual, its norm and the stopping tests are those of J dx = sign * R;
+  // dx = M^{-1} z at the end.
   static jfnk_status gmres(jfnk_solver* s, const T* x, const T* R, double sign, int m, double tol, int max_restarts,
-                           int mode, double fixed_eps, int eps_rule, double brk, GOut& go, bool lagged = false) {
+                           int mode, double fixed_eps, int eps_rule, double brk, GOut& go, bool lagged = false,
+                           bool pre = false) {
     go = GOut{};
     if constexpr (!std::is_same<T, VT>::value) lagged = false;  // FP16 storage keeps CGS2
     T* dxi = static_cast<T*>(s->dx);
@@ -361,7 +370,7 @@ struct Impl {
       const T* wr = nullptr;
       s->cur_step = -1;
       if (cycle > 0) {
-        JFNK_TRY(jvp<T>(s, x, dxi, nullptr, w, nullptr, mode, eps_restart));
+        JFNK_TRY(jvp<T>(s, x, dxi, nullptr, w, nullptr, mode, eps_restart, -1, nullptr, false, pre));
         wr = w;
       }
       {
@@ -416,7 +425,7 @@ struct Impl {
         const int K = j + 1;
         if (j >= 1) flags[j - 1] = -1;
         int nb_jvp = 0;  // the JVP carries the first projection (pass A)
-        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged));
+        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged, pre));
         KArgs<T, VT> ka{s->npad, basis(s, 0), s->npad, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1)};
         if (lagged) {
           // one update pass: v_j completed, the next vector projected once
@@ -450,6 +459,8 @@ struct Impl {
       pending_vy = true;
     }
     if (!updated) JFNK_HIP(s, launch_fill_zero<T>(s->npad, dxi, sgrid, s->stream));
+    if (pre && updated)
+      JFNK_HIP(s, launch_cslp_apply<T>(s->pid, x, dxi, s->prob.nx, s->prob.ny, s->coefs, sgrid, s->stream));
     return JFNK_OK;
   }
 
@@ -746,7 +757,8 @@ struct Impl {
       s->err = "the single-workgroup engine needs FP64 or FP32 and a problem that fits in LDS";
       return JFNK_ERR_ARG;
     }
-    if (o.krylov == JFNK_KRYLOV_GMRES && o.engine != JFNK_ENGINE_MULTI_KERNEL && fused_fits(s, o.m))
+    if (o.krylov == JFNK_KRYLOV_GMRES && o.engine != JFNK_ENGINE_MULTI_KERNEL && o.precond == JFNK_PRECOND_NONE &&
+        fused_fits(s, o.m))
       return newton_fused(s, x_user, o, info);
     const long long n = s->n;
     const bool f64 = std::is_same<T, double>::value;
@@ -794,7 +806,8 @@ struct Impl {
         }
       } else {
         JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
-                       o.fd_eps, o.eps_rule, o.breakdown_tol, go, o.orth == JFNK_ORTH_DCGS2));
+                       o.fd_eps, o.eps_rule, o.breakdown_tol, go, o.orth == JFNK_ORTH_DCGS2,
+                       o.precond == JFNK_PRECOND_CSLP));
       }
       info->krylov_iters += go.iters;
       info->restarts += go.cycles;
@@ -1035,7 +1048,7 @@ jfnk_status gmres_api(jfnk_solver* s, const T* x, const T* rhs, T* dx, int m, do
   const double brk = s->prec == JFNK_F64 ? 1e-14 : 1e-6;
   typename Impl<T, VT>::GOut go;
   JFNK_TRY(Impl<T, VT>::gmres(s, x, static_cast<const T*>(s->R), 1.0, m, tol, max_restarts, mode, eps, rule, brk, go,
-                              s->orth == JFNK_ORTH_DCGS2));
+                              s->orth == JFNK_ORTH_DCGS2, s->precond == JFNK_PRECOND_CSLP));
   JFNK_HIP(s, hipMemcpyAsync(dx, s->dx, n * sizeof(T), hipMemcpyDeviceToDevice, s->stream));
   JFNK_HIP(s, hipStreamSynchronize(s->stream));
   if (info) {
@@ -1070,6 +1083,31 @@ jfnk_status short_recurrence_api(jfnk_solver* s, int krylov, const T* x, const T
     info->status = st;
   }
   return st;
+}
+
+// The CSLP preconditioner: the Maxwell-Kerr problem only, with GMRES on the
+// multi-kernel engine; the FD JVP takes the paper's step rule (the
+// normalized rule would need the norm of M^{-1} v).
+bool precond_ok(const jfnk_solver* s, int precond, int krylov, int engine, int mode, int eps_rule, double fd_eps,
+                std::string* why) {
+  if (precond == JFNK_PRECOND_NONE) return true;
+  if (precond != JFNK_PRECOND_CSLP) {
+    *why = "unknown preconditioner";
+    return false;
+  }
+  if (s->pid != kMaxwell) {
+    *why = "the CSLP preconditioner is defined for the Maxwell-Kerr problem only";
+    return false;
+  }
+  if (krylov != JFNK_KRYLOV_GMRES || engine == JFNK_ENGINE_SINGLE_WORKGROUP) {
+    *why = "the CSLP preconditioner runs with GMRES on the multi-kernel engine";
+    return false;
+  }
+  if (mode == JFNK_JVP_FD && eps_rule == JFNK_EPS_NORMALIZED && !(fd_eps > 0.0)) {
+    *why = "the CSLP preconditioner takes the paper's FD step rule (or a fixed step)";
+    return false;
+  }
+  return true;
 }
 
 // BiCGSTAB keeps r^, r, p, v, s, t in the first six basis slots, CG r, p,
@@ -1308,6 +1346,15 @@ jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth) {
   return JFNK_OK;
 }
 
+jfnk_status jfnk_set_preconditioner(jfnk_solver* s, int precond) {
+  if (!s) return JFNK_ERR_ARG;
+  if (precond != JFNK_PRECOND_NONE &&
+      !precond_ok(s, precond, JFNK_KRYLOV_GMRES, JFNK_ENGINE_MULTI_KERNEL, JFNK_JVP_AD, JFNK_EPS_PAPER, 0.0, &s->err))
+    return JFNK_ERR_ARG;
+  s->precond = precond;
+  return JFNK_OK;
+}
+
 jfnk_status jfnk_set_stream(jfnk_solver* s, void* hip_stream) {
   if (!s) return JFNK_ERR_ARG;
   s->stream = static_cast<hipStream_t>(hip_stream);
@@ -1407,6 +1454,8 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
     s->err = "jfnk_set_previous must be called first";
     return JFNK_ERR_ARG;
   }
+  if (!precond_ok(s, s->precond, JFNK_KRYLOV_GMRES, JFNK_ENGINE_MULTI_KERNEL, mode, eps_rule, eps, &s->err))
+    return JFNK_ERR_ARG;
   if (info) std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   jfnk_status st;
@@ -1451,6 +1500,7 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
     return JFNK_ERR_ARG;
   }
   if (o.krylov != JFNK_KRYLOV_GMRES && !short_recurrence_fits(s, o.krylov, &s->err)) return JFNK_ERR_ARG;
+  if (!precond_ok(s, o.precond, o.krylov, o.engine, o.mode, o.eps_rule, o.fd_eps, &s->err)) return JFNK_ERR_ARG;
   if (!s->has_prev) {
     s->err = "jfnk_set_previous must be called first";
     return JFNK_ERR_ARG;

@@ -64,6 +64,9 @@ struct StencilArgs {
   const int* gate;
   Partials gate_parts;
   const double* gate_tol;
+  // Right preconditioning (operators with P::cslp_inv only): the JVP is
+  // applied to M^{-1} v, M frozen at x.
+  int precond;
 };
 
 template <bool PERIODIC>
@@ -221,6 +224,70 @@ struct Tile {
   }
 };
 
+// Right preconditioning of a loaded tangent tile: every value, halo words
+// included, becomes M^{-1} v at its node, with M frozen at the state values
+// loaded at the same place (identity on boundary nodes).  Row and column of
+// each word are those its load used (clamped at the non-periodic edges).
+template <class P, class T, int VEC, int RY, class KT>
+__device__ __forceinline__ void precondition_tile(const KT& k, const Tile<P, T, VEC, RY>& X, Tile<P, T, VEC, RY>& V,
+                                                  int col0, int r0, int nx, int ny) {
+  using TileT = Tile<P, T, VEC, RY>;
+  constexpr int NF = P::NF;
+  auto node = [&](int c, int r, auto get_x, auto get_v, auto set_v) {
+    if (P::boundary(c, r, nx, ny)) return;
+    T xv[NF], vv[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      xv[f] = get_x(f);
+      vv[f] = get_v(f);
+    }
+    P::template cslp_inv<T>(k, xv, vv);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) set_v(f, vv[f]);
+  };
+#pragma unroll
+  for (int t = 0; t < TileT::NR; ++t) {
+    const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + t, ny) : 0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      node(col0 + e, r, [&](int f) { return X.a[f][t][e]; }, [&](int f) { return V.a[f][t][e]; },
+           [&](int f, T y) { V.a[f][t][e] = y; });
+  }
+  const int cl = wrap_idx<P::kPeriodic>(col0 - 1, nx);
+  const int cr = wrap_idx<P::kPeriodic>(col0 + VEC, nx);
+#pragma unroll
+  for (int hh = 0; hh < TileT::RH; ++hh) {
+    const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + TileT::halo_row(hh), ny) : 0;
+    node(cl, r, [&](int f) { return X.lh[f][hh]; }, [&](int f) { return V.lh[f][hh]; },
+         [&](int f, T y) { V.lh[f][hh] = y; });
+    node(cr, r, [&](int f) { return X.rh[f][hh]; }, [&](int f) { return V.rh[f][hh]; },
+         [&](int f, T y) { V.rh[f][hh] = y; });
+  }
+}
+
+// dx = M^{-1} z in place (the update of right-preconditioned GMRES), one
+// node per thread, grid-stride; SoA planes.
+template <class P, class T>
+__global__ void __launch_bounds__(256) cslp_apply_kernel(const T* __restrict__ x, T* __restrict__ z, int nx, int ny,
+                                                          long long plane, const Coefs coefs) {
+  const auto k = P::template make<T>(coefs);
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += step) {
+    const int c = (int)(i % nx);
+    const int r = (int)(i / nx);
+    if (P::boundary(c, r, nx, ny)) continue;
+    T xv[P::NF], vv[P::NF];
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) {
+      xv[f] = x[f * plane + i];
+      vv[f] = z[f * plane + i];
+    }
+    P::template cslp_inv<T>(k, xv, vv);
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) z[f * plane + i] = vv[f];
+  }
+}
+
 // Persistent launch: the grid holds at most a bounded number of blocks and
 // each block walks a contiguous range of tiles (vertically adjacent row
 // bands, so the halo rows of one tile are still in cache for the next).  A
@@ -338,6 +405,9 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       Vt.exchange(col0, nx, lane);
       if constexpr (OP == OP_AD) {
         if (vscale != 1.0) Vt.scale_by(vs_t);
+      }
+      if constexpr (has_cslp<P>::value) {
+        if (a.precond) precondition_tile<P, T, VEC, RY>(k, X, Vt, col0, r0, nx, ny);
       }
     }
 

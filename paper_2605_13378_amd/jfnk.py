@@ -24,6 +24,7 @@ EPS_RULES = {"paper": 0, "normalized": 1}
 ENGINES = {"auto": 0, "multi": 1, "single": 2}
 KRYLOV = {"gmres": 0, "bicgstab": 1, "cg": 2}
 ORTH = {"cgs2": 0, "dcgs2": 1}
+PRECOND = {"none": 0, "cslp": 1}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "hip error", 4: "nonfinite",
           5: "breakdown", 6: "not_converged"}
 PROFILE_KERNELS = {"residual": 0, "jvp_ad": 1, "jvp_fd": 2, "cgs_a": 3, "cgs_b": 4, "cgs_c": 5, "vy": 6,
@@ -44,7 +45,7 @@ class Options(ctypes.Structure):
                 ("fd_eps", ctypes.c_double), ("breakdown_tol", ctypes.c_double),
                 ("mode", ctypes.c_int), ("eps_rule", ctypes.c_int),
                 ("history", ctypes.c_void_p), ("engine", ctypes.c_int), ("krylov", ctypes.c_int),
-                ("orth", ctypes.c_int)]
+                ("orth", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -117,6 +118,7 @@ _SIGNATURES = [
     ("jfnk_profile_reset", ctypes.c_int, [ctypes.c_void_p]),
     ("jfnk_set_stream", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("jfnk_set_orthogonalization", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    ("jfnk_set_preconditioner", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     ("jfnk_batch_create", ctypes.c_int, [ctypes.POINTER(BatchConfig), ctypes.POINTER(ctypes.c_void_p)]),
     ("jfnk_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("jfnk_batch_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
@@ -191,6 +193,8 @@ def default_options(precision: str = "f64", **kw) -> Options:
             val = KRYLOV[val]
         elif key == "orth":
             val = ORTH[val]
+        elif key == "precond":
+            val = PRECOND[val]
         elif key == "history":
             val = None if val is None else val.data_ptr()
         setattr(o, key, val)
@@ -277,6 +281,10 @@ class Solver:
     def set_orthogonalization(self, orth: str):
         """Gram-Schmidt form of later gmres() calls: 'cgs2' or 'dcgs2' (default in FP64/FP32)."""
         self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
+
+    def set_preconditioner(self, precond: str):
+        """Right preconditioner of later gmres() calls: 'none' (default) or 'cslp' (Maxwell-Kerr)."""
+        self._check(lib().jfnk_set_preconditioner(self._h, PRECOND[precond]))
 
     def gmres(self, x, rhs, m=None, tol=1e-8, max_restarts=100, mode="ad", eps=0.0, eps_rule="paper"):
         x = self._vec(x, self.wdtype, "x")

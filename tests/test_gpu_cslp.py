@@ -1,0 +1,161 @@
+"""GPU parity of the CSLP-preconditioned GMRES of the Maxwell-Kerr problem
+(Appendix A.4) against the oracle's right-preconditioned GMRES.
+
+Parity contract:
+  * GMRES with the preconditioner on a field with |E| > 0 (so M varies from
+    node to node) on a non-square grid (hx != hy), a fixed number of Arnoldi
+    steps (tolerance out of reach): dx = M^{-1} V y within 1e-9 (FP64 AD,
+    both Gram-Schmidt forms, one and several cycles), 1e-3 (FP64 FD, the
+    paper's step: rounding-bound on this operator, see the test), 2e-4 (FP32
+    AD, oracle in FP64 on the FP32-rounded inputs) of the oracle's; the GPU's true residual norm equals the oracle's;
+  * the same at the full 512^2 grid in FP32 (the JVP-row shape);
+  * Newton from E = 0 with the preconditioner, per iterate, as the
+    unpreconditioned Maxwell tests (1e-6: Krylov-tolerance band);
+  * the configurations the library rejects, and AUTO running the
+    multi-kernel engine for a problem the single-workgroup engine would take.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import dev, gpu_available, host, wdtype
+from oracle import EPS_MACH, Problem, cslp_solve, fd_step, gmres_solve, jvp_ad, jvp_fd, residual
+from test_gpu_solver import compare_newton, solver
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def linear_case(nx, ny, prec, omega=3.0, seed=5, amp=0.3):
+    spec = W.maxwell_spec(nx, omega=omega, ny=ny)
+    src = W.maxwell_source(nx, omega=omega, ny=ny)
+    p = Problem.from_spec(spec)
+    x = amp * W.random_vector(p.n, seed)
+    xw = x if prec == "f64" else x.astype(np.float32).astype(np.float64)
+    rhs = -residual(p, xw, None, src)
+    if prec == "f32":
+        rhs = rhs.astype(np.float32).astype(np.float64)
+    return spec, src, p, xw, rhs
+
+
+def oracle_gmres(p, xw, rhs, src, m, cycles, mode="ad", orth="cgs2"):
+    if mode == "ad":
+        mv = lambda v: jvp_ad(p, xw, v, None, src)[1]  # noqa: E731
+    else:
+        F0 = residual(p, xw, None, src)
+        eps = fd_step("paper", EPS_MACH["f64"], xw, None)
+        mv = lambda v: jvp_fd(p, xw, v, eps, None, src, Fx=F0)  # noqa: E731
+    z, info = gmres_solve(lambda v: mv(cslp_solve(p, xw, v)), rhs, m=m, tol=1e-30, max_restarts=cycles, orth=orth)
+    return cslp_solve(p, xw, z), info, mv
+
+
+def run_gpu(spec, src, prec, xw, rhs, m, cycles, mode="ad", orth="dcgs2"):
+    s = solver(spec, prec, None, src, m=m)
+    s.set_orthogonalization(orth)
+    s.set_preconditioner("cslp")
+    return s.gmres(dev(xw, wdtype(prec)), dev(rhs, wdtype(prec)), m=m, tol=1e-30, max_restarts=cycles, mode=mode)
+
+
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+@pytest.mark.parametrize("m,cycles", [(8, 1), (6, 3)])
+def test_cslp_gmres_f64_ad(orth, m, cycles):
+    spec, src, p, xw, rhs = linear_case(40, 36, "f64")
+    ref, rinfo, mv = oracle_gmres(p, xw, rhs, src, m, cycles, orth=orth)
+    dx, info = run_gpu(spec, src, "f64", xw, rhs, m, cycles, orth=orth)
+    assert info["krylov_iters"] == rinfo.iters == m * cycles and not info["converged"]
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 1e-9 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+    # the update is in the original space: its residual is the one GMRES reports
+    true_res = np.linalg.norm(rhs - mv(d))
+    assert abs(true_res - np.linalg.norm(rhs - mv(ref))) <= 1e-8 * np.linalg.norm(rhs)
+    # the preconditioner did something: unpreconditioned GMRES gives another iterate
+    plain, _ = gmres_solve(mv, rhs, m=m, tol=1e-30, max_restarts=cycles)
+    assert np.linalg.norm(plain - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_cslp_gmres_f64_fd_paper_step():
+    # FD in FP64 on this operator is rounding-bound: F(x + eps v) - F(x) cancels
+    # about eight digits, and a one-ulp change of F(x) alone moves the oracle's
+    # own 16-step iterate by 1.1e-4 (measured), about as far as AD is from FD.
+    # The bound is ten times that; a JVP that skipped the preconditioner would
+    # be off by O(1), as the unpreconditioned iterate shows.
+    spec, src, p, xw, rhs = linear_case(40, 36, "f64")
+    ref, rinfo, mv = oracle_gmres(p, xw, rhs, src, 8, 2, mode="fd")
+    dx, info = run_gpu(spec, src, "f64", xw, rhs, 8, 2, mode="fd")
+    assert info["krylov_iters"] == rinfo.iters == 16
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 1e-3 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+    plain, _ = gmres_solve(mv, rhs, m=8, tol=1e-30, max_restarts=2)
+    assert np.linalg.norm(plain - ref) > 1e-2 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("nx,ny", [(40, 36), (512, 512)])
+def test_cslp_gmres_f32_ad(nx, ny):
+    spec, src, p, xw, rhs = linear_case(nx, ny, "f32")
+    ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, 8, 1, orth="dcgs2")
+    dx, info = run_gpu(spec, src, "f32", xw, rhs, 8, 1)
+    assert info["krylov_iters"] == rinfo.iters == 8
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 2e-4 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+
+
+def test_cslp_gmres_f16_storage():
+    spec, src, p, xw, rhs = linear_case(40, 36, "f32")
+    ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, 8, 1)
+    dx, info = run_gpu(spec, src, "f16s", xw, rhs, 8, 1, orth="cgs2")
+    assert info["krylov_iters"] == 8
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 1e-2 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_newton_maxwell_cslp_from_born(orth):
+    spec = W.maxwell_spec(16, omega=2.5)
+    src = W.maxwell_source(16, omega=2.5)
+    info, ref = compare_newton(spec, np.zeros(4 * 16 * 16), src, "f64", "ad", 1e-6, orth=orth, precond="cslp",
+                               krylov_slack=0.1, max_newton=20)
+    assert info["converged"]
+
+
+def test_newton_maxwell_cslp_auto_engine_runs_multi_kernel():
+    spec = W.maxwell_spec(12, omega=2.5, ny=10)
+    src = W.maxwell_source(12, omega=2.5, ny=10)
+    # (tolerances above the rounding-sensitive regime: at tol_krylov 1e-10 the
+    # oracle's own two Gram-Schmidt forms differ by 12% in the second solve)
+    info, ref = compare_newton(spec, np.zeros(4 * 12 * 10), src, "f64", "ad", 1e-6, engine="auto", orth="dcgs2",
+                               precond="cslp", krylov_slack=0.1, tol_newton=1e-6, tol_krylov=1e-8,
+                               max_restarts=20, max_newton=8)
+    assert info["converged"]
+
+
+def test_cslp_rejected_configurations():
+    from paper_2605_13378_amd import JfnkError
+
+    spec, xp, src = W.config("grayscott", n=32)
+    gs = solver(spec, "f64", xp, src, m=8)
+    with pytest.raises(JfnkError, match="Maxwell"):
+        gs.set_preconditioner("cslp")
+    with pytest.raises(JfnkError, match="Maxwell"):
+        gs.newton_solve(dev(xp, wdtype("f64")), precond="cslp", m=8)
+    mspec = W.maxwell_spec(16)
+    msrc = W.maxwell_source(16)
+    s = solver(mspec, "f64", None, msrc, m=8)
+    x0 = dev(np.zeros(4 * 16 * 16), wdtype("f64"))
+    with pytest.raises(JfnkError, match="GMRES on the multi-kernel engine"):
+        s.newton_solve(x0, precond="cslp", krylov="bicgstab", m=8)
+    with pytest.raises(JfnkError, match="GMRES on the multi-kernel engine"):
+        s.newton_solve(x0, precond="cslp", engine="single", m=8)
+    with pytest.raises(JfnkError, match="paper's FD step rule"):
+        s.newton_solve(x0, precond="cslp", mode="fd", eps_rule="normalized", m=8)
+    s.set_preconditioner("cslp")
+    with pytest.raises(JfnkError, match="paper's FD step rule"):
+        s.gmres(x0, dev(np.ones(4 * 16 * 16), wdtype("f64")), mode="fd", eps_rule="normalized")
+    # back to none: the normalized rule is accepted again
+    s.set_preconditioner("none")
+    s.gmres(x0, dev(np.ones(4 * 16 * 16), wdtype("f64")), mode="fd", eps_rule="normalized", max_restarts=1)

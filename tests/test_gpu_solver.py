@@ -37,9 +37,10 @@ def solver(spec, prec, xp, src, m=30):
 
 
 def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", krylov_slack=None, engine="multi",
-                   krylov="gmres", orth="cgs2", **kw):
+                   krylov="gmres", orth="cgs2", precond="none", **kw):
     p = Problem.from_spec(spec)
-    o = NewtonOptions.for_precision(prec, mode=mode, eps_rule=eps_rule, krylov=krylov, orth=orth, **kw)
+    o = NewtonOptions.for_precision(prec, mode=mode, eps_rule=eps_rule, krylov=krylov, orth=orth, precond=precond,
+                                    **kw)
     x_ref, info_ref = newton_solve(p, xp, o, source=src, x0=x0, record=True)
     s = solver(spec, prec, xp, src, m=o.m)
     start = xp if x0 is None else x0
@@ -48,13 +49,14 @@ def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", kr
     x_gpu, info = s.newton_solve(dev(start, wdtype("f64")), history=True, mode=mode, eps_rule=eps_rule,
                                  m=o.m, tol_newton=o.tol_newton, tol_krylov=o.tol_krylov,
                                  max_newton=o.max_newton, max_restarts=o.max_restarts,
-                                 breakdown_tol=o.breakdown_tol, engine=engine, krylov=krylov, orth=orth)
+                                 breakdown_tol=o.breakdown_tol, engine=engine, krylov=krylov, orth=orth,
+                                 precond=precond)
     prof = s.profile_read()
     s.profile(False)
     # the engine asked for is the one that ran
     if engine == "single":
         assert prof["fused_solve"]["launches"] == 1 and prof["residual"]["launches"] == 0, prof
-    elif engine == "multi":
+    elif engine == "multi" or precond != "none":  # AUTO takes the multi-kernel engine with a preconditioner
         assert prof["fused_solve"]["launches"] == 0 and prof["residual"]["launches"] >= 1, prof
     assert info["newton_iters"] == info_ref.newton_iters, (info, info_ref)
     assert info["converged"] == info_ref.converged
