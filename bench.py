@@ -452,7 +452,7 @@ def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50, b
     import workloads as W
     from paper_2605_13378_amd import Solver
 
-    out = {"jvp_512": {}, "sweep": []}
+    out = {"jvp_512": {}, "arnoldi_jvp_512": {}, "sweep": [], "sweep_cslp": []}
     spec, x0, src = W.config("maxwell")
     nn = W.n_unknowns(spec)
     for pr in ("f32", "f64"):
@@ -461,25 +461,45 @@ def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50, b
         for mode in ("ad", "fd"):
             out["jvp_512"][f"{pr}-{mode}"] = jvp_bandwidth(s, torch, nn, pr, mode)
         log(f"[bench] maxwell jvp 512^2 {pr}: {out['jvp_512']}")
+        # the Arnoldi JVP (first projection fused) of one GMRES(30) cycle at a field with |E| > 0,
+        # without and with the CSLP preconditioner applied to its tangent
+        wd = torch.float64 if pr == "f64" else torch.float32
+        xf = torch.tensor(0.3 * W.random_vector(nn, 5), dtype=wd, device="cuda")
+        rhs = -s.residual(xf)
+        for pc in ("none", "cslp"):
+            s.set_preconditioner(pc)
+            s.gmres(xf, rhs, m=30, tol=1e-30, max_restarts=1)  # warm-up
+            s.profile_reset()
+            s.profile(True)
+            _, info = s.gmres(xf, rhs, m=30, tol=1e-30, max_restarts=1)
+            st = s.profile_read()
+            s.profile(False)
+            j = st["jvp_ad"]
+            out["arnoldi_jvp_512"][f"{pr}-{pc}"] = dict(
+                launches=j["launches"], avg_us=round(j["ms"] * 1e3 / max(1, j["launches"]), 3),
+                gbs=round(j["bytes"] / max(j["ms"], 1e-9) / 1e6, 1), krylov_iters=info["krylov_iters"])
+        s.set_preconditioner("none")
+        log(f"[bench] maxwell arnoldi jvp 512^2 {pr}: {out['arnoldi_jvp_512']}")
         s.close()
-    x = torch.zeros(4 * n * n, dtype=torch.float64, device="cuda")
-    t_start = time.perf_counter()
-    for om in omegas:
-        if time.perf_counter() - t_start > budget_s:
-            break
-        s = Solver(W.maxwell_spec(n, omega=om), "f64", m=30)
-        s.set_previous(None, torch.tensor(W.maxwell_source(n, omega=om), dtype=torch.float64, device="cuda"))
-        t0 = time.perf_counter()
-        xn, info = s.newton_solve(x, max_newton=max_newton)
-        el = time.perf_counter() - t0
-        ok = info["converged"]
-        row = dict(omega=om, converged=ok, newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
-                   final_rel_res=info["rel_res"][-1], seconds=round(el, 3),
-                   start="previous" if bool(x.abs().sum() > 0) else "born")
-        out["sweep"].append(row)
-        log(f"[bench] maxwell sweep {n}^2: {row}")
-        x = xn if ok else torch.zeros_like(x)
-        s.close()
+    for pc, key in (("none", "sweep"), ("cslp", "sweep_cslp")):
+        x = torch.zeros(4 * n * n, dtype=torch.float64, device="cuda")
+        t_start = time.perf_counter()
+        for om in omegas:
+            if time.perf_counter() - t_start > budget_s / 2:
+                break
+            s = Solver(W.maxwell_spec(n, omega=om), "f64", m=30)
+            s.set_previous(None, torch.tensor(W.maxwell_source(n, omega=om), dtype=torch.float64, device="cuda"))
+            t0 = time.perf_counter()
+            xn, info = s.newton_solve(x, max_newton=max_newton, precond=pc)
+            el = time.perf_counter() - t0
+            ok = info["converged"]
+            row = dict(omega=om, converged=ok, newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                       final_rel_res=info["rel_res"][-1], seconds=round(el, 3),
+                       start="previous" if bool(x.abs().sum() > 0) else "born")
+            out[key].append(row)
+            log(f"[bench] maxwell sweep {n}^2 precond {pc}: {row}")
+            x = xn if ok else torch.zeros_like(x)
+            s.close()
     return out
 
 

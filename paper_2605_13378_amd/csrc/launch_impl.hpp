@@ -81,6 +81,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
     case kSuOlson:
       return stencil_for_problem<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kMaxwell:
+      if (a.precond && op != OP_RES)
+        return stencil_for_problem<MaxwellTECslpOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
       return stencil_for_problem<MaxwellTEOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;

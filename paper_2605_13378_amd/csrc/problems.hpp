@@ -289,7 +289,6 @@ struct MaxwellTEOp {
   // Ey pair by M_yy = 2/hx^2 - omega^2 eps_p, with the damped permittivity
   // eps_p = (1 - loss i)(1 + chi |E|)(1 - 0.5 i).  (Boundary nodes: identity,
   // left to the caller.)
-  static constexpr bool kCslp = true;
   template <class T>
   __device__ __forceinline__ static void cslp_inv(const K<T>& k, const T (&x)[4], T (&v)[4]) {
     const T m = T(1) + k.chi * sqrt(((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]) + x[3] * x[3]);
@@ -309,14 +308,21 @@ struct MaxwellTEOp {
   }
 };
 
-// Operators with a diagonal right preconditioner (P::cslp_inv) set kCslp.
+// The Maxwell-Kerr operator with the CSLP preconditioner applied to every
+// JVP tangent (right preconditioning): a type of its own, so that the
+// unpreconditioned kernels are compiled without the extra code.
+struct MaxwellTECslpOp : MaxwellTEOp {
+  static constexpr bool kPrecondTangent = true;
+};
+
+// Operators whose JVP tangent is preconditioned (P::kPrecondTangent).
 template <class P, class = void>
-struct has_cslp {
+struct precond_tangent {
   static constexpr bool value = false;
 };
 template <class P>
-struct has_cslp<P, decltype((void)P::kCslp)> {
-  static constexpr bool value = P::kCslp;
+struct precond_tangent<P, decltype((void)P::kPrecondTangent)> {
+  static constexpr bool value = P::kPrecondTangent;
 };
 
 }  // namespace jfnk

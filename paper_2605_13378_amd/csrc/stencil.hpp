@@ -64,8 +64,9 @@ struct StencilArgs {
   const int* gate;
   Partials gate_parts;
   const double* gate_tol;
-  // Right preconditioning (operators with P::cslp_inv only): the JVP is
-  // applied to M^{-1} v, M frozen at x.
+  // Right preconditioning (problems with a diagonal preconditioner only):
+  // the JVP is applied to M^{-1} v, M frozen at x; the launcher picks the
+  // operator type that applies it.
   int precond;
 };
 
@@ -406,9 +407,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       if constexpr (OP == OP_AD) {
         if (vscale != 1.0) Vt.scale_by(vs_t);
       }
-      if constexpr (has_cslp<P>::value) {
-        if (a.precond) precondition_tile<P, T, VEC, RY>(k, X, Vt, col0, r0, nx, ny);
-      }
+      if constexpr (precond_tangent<P>::value) precondition_tile<P, T, VEC, RY>(k, X, Vt, col0, r0, nx, ny);
     }
 
 #pragma unroll
