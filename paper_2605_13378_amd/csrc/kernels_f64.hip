@@ -16,6 +16,11 @@ hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16,
   return hipGetLastError();
 }
 
+hipError_t launch_publish_ctl(const Ctl* c, int* dst, int words, int* seq_dst, int seq, hipStream_t s) {
+  JFNK_LAUNCH(publish_ctl_kernel<0>, dim3(1), dim3(64), s, c, dst, words, seq_dst, seq);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish_sums(Partials in, int nr, double* out0, double* out1, hipStream_t s) {
   JFNK_LAUNCH(finish_sums_kernel<0>, dim3(1), dim3(kStreamThreads), s, in, nr, out0, out1);
   return hipGetLastError();

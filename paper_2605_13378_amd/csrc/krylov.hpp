@@ -768,4 +768,23 @@ __global__ void ctl_begin_kernel(Ctl* c, double tol, double brk_tol, int m) {
   }
 }
 
+// Publish the control block's head (the scalars the host driver reads between
+// kernels: counts, stop states, norms; `words` 32-bit words) to mapped host
+// memory, then set the sequence word there to `seq`.  The host waits by
+// spinning on that word instead of a stream synchronization plus a copy; the
+// kernel runs after everything before it on the stream, so the head is
+// final.  One wavefront, vector stores only.
+template <int kUnused = 0>
+__global__ void __launch_bounds__(64) publish_ctl_kernel(const Ctl* __restrict__ c, int* __restrict__ dst, int words,
+                                                         int* __restrict__ seq_dst, int seq) {
+  const int* src = reinterpret_cast<const int*>(c);
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile int*>(seq_dst) = seq;
+  }
+}
+
 }  // namespace jfnk

@@ -192,5 +192,8 @@ hipError_t launch_cg(int kind, const CgArgs<T>& a, double tol, int grid, hipStre
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);
 hipError_t launch_finish_sums(Partials in, int nr, double* out0, double* out1, hipStream_t s);
+// Copies the first `words` 32-bit words of the control block to mapped host
+// memory `dst`, then writes `seq` to the mapped word `seq_dst`.
+hipError_t launch_publish_ctl(const Ctl* c, int* dst, int words, int* seq_dst, int seq, hipStream_t s);
 
 }  // namespace jfnk

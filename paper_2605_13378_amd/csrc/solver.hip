@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -83,6 +84,9 @@ struct jfnk_solver {
   Ctl* hctl = nullptr;     // pinned host mirror of the control block header
   int* hflags = nullptr;   // pinned, mapped: per-step stop flags written by the device
   int* dflags = nullptr;   // device view of hflags
+  int* hpub = nullptr;     // pinned, mapped: the control block's head published by the device, then its sequence word
+  int* dpub = nullptr;     // device view of hpub
+  int pub_seq = 0;         // last sequence number asked for
   size_t lds_max = 0;           // LDS bytes one workgroup may use
   FusedInfo* dinfo = nullptr;   // single-workgroup solve record (device)
   FusedInfo* hinfo = nullptr;   // pinned host copy
@@ -176,7 +180,43 @@ void prof_harvest(jfnk_solver* s, int steps_done) {
   s->recs.clear();
 }
 
+// Bring the control block's head (the fields up to gp) to s->hctl once all
+// queued work has run.  Normally a one-wavefront kernel writes it to mapped
+// host memory and then a sequence word, and the host spins on that word (a
+// stream synchronization's wake-up and a copy cost more); with kernel timing
+// on, or if the stream drains without the word appearing, a copy and a
+// stream synchronization instead.
+constexpr int kPubWords = (int)(offsetof(Ctl, gp) / sizeof(int));
+static_assert(offsetof(Ctl, gp) % sizeof(int) == 0, "control block head must be whole words");
+
 jfnk_status sync_read_ctl(jfnk_solver* s) {
+  if (!s->prof && s->hpub != nullptr) {
+    const int seq = ++s->pub_seq;
+    JFNK_HIP(s, launch_publish_ctl(s->ctl, s->dpub, kPubWords, s->dpub + kPubWords, seq, s->stream));
+    volatile int* word = s->hpub + kPubWords;
+    bool seen = false;
+    for (unsigned it = 1;; ++it) {
+      if (*word == seq) {
+        seen = true;
+        break;
+      }
+      if ((it & 1023u) == 0) {
+        const hipError_t q = hipStreamQuery(s->stream);
+        if (q == hipSuccess) {
+          seen = *word == seq;
+          break;
+        }
+        if (q != hipErrorNotReady) JFNK_HIP(s, q);
+      }
+      __builtin_ia32_pause();
+    }
+    if (seen) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      std::memcpy(static_cast<void*>(s->hctl), const_cast<const int*>(static_cast<volatile int*>(s->hpub)),
+                  offsetof(Ctl, gp));
+      return JFNK_OK;
+    }
+  }
   JFNK_HIP(s, hipMemcpyAsync(s->hctl, s->ctl, offsetof(Ctl, gp), hipMemcpyDeviceToHost, s->stream));
   JFNK_HIP(s, hipStreamSynchronize(s->stream));
   return JFNK_OK;
@@ -1000,6 +1040,7 @@ void release(jfnk_solver* s) {
     if (p) (void)hipFree(p);
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->hflags) (void)hipHostFree(s->hflags);
+  if (s->hpub) (void)hipHostFree(s->hpub);
   if (s->dinfo) (void)hipFree(s->dinfo);
   if (s->hinfo) (void)hipHostFree(s->hinfo);
   if (s->dbi) (void)hipFree(s->dbi);
@@ -1316,6 +1357,22 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
         st = JFNK_ERR_HIP;
       }
       s->dflags = static_cast<int*>(d);
+    }
+  }
+  if (st == JFNK_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(int) * (kPubWords + 1), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      s->err = "hipHostMalloc (published control block) failed";
+      st = JFNK_ERR_OOM;
+    } else {
+      s->hpub = static_cast<int*>(h);
+      std::memset(h, 0, sizeof(int) * (kPubWords + 1));
+      void* d = nullptr;
+      if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        s->err = "hipHostGetDevicePointer failed";
+        st = JFNK_ERR_HIP;
+      }
+      s->dpub = static_cast<int*>(d);
     }
   }
   if (st == JFNK_OK && hipStreamSynchronize(s->stream) != hipSuccess) {
