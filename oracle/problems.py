@@ -49,7 +49,9 @@ The Su-Olson non-equilibrium radiation diffusion system (Appendix A.2),
 U_t = (1/3) Lap U - (U - V) + Q, V_t = xi (U - V): N = (-(1/3) Lap U + (U - V),
 -xi (U - V)), source (Q, 0), Dirichlet boundary nodes (F = x there).  The
 residual is affine in the state, so the FD difference quotient equals the
-Jacobian product up to rounding.
+Jacobian product up to rounding.  Its two configurations: the dynamic one with
+Dirichlet nodes all round, and the classic 1D profile on a 2D grid whose rows
+wrap (``periodic_y``): only the first and last columns are boundary nodes.
 
 Layouts are those of the ``workloads`` module: 1D ``u[i]``; two-field 2D
 problems as two row-major planes of shape (ny, nx); Kerr as interleaved
@@ -86,6 +88,7 @@ class Problem:
     eps_im: float = 0.0  # Kerr linear permittivity (imaginary part)
     chi3: float = 0.0  # Kerr coefficient
     xi: float = 0.0  # Su-Olson material coupling
+    periodic_y: bool = False  # Su-Olson's 1D-profile configuration: periodic rows, Dirichlet columns
 
     @classmethod
     def from_spec(cls, spec: dict) -> "Problem":
@@ -214,9 +217,15 @@ def N_apply(p: Problem, x):
 
 
 def interior_mask(p: Problem) -> np.ndarray:
-    """1 on interior nodes, 0 on the PEC boundary nodes, shape (ny, nx)."""
+    """1 on interior nodes, 0 on the boundary nodes (PEC or Dirichlet), shape (ny, nx).
+
+    With ``periodic_y`` (Su-Olson's 1D-profile configuration) the rows wrap, so
+    only the first and last columns are boundary nodes."""
     m = np.zeros((p.ny, p.nx))
-    m[1:-1, 1:-1] = 1.0
+    if p.periodic_y:
+        m[:, 1:-1] = 1.0
+    else:
+        m[1:-1, 1:-1] = 1.0
     return m
 
 

@@ -307,3 +307,14 @@ def test_cslp_update_left_in_the_preconditioned_space(monkeypatch):
     exec(compile(src.replace("dx = minv(z)", "dx = z", 1), "newton_mutant", "exec"), ns)
     monkeypatch.setattr(tcs, "newton_solve", ns["newton_solve"])
     _expect_failure(tcs.test_newton_with_cslp_reaches_the_same_field)
+
+
+def test_suolson_periodic_rows_held_as_boundary(monkeypatch):
+    def all_round(p):
+        m = np.zeros((p.ny, p.nx))
+        m[1:-1, 1:-1] = 1.0
+        return m
+
+    monkeypatch.setattr(oprob, "interior_mask", all_round)
+    _expect_failure(tso.test_suolson_periodic_rows_fourier_modes_closed_form, 17, 12, 0.5)
+    _expect_failure(tso.test_suolson_periodic_rows_reduce_to_the_1d_profile)

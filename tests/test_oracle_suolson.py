@@ -112,3 +112,92 @@ def test_suolson_newton_one_step():
     x, info = newton_solve(p, x0, o, source=src)
     assert info.converged and info.newton_iters == 1
     assert info.rel_res[1] <= 1e-10
+
+
+# The classic 1D-profile configuration: rows periodic (hy = L / ny), the first
+# and last columns Dirichlet nodes.
+
+
+def grid_py(nx, ny, xi=0.1, theta=0.5):
+    spec = W.suolson_spec(nx, xi=xi, theta=theta, ny=ny, periodic_y=True)
+    return spec, Problem.from_spec(spec)
+
+
+def mode_py(p, a, b, amp, phase=0.3):
+    # Dirichlet sine in x times a periodic Fourier mode in y
+    x = np.linspace(0.0, 1.0, p.nx)[None, :]
+    jy = np.arange(p.ny)[:, None]
+    return (amp * np.sin(a * np.pi * x) * np.cos(2.0 * np.pi * b * jy / p.ny + phase)).ravel()
+
+
+def eig_py(p, a, b):
+    tx = a * np.pi / (p.nx - 1)
+    ty = 2.0 * np.pi * b / p.ny
+    return -(4.0 / p.hx ** 2) * np.sin(tx / 2) ** 2 - (4.0 / p.hy ** 2) * np.sin(ty / 2) ** 2
+
+
+def inner_py(p):
+    m = np.zeros((p.ny, p.nx))
+    m[:, 1:-1] = 1.0
+    return np.tile(m.ravel(), 2)
+
+
+@pytest.mark.parametrize("nx,ny,theta", [(17, 12, 0.5), (24, 7, 1.0), (9, 16, 0.5)])
+def test_suolson_periodic_rows_fourier_modes_closed_form(nx, ny, theta):
+    """Periodic Fourier modes in y are eigenvectors of the wrapped second difference (a
+    wrong wrap, or a y boundary held, breaks the first and last rows)."""
+    spec, p = grid_py(nx, ny, xi=0.3, theta=theta)
+    lu = eig_py(p, 2, 1)
+    ln = eig_py(p, 1, 2)
+    U, V = mode_py(p, 2, 1, 0.8), mode_py(p, 2, 1, -0.4)
+    Un, Vn = mode_py(p, 1, 2, 1.1, 0.9), mode_py(p, 1, 2, 0.6, 0.9)
+    x = np.concatenate([U, V])
+    xn = np.concatenate([Un, Vn])
+    N = np.concatenate([-(lu / 3.0) * U + (U - V), -p.xi * (U - V)])
+    Nn = np.concatenate([-(ln / 3.0) * Un + (Un - Vn), -p.xi * (Un - Vn)])
+    Q = mode_py(p, 1, 0, 2.0)
+    src = np.concatenate([Q, np.zeros_like(Q)])
+    expect = inner_py(p) * (x - xn + p.dt * (theta * N + (1 - theta) * Nn) - p.dt * src)
+    got = residual(p, x, xn, src)
+    assert np.max(np.abs(got - expect)) <= 1e-13 * max(1.0, np.abs(expect).max())
+
+
+def test_suolson_periodic_rows_boundary_columns_only():
+    spec, p = grid_py(11, 6)
+    rng = np.random.default_rng(4)
+    x, xn, s = rng.standard_normal((3, p.n))
+    F = residual(p, x, xn, s)
+    m = inner_py(p)
+    assert np.array_equal(F[m == 0], x[m == 0])
+    assert not np.allclose(F[m == 1], x[m == 1])
+    # the first and last rows are interior rows here
+    assert m.reshape(2, p.ny, p.nx)[:, 0, 1:-1].all() and m.reshape(2, p.ny, p.nx)[:, -1, 1:-1].all()
+
+
+def test_suolson_periodic_rows_reduce_to_the_1d_profile():
+    """With the box source and a cold start every row of the solution is the same 1D profile:
+    one Newton step of the 2D problem equals the dense solve of the 1D (x only) system."""
+    spec, p = grid_py(41, 6, xi=0.1)
+    x0, src = W.suolson_box_initial(41, 6)
+    o = NewtonOptions(m=30, tol_newton=1e-12, tol_krylov=1e-13, max_newton=3)
+    x, info = newton_solve(p, x0, o, source=src)
+    assert info.converged
+    U = x[: p.n // 2].reshape(p.ny, p.nx)
+    V = x[p.n // 2:].reshape(p.ny, p.nx)
+    assert np.max(np.abs(U - U[0])) <= 1e-13 and np.max(np.abs(V - V[0])) <= 1e-13
+    # 1D Crank-Nicolson system along x, Dirichlet ends, from U = V = 0
+    nx, c = p.nx, p.theta * p.dt
+    q = src[: nx]
+    L1 = np.zeros((nx, nx))
+    for i in range(1, nx - 1):
+        L1[i, i - 1] = L1[i, i + 1] = 1.0 / p.hx ** 2
+        L1[i, i] = -2.0 / p.hx ** 2
+    I = np.eye(nx)
+    E = np.eye(nx)
+    E[0, 0] = E[-1, -1] = 0.0  # interior rows
+    A = np.block([[I + c * E @ (-(1.0 / 3.0) * L1 + I), -c * E], [-c * p.xi * E, I + c * p.xi * E]])
+    rhs = np.concatenate([p.dt * q, np.zeros(nx)])
+    ref = np.linalg.solve(A, rhs)
+    assert np.max(np.abs(U[0] - ref[:nx])) <= 1e-10 * np.abs(ref).max()
+    assert np.max(np.abs(V[0] - ref[nx:])) <= 1e-10 * np.abs(ref).max()
+    assert U[0, nx // 2] > 0 and U[0, 0] == 0.0

@@ -74,14 +74,32 @@ def rd2d_spec(n: int = 512, D: float = 0.01, C: float = 1.0, theta: float = 0.5,
 
 
 def suolson_spec(n: int = 512, xi: float = 0.1, C: float = 1.0, theta: float = 0.5, L: float = 10.0,
-                 ny: int | None = None) -> dict:
+                 ny: int | None = None, periodic_y: bool = False) -> dict:
     """Su-Olson radiation diffusion on the node grid of [-L/2, L/2]^2 (Appendix A.2): Dirichlet
-    boundary nodes, Crank-Nicolson, dt = min(C h^2 / D, C / xi) with D = 1/3."""
+    boundary nodes, Crank-Nicolson, dt = min(C h^2 / D, C / xi) with D = 1/3.  With
+    ``periodic_y`` (the classic 1D-profile configuration) the ny rows are periodic nodes of
+    [-L/2, L/2) (hy = L / ny) and only the first and last columns are Dirichlet nodes."""
     ny = n if ny is None else ny
     hx = L / (n - 1)
-    hy = L / (ny - 1)
+    hy = L / ny if periodic_y else L / (ny - 1)
     dt = min(C * min(hx, hy) ** 2 / (1.0 / 3.0), C / xi)
-    return dict(kind="suolson", nx=n, ny=ny, hx=hx, hy=hy, dt=dt, theta=theta, xi=xi)
+    spec = dict(kind="suolson", nx=n, ny=ny, hx=hx, hy=hy, dt=dt, theta=theta, xi=xi)
+    if periodic_y:
+        spec["periodic_y"] = True
+    return spec
+
+
+def suolson_box_initial(n: int = 512, ny: int | None = None, L: float = 10.0, Q0: float = 1.0,
+                        x0: float = 0.5) -> tuple[np.ndarray, np.ndarray]:
+    """(x^0, source) of the classic 1D-profile Su-Olson configuration: cold start (U = V = 0)
+    and the central stationary box source Q0 on |x| <= x0 (every row; the classic problem's
+    half-width x0 = 1/2), zero on the boundary columns."""
+    ny = n if ny is None else ny
+    x = np.linspace(-L / 2, L / 2, n)
+    q = np.where(np.abs(x) <= x0 + 1e-12, Q0, 0.0)
+    q[0] = q[-1] = 0.0
+    Q = np.tile(q, (ny, 1))
+    return np.zeros(2 * n * ny), np.concatenate([Q.ravel(), np.zeros(n * ny)])
 
 
 def suolson_initial(n: int = 512, seed: int = 0, ny: int | None = None, L: float = 10.0, Q0: float = 1.0,
@@ -324,7 +342,9 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
 
     Names: ``burgers1d`` (N=256 by default), ``grayscott`` (1024^2),
     ``burgers2d`` (2048^2), ``kerr`` (1024^2, chi3 = 0.1), ``rd2d`` (512^2,
-    the paper's GPU reaction-diffusion grid, multi-Gaussian start).
+    the paper's GPU reaction-diffusion grid, multi-Gaussian start), ``suolson``
+    (512^2, rings and orbiting source), ``suolson1d`` (512^2, periodic rows,
+    cold start with the central box source), ``maxwell`` (512^2, dipole).
     """
     if name == "burgers1d":
         nx = 256 if n is None else n
@@ -353,6 +373,10 @@ def config(name: str, seed: int = 0, n: int | None = None) -> tuple[dict, np.nda
         nn = 512 if n is None else n
         x0, src = suolson_initial(nn, seed)
         return suolson_spec(nn), x0, src
+    if name == "suolson1d":
+        nn = 512 if n is None else n
+        x0, src = suolson_box_initial(nn)
+        return suolson_spec(nn, periodic_y=True), x0, src
     raise KeyError(name)
 
 
