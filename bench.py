@@ -413,12 +413,14 @@ def rd_rows(torch, steps, budget_s=3.0):
     return rows
 
 
-def suolson_rows(torch, steps, budget_s=3.0):
+def suolson_rows(torch, steps, budget_s=3.0, config="suolson"):
     """The paper's Su-Olson radiation diffusion at 512^2 (affine: FD equals AD up to rounding):
-    one Crank-Nicolson step with GMRES(30) and BiCGSTAB, AD and FD (paper step), FP32 and FP64."""
+    one Crank-Nicolson step with GMRES(30) and BiCGSTAB, AD and FD (paper step), FP32 and FP64.
+    config: 'suolson' (rings and orbiting source, Dirichlet all round) or 'suolson1d' (the
+    classic 1D profile: periodic rows, cold start, central box source)."""
     import workloads as W
 
-    spec, xp, src = W.config("suolson")
+    spec, xp, src = W.config(config)
     x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
     rows = {}
     for pr in ("f32", "f64"):
@@ -438,7 +440,7 @@ def suolson_rows(torch, steps, budget_s=3.0):
                 rows[f"{pr}-{kr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
                                                  newton_iters=inf["newton_iters"], lin_iters=inf["lin_iters"],
                                                  converged=inf["converged"], final_rel_res=inf["rel_res"][-1])
-                log(f"[bench] suolson 512^2 {pr}-{kr}-{mode}: {rows[f'{pr}-{kr}-{mode}']}")
+                log(f"[bench] {config} 512^2 {pr}-{kr}-{mode}: {rows[f'{pr}-{kr}-{mode}']}")
         sv.close()
     return rows
 
@@ -763,10 +765,11 @@ def main():
         log("[bench] Maxwell-Kerr TE rows")
         mx = maxwell_rows(torch)
 
-    so = None
+    so = so1 = None
     if not args.no_rd:
         log("[bench] Su-Olson 512^2 rows")
         so = suolson_rows(torch, args.steps)
+        so1 = suolson_rows(torch, args.steps, config="suolson1d")
 
     pb = None
     if not args.no_paper_burgers:
@@ -830,6 +833,7 @@ def main():
         "reaction_diffusion_512": rd,
         "burgers2d_256_tgv_dsl": pb,
         "suolson_512": so,
+        "suolson1d_512": so1,
         "maxwell_te": mx,
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,

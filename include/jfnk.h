@@ -73,7 +73,7 @@ typedef enum {
   JFNK_GRAYSCOTT2D = 2, /* two-species reaction-diffusion, periodic; n = 2 nx ny */
   JFNK_KERR2D = 3,      /* -Lap E - k0^2 (eps_L + chi3 |E|^2) E = f, PEC nodes; n = 2 nx ny */
   JFNK_RD2D = 4,        /* u_t = D Lap u - u^3 (Appendix A.3), Dirichlet nodes; n = nx ny */
-  JFNK_SUOLSON2D = 5,   /* Su-Olson radiation diffusion (Appendix A.2), Dirichlet nodes; n = 2 nx ny */
+  JFNK_SUOLSON2D = 5,   /* Su-Olson radiation diffusion (Appendix A.2); n = 2 nx ny */
   JFNK_MAXWELL2D = 6    /* 2D TE Maxwell-Kerr (Appendix A.4), PEC nodes; n = 4 nx ny */
 } jfnk_problem_id;
 
@@ -87,9 +87,13 @@ typedef enum {
  * differences.  Kerr: F = -Lap E - k0^2 (eps_L + chi3 |E|^2) E - f on
  * interior nodes and F = E on the boundary nodes.
  *   p[]: Burgers {nu}; Gray-Scott {D, Dv, F, k}; Kerr {k0, eps_re, eps_im, chi3};
- *   reaction-diffusion {D}; Su-Olson {xi}.
+ *   reaction-diffusion {D}; Su-Olson {xi, periodic_y}.
  * Su-Olson: N = (-(1/3) Lap U + (U - V), -xi (U - V)) on (U, V) planes at the
  * interior nodes, F = x at the boundary nodes; the source (Q, 0) enters as s.
+ * Its two configurations (Appendix A.2): p[1] = 0, Dirichlet nodes all round
+ * (the dynamic 2D case); p[1] = 1, the classic 1D profile on a 2D grid: the
+ * rows are periodic (row 0 and row ny-1 are neighbours) and only the first
+ * and last columns are boundary nodes.  Other p[1] values: JFNK_ERR_ARG.
  * Maxwell TE (planes Re Ex, Im Ex, Re Ey, Im Ey; mu0 = eps0 = 1):
  *   F = curl curl E - omega^2 (1 - i loss)(1 + chi |E|) E - f inside, F = E on
  *   the boundary nodes, with the mixed derivative from the diagonal

@@ -137,8 +137,8 @@ __device__ __forceinline__ void gather(const T* a, int c, int nx, int ny, int ce
   const int cl = j * nx + il, cr = j * nx + ir;
   int cd = c, cu = c;
   if constexpr (P::kDim2) {
-    cd = wrap_idx<P::kPeriodic>(j - 1, ny) * nx + i;
-    cu = wrap_idx<P::kPeriodic>(j + 1, ny) * nx + i;
+    cd = wrap_idx<periodic_rows<P>::value>(j - 1, ny) * nx + i;
+    cu = wrap_idx<periodic_rows<P>::value>(j + 1, ny) * nx + i;
   }
 #pragma unroll
   for (int f = 0; f < P::NF; ++f) {

@@ -17,7 +17,11 @@
 
 namespace jfnk {
 
-enum ProblemKind { kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4, kSuOlson = 5, kMaxwell = 6 };
+// Problem kinds: the public ids, plus kSuOlsonPY for the Su-Olson problem in
+// its periodic-row configuration (public id 5 with p[1] = 1).
+enum ProblemKind {
+  kBurgers1D = 0, kBurgers2D = 1, kGrayScott = 2, kKerr = 3, kRD2D = 4, kSuOlson = 5, kMaxwell = 6, kSuOlsonPY = 7
+};
 
 // Kernel timing: when the host driver sets g_timing around one launch, the
 // launch goes through hipExtLaunchKernelGGL with start/stop events attached

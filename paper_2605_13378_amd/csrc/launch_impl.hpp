@@ -80,6 +80,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
       return stencil_for_problem<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kSuOlson:
       return stencil_for_problem<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+    case kSuOlsonPY:
+      return stencil_for_problem<SuOlsonPYOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kMaxwell:
       if (a.precond && op != OP_RES)
         return stencil_for_problem<MaxwellTECslpOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
@@ -257,6 +259,8 @@ hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStr
       return fused_for_problem<RD2DOp, T>(a, lds, s);
     case kSuOlson:
       return fused_for_problem<SuOlsonOp, T>(a, lds, s);
+    case kSuOlsonPY:
+      return fused_for_problem<SuOlsonPYOp, T>(a, lds, s);
     case kMaxwell:
       return fused_for_problem<MaxwellTEOp, T>(a, lds, s);
     default:

@@ -248,6 +248,13 @@ struct SuOlsonOp {
   }
 };
 
+// Su-Olson's classic 1D-profile configuration (Appendix A.2): the rows wrap
+// (periodic in y) and only the first and last columns are Dirichlet nodes.
+struct SuOlsonPYOp : SuOlsonOp {
+  static constexpr bool kPeriodicRows = true;
+  __device__ __forceinline__ static bool boundary(int i, int, int nx, int) { return i == 0 || i == nx - 1; }
+};
+
 struct MaxwellTEOp {
   static constexpr int NF = 4;  // planes Re Ex, Im Ex, Re Ey, Im Ey
   static constexpr bool kDim2 = true;
@@ -313,6 +320,17 @@ struct MaxwellTEOp {
 // unpreconditioned kernels are compiled without the extra code.
 struct MaxwellTECslpOp : MaxwellTEOp {
   static constexpr bool kPrecondTangent = true;
+};
+
+// Row (y) periodicity: P::kPeriodicRows where an operator sets it, else the
+// operator's kPeriodic (which always governs the columns).
+template <class P, class = void>
+struct periodic_rows {
+  static constexpr bool value = P::kPeriodic;
+};
+template <class P>
+struct periodic_rows<P, decltype((void)P::kPeriodicRows)> {
+  static constexpr bool value = P::kPeriodicRows;
 };
 
 // Operators whose JVP tangent is preconditioned (P::kPrecondTangent).

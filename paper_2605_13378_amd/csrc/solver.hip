@@ -989,7 +989,18 @@ bool problem_valid(const jfnk_problem* p, std::string* why) {
     if (why) *why = "time-dependent problems need dt > 0 and 0 < theta <= 1";
     return false;
   }
+  if (p->id == JFNK_SUOLSON2D && p->p[1] != 0.0 && p->p[1] != 1.0) {
+    if (why) *why = "Su-Olson p[1] (periodic rows) must be 0 or 1";
+    return false;
+  }
   return true;
+}
+
+// Kernel dispatch kind of a problem: its public id, except the Su-Olson
+// problem in its periodic-row configuration.
+int problem_kind(const jfnk_problem* p) {
+  if (p->id == JFNK_SUOLSON2D && p->p[1] == 1.0) return kSuOlsonPY;
+  return p->id;
 }
 
 long long problem_n(const jfnk_problem* p) {
@@ -1276,7 +1287,7 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   s->prec = precision;
   s->m = m;
   s->stream = static_cast<hipStream_t>(hip_stream);
-  s->pid = problem->id;
+  s->pid = problem_kind(problem);
   s->n = problem_n(problem);
   s->npad = round_up(s->n, 256);
   s->tsize = elem_size(precision);

@@ -150,7 +150,7 @@ struct Tile {
                                        int col0, int cc, int lane) {
 #pragma unroll
     for (int t = 0; t < NR; ++t) {
-      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + t, ny) : 0;
+      const int r = P::kDim2 ? wrap_idx<periodic_rows<P>::value>(r0 - 1 + t, ny) : 0;
       S tmp[P::NF][VEC];
       load_nodes<P, S, VEC>(base, plane, nx, r, cc, tmp);
 #pragma unroll
@@ -164,7 +164,7 @@ struct Tile {
     const bool need_r = (lane == kWave - 1) || (col0 + VEC >= nx);
 #pragma unroll
     for (int hh = 0; hh < RH; ++hh) {
-      const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + halo_row(hh), ny) : 0;
+      const int r = P::kDim2 ? wrap_idx<periodic_rows<P>::value>(r0 - 1 + halo_row(hh), ny) : 0;
 #pragma unroll
       for (int f = 0; f < P::NF; ++f) {
         lh[f][hh] = need_l ? to_c<T>(load_node<P, S>(base, plane, nx, r, cl, f)) : T(0);
@@ -248,7 +248,7 @@ __device__ __forceinline__ void precondition_tile(const KT& k, const Tile<P, T, 
   };
 #pragma unroll
   for (int t = 0; t < TileT::NR; ++t) {
-    const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + t, ny) : 0;
+    const int r = P::kDim2 ? wrap_idx<periodic_rows<P>::value>(r0 - 1 + t, ny) : 0;
 #pragma unroll
     for (int e = 0; e < VEC; ++e)
       node(col0 + e, r, [&](int f) { return X.a[f][t][e]; }, [&](int f) { return V.a[f][t][e]; },
@@ -258,7 +258,7 @@ __device__ __forceinline__ void precondition_tile(const KT& k, const Tile<P, T, 
   const int cr = wrap_idx<P::kPeriodic>(col0 + VEC, nx);
 #pragma unroll
   for (int hh = 0; hh < TileT::RH; ++hh) {
-    const int r = P::kDim2 ? wrap_idx<P::kPeriodic>(r0 - 1 + TileT::halo_row(hh), ny) : 0;
+    const int r = P::kDim2 ? wrap_idx<periodic_rows<P>::value>(r0 - 1 + TileT::halo_row(hh), ny) : 0;
     node(cl, r, [&](int f) { return X.lh[f][hh]; }, [&](int f) { return V.lh[f][hh]; },
          [&](int f, T y) { V.lh[f][hh] = y; });
     node(cr, r, [&](int f) { return X.rh[f][hh]; }, [&](int f) { return V.rh[f][hh]; },

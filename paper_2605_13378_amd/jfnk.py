@@ -169,7 +169,7 @@ def make_problem(spec: dict) -> Problem:
     elif kind == "rd2d":
         vals = [spec["D"]]
     elif kind == "suolson":
-        vals = [spec["xi"]]
+        vals = [spec["xi"], 1.0 if spec.get("periodic_y") else 0.0]
     elif kind == "maxwell":
         vals = [spec["k0"], spec["eps_im"], spec["chi3"]]
     else:

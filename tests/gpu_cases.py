@@ -61,6 +61,13 @@ def case(kind: str, nx: int, ny: int | None = None, seed: int = 0):
     if kind == "suolson":
         x0, src = W.suolson_initial(nx, seed, ny=ny)
         return W.suolson_spec(nx, ny=ny), x0, src
+    if kind == "suolson1d":
+        # periodic rows; a y-dependent start so that the row wrap matters
+        x0, src = W.suolson_box_initial(nx, ny=ny)
+        x0 = x0 + 0.1 * W.random_vector(2 * nx * ny, seed + 3)
+        m = np.zeros((ny, nx))
+        m[:, 1:-1] = 1.0
+        return W.suolson_spec(nx, ny=ny, periodic_y=True), x0 * np.tile(m.ravel(), 2), src
     if kind == "kerr":
         spec = dict(W.kerr_spec(nx, chi3=0.3, cells_per_wavelength=8.0, eps_im=0.05), ny=ny)
         src = W.kerr_gaussian_source(nx, amp=1.0, sigma=max(1.0, nx / 8), ny=ny)

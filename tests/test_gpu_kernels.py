@@ -30,6 +30,7 @@ SIZES = {
     "kerr": [(40, 24), (17, 9), (3, 3), (130, 11)],
     "rd2d": [(64, 64), (130, 37), (3, 3), (1024, 12)],
     "suolson": [(64, 64), (130, 37), (3, 3), (40, 1030)],
+    "suolson1d": [(64, 64), (130, 37), (3, 3), (40, 1030)],
     "maxwell": [(64, 64), (130, 37), (3, 3), (40, 1030)],
 }
 CASES = [(k, nx, ny) for k, sizes in SIZES.items() for nx, ny in sizes]
@@ -141,6 +142,7 @@ def test_misaligned_pointers_take_the_scalar_path(prec):
 @pytest.mark.parametrize("kind,n,prec", [("grayscott", 1024, "f64"), ("grayscott", 1024, "f32"),
                                          ("burgers2d", 2048, "f32"), ("kerr", 1024, "f64"), ("rd2d", 512, "f64"),
                                          ("rd2d", 512, "f32"), ("suolson", 512, "f64"), ("suolson", 512, "f32"),
+                                         ("suolson1d", 512, "f64"), ("suolson1d", 512, "f32"),
                                          ("maxwell", 512, "f64"), ("maxwell", 512, "f32")])
 def test_full_size_jvp_and_residual(kind, n, prec):
     spec, xp, src = W.config(kind, n=n)

@@ -62,3 +62,35 @@ def test_newton_suolson_fd_reaches_the_ad_iterate():
     xf, if_ = s.newton_solve(dev(xp, wdtype("f64")), mode="fd", tol_krylov=1e-10)
     assert ia["converged"] and if_["converged"]
     assert np.linalg.norm(host(xf) - host(xa)) <= 1e-8 * np.linalg.norm(host(xa))
+
+
+# The classic 1D-profile configuration: rows periodic, the first and last
+# columns Dirichlet nodes, cold start with the central box source.
+
+
+@pytest.mark.parametrize("krylov,orth", [("gmres", "dcgs2"), ("gmres", "cgs2"), ("bicgstab", "cgs2")])
+@pytest.mark.parametrize("nx,ny,prec,tol", [(64, 64, "f64", 1e-12), (130, 37, "f64", 1e-12), (64, 64, "f32", 1e-5)])
+def test_newton_suolson_periodic_rows(krylov, orth, nx, ny, prec, tol):
+    spec, xp, src = case("suolson1d", nx, ny)
+    info, ref = compare_newton(spec, xp, src, prec, "ad", tol, krylov=krylov, orth=orth, krylov_slack=0.1)
+    assert info["converged"] and info["newton_iters"] == 1
+
+
+@pytest.mark.parametrize("engine", ["multi", "single"])
+def test_newton_suolson_periodic_rows_engines(engine):
+    spec, xp, src = case("suolson1d", 12, 10)
+    compare_newton(spec, xp, src, "f64", "ad", 1e-12, engine=engine)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_suolson_1d_profile_full_size(prec, tol):
+    """512^2 from the cold start: one Newton step per iterate against the oracle, and every row
+    of the result the same 1D profile (to rounding: each row sums in the same order)."""
+    spec, xp, src = W.config("suolson1d")
+    info, ref = compare_newton(spec, xp, src, prec, "ad", tol, krylov_slack=0.1, orth="dcgs2")
+    assert info["converged"]
+    x = host(info["history"])[-1]
+    n = spec["nx"] * spec["ny"]
+    U = x[:n].reshape(spec["ny"], spec["nx"])
+    assert np.max(np.abs(U - U[0])) <= (1e-12 if prec == "f64" else 1e-5) * np.abs(U).max()
+    assert U[0, spec["nx"] // 2] > 0 and U[0, 0] == 0.0
