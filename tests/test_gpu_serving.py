@@ -146,7 +146,8 @@ def test_submit_rejects_oversized_and_invalid():
 
 
 def mixed_kind_requests():
-    """Every problem kind and Krylov method in one stream (FP64)."""
+    """Every problem kind (both Su-Olson configurations), Krylov method and the CSLP
+    preconditioner in one stream (FP64)."""
     reqs = []
     spec, xp = W.rd2d_spec(48), W.rd2d_initial(48, 1)
     reqs.append((spec, xp, None, dict(krylov="cg")))
@@ -159,6 +160,10 @@ def mixed_kind_requests():
     spec, x0 = W.burgers2d_paper_case("dsl", 32)
     reqs.append((spec, x0, None, dict(orth="cgs2")))
     reqs.append((W.rd2d_spec(32), W.rd2d_initial(32, 4), None, dict(krylov="bicgstab")))
+    reqs.append((W.maxwell_spec(16, omega=2.5), np.zeros(4 * 16 * 16), W.maxwell_source(16, omega=2.5),
+                 dict(max_newton=20, precond="cslp")))
+    x1, src1 = W.suolson_box_initial(40, ny=24)
+    reqs.append((W.suolson_spec(40, ny=24, periodic_y=True), x1, src1, dict(orth="dcgs2")))
     return reqs
 
 
@@ -182,7 +187,7 @@ def test_mixed_problem_kinds_and_methods_alone_equals_mix():
         # against the oracle with the same method and Gram-Schmidt form
         p = Problem.from_spec(spec)
         opts = NewtonOptions.for_precision("f64", krylov=o.get("krylov", "gmres"), orth=o.get("orth", "dcgs2"),
-                                           max_newton=o.get("max_newton", 15))
+                                           max_newton=o.get("max_newton", 15), precond=o.get("precond", "none"))
         xr, ir = newton_solve(p, xp, opts, source=src)
         assert ir.converged and ir.newton_iters == ia["newton_iters"], (spec["kind"], ir.newton_iters, ia)
         tol = 1e-6 if spec["kind"] == "maxwell" else 1e-10
