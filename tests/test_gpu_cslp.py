@@ -105,6 +105,20 @@ def test_cslp_gmres_f32_ad(nx, ny):
     assert np.linalg.norm(d - ref) <= 2e-4 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("nx,ny,prec,m,tol", [(512, 512, "f64", 8, 1e-9), (37, 29, "f32", 8, 2e-4),
+                                              (37, 29, "f64", 8, 1e-9), (3, 3, "f64", 4, 1e-12),
+                                              (4, 3, "f32", 4, 1e-5)])
+def test_cslp_gmres_sizes(nx, ny, prec, m, tol):
+    """Full size in FP64; an odd width (the scalar, one-column-per-thread path, whose halo words
+    cross every wavefront edge); the smallest grids (one or two interior nodes)."""
+    spec, src, p, xw, rhs = linear_case(nx, ny, prec)
+    ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, m, 1)
+    dx, info = run_gpu(spec, src, prec, xw, rhs, m, 1, orth="dcgs2" if nx > 4 else "cgs2")
+    assert info["krylov_iters"] == rinfo.iters, (info["krylov_iters"], rinfo.iters)
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= tol * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+
+
 def test_cslp_gmres_f16_storage():
     spec, src, p, xw, rhs = linear_case(40, 36, "f32")
     ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, 8, 1)
