@@ -51,6 +51,18 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_traffic(kernel: str, bytes_per_launch: float, orth: str, sources: str | None = None):
+    """HBM bytes per launch of `kernel` from the calibrated counter ratio, or None when no
+    measurement exists for it, or the kernel sources or the Gram-Schmidt form differ from the
+    ones the counters were taken with."""
+    meas = MEASURED_TRAFFIC.get(kernel)
+    if meas is None or meas["orth"] != orth:
+        return None
+    if meas["sources"] != (kernel_sources_hash() if sources is None else sources):
+        return None
+    return round(meas["ratio"] * bytes_per_launch)
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -682,10 +694,7 @@ def main():
                        share=round(v["ms"] / total_ms, 4) if total_ms > 0 else 0.0)
                for k, v in stats.items() if v["launches"]}
     bpl = dom["bytes"] / max(1, dom["launches"])
-    meas = MEASURED_TRAFFIC.get(dom_name)
-    traffic = None
-    if meas is not None and meas["sources"] == kernel_sources_hash() and meas["orth"] == ORTH:
-        traffic = round(meas["ratio"] * bpl)  # HBM bytes per launch, calibrated counters
+    traffic = measured_traffic(dom_name, bpl, ORTH)
     roofline = dict(bound="hbm", kernel=dom_name, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic, avg_us=round(dom_avg_us, 3),
                     launches=dom["launches"], bytes_per_launch_avg=bpl)
