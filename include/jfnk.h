@@ -231,11 +231,23 @@ jfnk_status jfnk_residual(jfnk_solver* s, const void* x, void* F);
 jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, void* F_or_null,
                      int mode, double eps, int eps_rule);
 
-/* Solve J(x) dx = rhs by restarted GMRES(m) from dx = 0 with CGS2 Arnoldi and
- * FP64 Givens least squares; tolerance relative to ||rhs||.  Reaching the
- * cycle cap returns JFNK_OK with info->converged = 0. */
+/* Solve J(x) dx = rhs by restarted GMRES(m) (paper, Section 2) from dx = 0,
+ * with the Gram-Schmidt form set by jfnk_set_orthogonalization (DCGS2 by
+ * default in FP64/FP32, CGS2 with FP16 storage) and FP64 Givens least
+ * squares; tolerance relative to ||rhs||.  Reaching the cycle cap returns
+ * JFNK_OK with info->converged = 0. */
 jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx, int m, double tol,
                        int max_restarts, int mode, double eps, int eps_rule, jfnk_info* info);
+
+/* Unrotated Hessenberg matrix of the last restart cycle of the last GMRES
+ * solve on the multi-kernel engine (paper, Section 2: the Arnoldi relation
+ * J V_k = V_{k+1} H_k, column j holding V^T J v_j and ||w_j||), either
+ * Gram-Schmidt form.  *k_out receives k, the cycle's Arnoldi steps; H (host,
+ * column-major, leading dimension ldh >= k + 1, nullable when k = 0)
+ * receives the (k + 1) x k matrix, zero below the subdiagonal.  With a
+ * preconditioner it is that of J M^{-1}.  Synchronizes the solver's stream;
+ * JFNK_ERR_ARG when H is too small. */
+jfnk_status jfnk_gmres_hessenberg(jfnk_solver* s, double* H, int ldh, int* k_out);
 
 /* Solve J(x) dx = rhs by BiCGSTAB (paper, Section 2: van der Vorst's
  * stabilized bi-conjugate gradients, two JVPs per iteration) from dx = 0

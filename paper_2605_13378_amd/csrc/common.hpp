@@ -239,7 +239,9 @@ struct Ctl {
   double vsig[kMaxM + 1];            // FP16 storage: V_i holds w_i * vsig_i (a power of two)
   double H[(kMaxM + 1) * kMaxM];     // rotated Hessenberg, column-major, ld = kMaxM + 1
   // Arnoldi with the second Gram-Schmidt pass delayed one step (krylov.hpp):
-  double Hu[(kMaxM + 1) * kMaxM];    // unrotated Hessenberg (first projections, then completed columns)
+  double Hu[(kMaxM + 1) * kMaxM];    // unrotated Hessenberg, completed columns (written by the column's completion;
+                                     // read by the DCGS2 update pass and by jfnk_gmres_hessenberg)
+  double Hp[(kMaxM + 1) * kMaxM];    // first projections of each column (written by the update pass, read by the completion)
   double tscale[kMaxM + 1];          // scale of the JVP tangent of step j: J (tscale_j U_j)
   double ahat[kMaxM + 1];            // second-pass coefficients of the pending vector over its norm
   double jvn2c[kMaxM + 1];           // ||J u^_j||^2 of step j (breakdown test of column j)

@@ -127,7 +127,13 @@ __device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Pa
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   if (tid == 0) {
     out = givens_column(in, j, tot[0], col);
-    if (blockIdx.x == 0 && blockIdx.y == 0) givens_commit(ctl, j, out, col, host_flags);
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      givens_commit(ctl, j, out, col, host_flags);
+      // the unrotated column (no kernel on this path reads Hu)
+      const int ld = kMaxM + 1;
+      for (int i = 0; i <= j; ++i) ctl->Hu[j * ld + i] = in.h[i];
+      ctl->Hu[j * ld + j + 1] = out.wn;
+    }
   }
   __syncthreads();
   return out;
@@ -147,7 +153,10 @@ __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, c
   __shared__ double ucol[kMaxM + 2];
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int ld = kMaxM + 1;
-  if (tid <= c) in.h[tid] = ctl->Hu[c * ld + tid];
+  // the first projection comes from Hp, which no block of this kernel
+  // writes; block 0 commits the completed column to Hu, which no block of
+  // this kernel reads
+  if (tid <= c) in.h[tid] = ctl->Hp[c * ld + tid];
   if (tid < c) {
     in.cs[tid] = ctl->cs[tid];
     in.sn[tid] = ctl->sn[tid];
@@ -419,12 +428,12 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
       const double h = sh_b[l] - sh_ha[l];
       sh_cv[l] = -sh_ah[l] * sh_sc[l];
       sh_cw[l] = (sh_ha[l] + h - gamma * sh_ah[l]) * sh_sc[l];
-      if (blockIdx.x == 0) ctl->Hu[j * ld + l] = h;
+      if (blockIdx.x == 0) ctl->Hp[j * ld + l] = h;
     }
     sh_cv[j] = ts;
     sh_cw[j] = gamma * ts;
     if (blockIdx.x == 0) {
-      ctl->Hu[j * ld + j] = gamma - sh_ha[j];
+      ctl->Hp[j * ld + j] = gamma - sh_ha[j];
       ctl->scale[j] = 1.0;
       ctl->jvn2c[j] = tot[K];
     }

@@ -89,7 +89,7 @@ struct jfnk_solver {
   double* parts = nullptr;
   size_t part_rows = 0;
   Ctl* ctl = nullptr;
-  Ctl* hctl = nullptr;     // pinned host mirror of the control block header
+  Ctl* hctl = nullptr;     // pinned host mirror of the control block header (+ one whole-block copy)
   int* hflags = nullptr;   // pinned, mapped: per-step stop flags written by the device
   int* dflags = nullptr;   // device view of hflags
   int* hpub = nullptr;     // pinned, mapped: the control block's head published by the device, then its sequence word
@@ -1356,12 +1356,13 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   }
   if (st == JFNK_OK) {
     void* h = nullptr;
-    if (hipHostMalloc(&h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    // two control blocks: the head mirror, then a whole-block copy for jfnk_gmres_hessenberg
+    if (hipHostMalloc(&h, 2 * sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
       s->err = "hipHostMalloc failed";
       st = JFNK_ERR_OOM;
     } else {
       s->hctl = static_cast<Ctl*>(h);
-      std::memset(s->hctl, 0, sizeof(Ctl));
+      std::memset(s->hctl, 0, 2 * sizeof(Ctl));
     }
   }
   if (st == JFNK_OK) {
@@ -1549,6 +1550,23 @@ jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx,
   return st;
 }
 
+jfnk_status jfnk_gmres_hessenberg(jfnk_solver* s, double* H, int ldh, int* k_out) {
+  if (!s || !k_out) return JFNK_ERR_ARG;
+  Ctl* c = s->hctl + 1;  // host scratch behind the head mirror
+  JFNK_HIP(s, hipMemcpyAsync(c, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  JFNK_HIP(s, hipStreamSynchronize(s->stream));
+  const int k = c->k_last;
+  *k_out = k;
+  if (k == 0) return JFNK_OK;
+  if (!H || ldh < k + 1) {
+    s->err = "H must hold (k + 1) x k doubles with ldh >= k + 1";
+    return JFNK_ERR_ARG;
+  }
+  const int ld = kMaxM + 1;
+  for (int l = 0; l < k; ++l)
+    for (int i = 0; i <= k; ++i) H[(size_t)l * ldh + i] = i <= l + 1 ? c->Hu[l * ld + i] : 0.0;
+  return JFNK_OK;
+}
 
 jfnk_status jfnk_bicgstab(jfnk_solver* s, const void* x, const void* rhs, void* dx, double tol, int max_iters,
                           int mode, double eps, int eps_rule, jfnk_info* info) {

@@ -101,6 +101,8 @@ _SIGNATURES = [
     ("jfnk_gmres", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(Info)]),
+    ("jfnk_gmres_hessenberg", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]),
     ("jfnk_bicgstab", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                      ctypes.POINTER(Info)]),
@@ -297,6 +299,17 @@ class Solver:
         d = info.as_dict()
         d["converged"] = bool(info.converged)
         return dx, d
+
+    def gmres_hessenberg(self):
+        """Unrotated (k + 1) x k Hessenberg matrix of the last GMRES cycle (numpy, FP64)."""
+        import numpy as np
+
+        k = ctypes.c_int(0)
+        ld = self.m + 1
+        H = np.zeros((self.m, ld), dtype=np.float64)  # column-major: row l of this array is column l
+        self._check(lib().jfnk_gmres_hessenberg(self._h, H.ctypes.data, ld, ctypes.byref(k)))
+        kk = k.value
+        return np.ascontiguousarray(H[:kk, : kk + 1].T)
 
     def bicgstab(self, x, rhs, tol=1e-8, max_iters=100, mode="ad", eps=0.0, eps_rule="paper"):
         """BiCGSTAB solve of J(x) dx = rhs; returns (dx, info dict with 'breakdown')."""

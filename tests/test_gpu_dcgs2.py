@@ -59,6 +59,34 @@ def test_gmres_dcgs2_parity(kind, nx, ny, m, prec):
     assert np.linalg.norm(host(dx2) - ref_c) <= bound * np.linalg.norm(ref_c)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_gmres_hessenberg_matches_oracle(orth, prec):
+    """The unrotated Hessenberg matrix the GPU builds over one full cycle, entry
+    by entry, against the oracle's (either Gram-Schmidt form; the two agree in
+    exact arithmetic) on a grid that spreads every kernel over many blocks.
+    In the delayed form each column's first projection and its completion are
+    separate control-block arrays: a completion that read a column its own
+    launch had already completed would add the second-pass sums twice."""
+    spec, xp, src, p, xw, rhs = linear_case("grayscott", 256, 192, prec)
+    m = 20
+    mv = lambda v: jvp_ad(p, xw, v, xp, src)[1]  # noqa: E731
+    s = solver(spec, prec, xp, src, m=m)
+    s.set_orthogonalization(orth)
+    _, info = s.gmres(dev(xw, wdtype(prec)), dev(rhs, wdtype(prec)), m=m, tol=1e-300, max_restarts=1)
+    assert info["krylov_iters"] == m and not info["converged"]
+    H = s.gmres_hessenberg()
+    assert H.shape == (m + 1, m)
+    bound = 1e-12 if prec == "f64" else 1e-5
+    for form in ("dcgs2", "cgs2"):
+        _, ri = gmres_solve(mv, rhs, m=m, tol=1e-300, max_restarts=1, orth=form, record=True)
+        Hr = ri.last_H
+        assert Hr.shape == H.shape
+        scale = float(np.abs(Hr).max())
+        assert float(np.abs(H - Hr).max()) <= bound * scale, (form, float(np.abs(H - Hr).max()) / scale)
+        assert np.all(np.tril(H, -2) == 0.0)
+
+
 def test_gmres_dcgs2_cycle_ends():
     spec, xp, src, p, xw, rhs = linear_case("grayscott", 32, 32, "f64")
     mv = lambda v: jvp_ad(p, xw, v, xp, src)[1]  # noqa: E731
