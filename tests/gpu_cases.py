@@ -80,3 +80,40 @@ def rel_err(got, ref, x=None):
     if x is not None:
         scale = max(scale, float(np.abs(x).max()))
     return float(np.abs(got - ref).max()) / scale
+
+
+def _node_planes(spec, a):
+    """View of a state vector as (fields, ny, nx) planes (Kerr's interleaved pairs as two planes)."""
+    nx, ny = spec["nx"], spec["ny"]
+    if spec["kind"] == "kerr":
+        return a.reshape(ny, nx, 2).transpose(2, 0, 1)
+    return a.reshape(-1, ny, nx)
+
+
+def local_scale(spec, *arrays):
+    """Per element: the largest |value| of any of `arrays` over every field of
+    the node's 3 x 3 neighbourhood (the operands a stencil output at that node
+    is formed from), laid out like a state vector."""
+    from scipy.ndimage import maximum_filter
+
+    nx, ny = spec["nx"], spec["ny"]
+    nf = None
+    s = None
+    for a in arrays:
+        pl = np.abs(_node_planes(spec, np.asarray(a, dtype=np.float64)))
+        nf = pl.shape[0]
+        m = maximum_filter(pl.max(axis=0), size=3, mode="wrap")
+        s = m if s is None else np.maximum(s, m)
+    if spec["kind"] == "kerr":
+        return np.repeat(s.reshape(-1), 2)
+    return np.tile(s.reshape(-1), nf)
+
+
+def elem_err(got, ref, scale):
+    """max_i |got_i - ref_i| / max(|ref_i|, scale_i): a per-element relative
+    error, so that a mistake confined to small entries is not hidden by the
+    largest ones (scale_i, from local_scale, keeps nodes where the output
+    cancels to near zero from demanding more than their operands' rounding)."""
+    den = np.maximum(np.abs(ref), scale)
+    den = np.where(den > 0.0, den, 1.0)
+    return float((np.abs(got - ref) / den).max())

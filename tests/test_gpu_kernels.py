@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_cases import case, dev, gpu_available, host, rel_err, wdtype
+from gpu_cases import case, dev, elem_err, gpu_available, host, local_scale, rel_err, wdtype
 from oracle import EPS_MACH, Problem, fd_step, jvp_ad, jvp_fd, residual
 
 pytestmark = pytest.mark.gpu
@@ -68,6 +68,7 @@ def test_residual_parity(kind, nx, ny, prec):
     s = make_solver(spec, prec, xp, src)
     got = host(s.residual(dev(x, wdtype(prec))))
     assert rel_err(got, ref, x) <= TOL[prec]
+    assert elem_err(got, ref, local_scale(spec, *[a for a in (ref, x, xp, src) if a is not None])) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -81,6 +82,8 @@ def test_ad_jvp_parity(kind, nx, ny, prec):
     jv, F = s.jvp(dev(x, wdtype(prec)), dev(v, wdtype(prec)), mode="ad", want_F=True)
     assert rel_err(host(jv), Jref, v) <= TOL[prec]
     assert rel_err(host(F), Fref, x) <= TOL[prec]
+    assert elem_err(host(jv), Jref, local_scale(spec, Jref, v)) <= TOL[prec]
+    assert elem_err(host(F), Fref, local_scale(spec, *[a for a in (Fref, x, xp, src) if a is not None])) <= TOL[prec]
     jv_only = s.jvp(dev(x, wdtype(prec)), dev(v, wdtype(prec)), mode="ad")
     assert np.array_equal(host(jv_only), host(jv))
 
@@ -154,6 +157,8 @@ def test_full_size_jvp_and_residual(kind, n, prec):
     jv, F = s.jvp(dev(x, wdtype(prec)), dev(v, wdtype(prec)), mode="ad", want_F=True)
     assert rel_err(host(jv), Jref, v) <= TOL[prec]
     assert rel_err(host(F), Fref, x) <= TOL[prec]
+    assert elem_err(host(jv), Jref, local_scale(spec, Jref, v)) <= TOL[prec]
+    assert elem_err(host(F), Fref, local_scale(spec, *[a for a in (Fref, x, xp, src) if a is not None])) <= TOL[prec]
     assert rel_err(host(s.residual(dev(x, wdtype(prec)))), Fref, x) <= TOL[prec]
 
 

@@ -58,18 +58,27 @@ def compare_newton(spec, xp, src, prec, mode, tol, x0=None, eps_rule="paper", kr
         assert prof["fused_solve"]["launches"] == 1 and prof["residual"]["launches"] == 0, prof
     elif engine == "multi" or precond != "none":  # AUTO takes the multi-kernel engine with a preconditioner
         assert prof["fused_solve"]["launches"] == 0 and prof["residual"]["launches"] >= 1, prof
-    assert info["newton_iters"] == info_ref.newton_iters, (info, info_ref)
-    assert info["converged"] == info_ref.converged
     hist = host(info["history"])
-    for k, (r_gpu, r_ref) in enumerate(zip(info["rel_res"], info_ref.rel_res)):
-        assert abs(r_gpu - r_ref) <= tol, (k, r_gpu, r_ref)
-        xr = info_ref.iterates[k]
-        assert np.linalg.norm(hist[k] - xr) <= tol * np.linalg.norm(xr), k
-    for a, b in zip(info["lin_iters"], info_ref.lin_iters):
-        slack = 1 if (mode == "ad" and prec == "f64") else (2 if mode == "ad" else 1 + b // 10)
-        if krylov_slack is not None:
-            slack = max(slack, int(krylov_slack * b))
-        assert abs(a - b) <= slack, (info["lin_iters"], info_ref.lin_iters)
+    refs = [(orth, info_ref)]
+    if orth == "dcgs2" and krylov == "gmres":
+        # the delayed second pass and plain CGS2 build the same Krylov basis
+        # in exact arithmetic: a mistake shared by the GPU kernel and the
+        # oracle's DCGS2 form would show against the plain form
+        o2 = NewtonOptions.for_precision(prec, mode=mode, eps_rule=eps_rule, krylov=krylov, orth="cgs2",
+                                         precond=precond, **kw)
+        refs.append(("cgs2", newton_solve(p, xp, o2, source=src, x0=x0, record=True)[1]))
+    for form, ref in refs:
+        assert info["newton_iters"] == ref.newton_iters, (form, info, ref)
+        assert info["converged"] == ref.converged, form
+        for k, (r_gpu, r_ref) in enumerate(zip(info["rel_res"], ref.rel_res)):
+            assert abs(r_gpu - r_ref) <= tol, (form, k, r_gpu, r_ref)
+            xr = ref.iterates[k]
+            assert np.linalg.norm(hist[k] - xr) <= tol * np.linalg.norm(xr), (form, k)
+        for a, b in zip(info["lin_iters"], ref.lin_iters):
+            slack = 1 if (mode == "ad" and prec == "f64") else (2 if mode == "ad" else 1 + b // 10)
+            if krylov_slack is not None:
+                slack = max(slack, int(krylov_slack * b))
+            assert abs(a - b) <= slack, (form, info["lin_iters"], ref.lin_iters)
     assert np.array_equal(host(x_gpu), hist[-1])
     return info, info_ref
 
