@@ -323,6 +323,27 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   Tile<P, T, VEC, RY> X;
   Tile<P, T, VEC, RY> Vt;
   int col0 = 0, r0 = 0;
+  // the pointwise term b of the centre rows (zero when absent), loaded with
+  // the tile so that its latency overlaps the exchange; the AD tangent alone
+  // does not involve it
+  constexpr bool kNeedB = OP != OP_AD || WITHF;
+  T bval[RC][NF][VEC];
+  const bool use_b = a.b != nullptr;
+  auto load_b = [&](int cc) {
+#pragma unroll
+    for (int tt = 0; tt < RC; ++tt) {
+      const int r = r0 + tt;
+      const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
+      if (kNeedB && use_b) {
+        load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval[tt]);
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) bval[tt][f][e] = T(0);
+      }
+    }
+  };
   // the first tile's loads go out before the stop check and the prologue
   // reductions (in-bounds either way; unused if the cycle has stopped)
   if (t_begin < t_end) {
@@ -330,6 +351,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     const int cc = col0 < nx ? col0 : 0;
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
+    load_b(cc);
   }
 
   // Arnoldi mode: leave at once if the cycle has already stopped
@@ -389,7 +411,10 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     eps = fd_eps(a.eps, vn2);
     eps_s = T(eps * vscale);
   }
-  const T eps_t = T(eps);
+  // the quotient by eps as a product with its reciprocal (formed once, in
+  // FP64): within one rounding of the division, far inside the FD JVP's
+  // rounding bound of a few u S / eps
+  const T inv_eps = T(OP == OP_FD ? 1.0 / eps : 0.0);
   const T vs_t = T(vscale);
 
   constexpr int NACC = OP == OP_RES ? 2 : (KDOT > 0 ? KDOT + 1 : 1);
@@ -415,15 +440,6 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       const int r = r0 + tt;
       const bool ok = colok && (!P::kDim2 || r < ny);
       const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
-      T bval[NF][VEC];
-      if (a.b != nullptr) {
-        load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval);
-      } else {
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) bval[f][e] = T(0);
-      }
       T o[NF][VEC];
       T o2[NF][VEC];
 #pragma unroll
@@ -436,7 +452,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           P::template N<T, T>(k, xn, n);
 #pragma unroll
           for (int f = 0; f < NF; ++f)
-            o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[f][e];
+            o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[tt][f][e];
         } else if constexpr (OP == OP_AD) {
           Nbr<T> vn[NF];
           Vt.nbr(tt, e, vn);
@@ -448,7 +464,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
             o[f][e] = bnd ? vn[f].c : alpha * vn[f].c + cN * n[f].t;
-            o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[f][e];
+            o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[tt][f][e];
           }
         } else {
           Nbr<T> vn[NF];
@@ -461,9 +477,9 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           P::template N<T, T>(k, yn, n1);
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
-            const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[f][e];
-            const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[f][e];
-            o[f][e] = (f1 - f0) / eps_t;
+            const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[tt][f][e];
+            const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[tt][f][e];
+            o[f][e] = (f1 - f0) * inv_eps;
           }
         }
       }
@@ -524,6 +540,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     const int cc = col0 < nx ? col0 : 0;
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
+    load_b(cc);
     process();
   }
 
