@@ -136,6 +136,14 @@ inline StencilPlan stencil_plan(int pid, int nx, int ny, int vec, int cap) {
 // Blocks of a stencil launch with at most `cap` blocks.
 inline int stencil_blocks(int pid, int nx, int ny, int vec, int cap) { return stencil_plan(pid, nx, ny, vec, cap).grid; }
 
+// Per-operator launchers (launch_stencil.hpp), each (operator, precision)
+// pair instantiated in its own translation unit.
+template <class P, class T, class VT>
+hipError_t launch_stencil_p(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a, const Coefs& c,
+                            int cap, hipStream_t s, int* nblocks);
+template <class P, class T>
+hipError_t launch_fused_p(const FusedArgs<T>& a, size_t lds, hipStream_t s);
+
 // Launches the stencil kernel on at most `cap` blocks; *nblocks (nullable)
 // receives the block count (the number of partial rows it writes).  In
 // Arnoldi mode with a.Vb set, the first CGS projection on a.K basis vectors

@@ -6,86 +6,28 @@
 
 namespace jfnk {
 
-template <class P, class T, class VT, int VEC, int RY, int OP>
-static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid, dim3 block, hipStream_t s) {
-  if constexpr (RY == 1) {
-    // RY = 1 plans only uncapped launches, which carry no fused projection
-    if (a.Vb != nullptr) return hipErrorInvalidValue;
-    JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
-  } else {
-    if (a.Vb == nullptr)
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
-    else if (a.K <= 4)
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
-    else if (a.K <= 8)
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 8>), grid, block, s, a, c);
-    else if (a.K <= 16)
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 16>), grid, block, s, a, c);
-    else
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 32>), grid, block, s, a, c);
-  }
-  return hipGetLastError();
-}
-
-template <class P, class T, class VT, int VEC, int RY>
-static hipError_t stencil_by_op(int op, bool withf, const StencilArgs<T, VT>& a, const Coefs& c, dim3 grid,
-                                dim3 block, hipStream_t s) {
-  if (op == OP_RES) {
-    if constexpr (std::is_same<T, VT>::value) {
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_RES, false, 0>), grid, block, s, a, c);
-      return hipGetLastError();
-    } else {
-      return hipErrorInvalidValue;
-    }
-  }
-  if (op == OP_AD) {
-    if (withf) {
-      JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP_AD, true, 0>), grid, block, s, a, c);
-      return hipGetLastError();
-    }
-    return stencil_kdot<P, T, VT, VEC, RY, OP_AD>(a, c, grid, block, s);
-  }
-  return stencil_kdot<P, T, VT, VEC, RY, OP_FD>(a, c, grid, block, s);
-}
-
-template <class P, class T, class VT>
-static hipError_t stencil_for_problem(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
-                                      const Coefs& c, int cap, hipStream_t s, int* nblocks) {
-  constexpr int V = (P::kInterleaved || P::kCorners) ? (int)(8 / sizeof(T)) : (int)(16 / sizeof(T));
-  const int vec = vectorized ? V : 1;
-  const StencilPlan p = stencil_plan(pid, a.nx, a.ny, vec, cap);
-  if (nblocks) *nblocks = p.grid;
-  const dim3 grid(p.grid, 1, 1);
-  if (!vectorized) return stencil_by_op<P, T, VT, 1, 2>(op, withf, a, c, grid, p.block, s);
-  if constexpr (P::kDim2) {
-    if (p.ry == 4) return stencil_by_op<P, T, VT, V, 4>(op, withf, a, c, grid, p.block, s);
-    if (p.ry == 1) return stencil_by_op<P, T, VT, V, 1>(op, withf, a, c, grid, p.block, s);
-  }
-  return stencil_by_op<P, T, VT, V, 2>(op, withf, a, c, grid, p.block, s);
-}
-
 template <class T, class VT>
 hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const StencilArgs<T, VT>& a,
                           const Coefs& c, int cap, hipStream_t s, int* nblocks) {
   switch (pid) {
     case kBurgers1D:
-      return stencil_for_problem<Burgers1DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<Burgers1DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kBurgers2D:
-      return stencil_for_problem<Burgers2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<Burgers2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kGrayScott:
-      return stencil_for_problem<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kKerr:
-      return stencil_for_problem<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kRD2D:
-      return stencil_for_problem<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kSuOlson:
-      return stencil_for_problem<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<SuOlsonOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kSuOlsonPY:
-      return stencil_for_problem<SuOlsonPYOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<SuOlsonPYOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kMaxwell:
       if (a.precond && op != OP_RES)
-        return stencil_for_problem<MaxwellTECslpOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
-      return stencil_for_problem<MaxwellTEOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+        return launch_stencil_p<MaxwellTECslpOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
+      return launch_stencil_p<MaxwellTEOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     default:
       return hipErrorInvalidValue;
   }
@@ -234,35 +176,25 @@ hipError_t launch_cg(int kind, const CgArgs<T>& a, double tol, int grid, hipStre
   return hipGetLastError();
 }
 
-template <class P, class T>
-static hipError_t fused_for_problem(const FusedArgs<T>& a, size_t lds, hipStream_t s) {
-  const auto k = fused_solve_kernel<P, T>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  JFNK_LAUNCH_SHM(k, dim3(1), dim3(kFusedThreads), lds, s, a);
-  return hipGetLastError();
-}
-
 template <class T>
 hipError_t launch_fused_solve(int pid, const FusedArgs<T>& a, size_t lds, hipStream_t s) {
   switch (pid) {
     case kBurgers1D:
-      return fused_for_problem<Burgers1DOp, T>(a, lds, s);
+      return launch_fused_p<Burgers1DOp, T>(a, lds, s);
     case kBurgers2D:
-      return fused_for_problem<Burgers2DOp, T>(a, lds, s);
+      return launch_fused_p<Burgers2DOp, T>(a, lds, s);
     case kGrayScott:
-      return fused_for_problem<GrayScottOp, T>(a, lds, s);
+      return launch_fused_p<GrayScottOp, T>(a, lds, s);
     case kKerr:
-      return fused_for_problem<KerrOp, T>(a, lds, s);
+      return launch_fused_p<KerrOp, T>(a, lds, s);
     case kRD2D:
-      return fused_for_problem<RD2DOp, T>(a, lds, s);
+      return launch_fused_p<RD2DOp, T>(a, lds, s);
     case kSuOlson:
-      return fused_for_problem<SuOlsonOp, T>(a, lds, s);
+      return launch_fused_p<SuOlsonOp, T>(a, lds, s);
     case kSuOlsonPY:
-      return fused_for_problem<SuOlsonPYOp, T>(a, lds, s);
+      return launch_fused_p<SuOlsonPYOp, T>(a, lds, s);
     case kMaxwell:
-      return fused_for_problem<MaxwellTEOp, T>(a, lds, s);
+      return launch_fused_p<MaxwellTEOp, T>(a, lds, s);
     default:
       return hipErrorInvalidValue;
   }
