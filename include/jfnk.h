@@ -282,6 +282,28 @@ jfnk_status jfnk_cg(jfnk_solver* s, const void* x, const void* rhs, void* dx, do
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts,
                               jfnk_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the Newton
+ * solve of jfnk_newton_solve on the SINGLE_WORKGROUP engine without a solver
+ * handle and without any allocation.  It computes the constant part from
+ * x_prev and source (FP64 device arrays of n entries as for
+ * jfnk_set_previous; x_prev may be NULL for Kerr and Maxwell) and runs the
+ * solve from x_inout (FP64 device array, overwritten with the last iterate)
+ * on `hip_stream` (a hipStream_t; NULL = the default stream), then
+ * synchronizes that stream and fills info.  The constant part and the solve
+ * record live in a static device array of 68 KiB per GPU (allocated with the
+ * library's code object and held until the process ends), so the call
+ * accepts at most 4096 unknowns, FP64 or FP32 (not FP16S), GMRES with no
+ * preconditioner and an engine of AUTO or SINGLE_WORKGROUP, and the problem
+ * must fit the engine's LDS; otherwise it returns JFNK_ERR_ARG and
+ * jfnk_last_error(NULL) says why.  Results are bitwise those of
+ * jfnk_newton_solve on the same engine.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialized by the caller.  Statuses as for jfnk_newton_solve. */
+jfnk_status jfnk_newton_solve_noalloc(const jfnk_problem* problem, int precision, const double* x_prev,
+                                      const double* source, double* x_inout, const jfnk_options* opts,
+                                      jfnk_info* info, void* hip_stream);
+
 /* Gram-Schmidt form (jfnk_orth) of later jfnk_gmres calls on this solver
  * (default DCGS2 in FP64 and FP32, CGS2 with FP16 storage); jfnk_newton_solve
  * takes it from its options instead (jfnk_default_options: the same).

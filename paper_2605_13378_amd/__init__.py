@@ -24,5 +24,6 @@ from .jfnk import (  # noqa: F401
     footprint_bytes,
     lib,
     make_problem,
+    newton_solve_noalloc,
     problem_size,
 )

@@ -17,7 +17,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1074,7 +1076,14 @@ void release(jfnk_solver* s) {
   }
 }
 
-thread_local std::string g_create_error;
+// Last error of the calls that take no handle (jfnk_create,
+// jfnk_newton_solve_noalloc), per thread; a fixed buffer, so that recording
+// an error allocates nothing.
+thread_local char g_free_error[256] = "";
+
+void set_free_error(const char* msg) {
+  std::snprintf(g_free_error, sizeof(g_free_error), "%s", msg);
+}
 
 }  // namespace
 
@@ -1270,7 +1279,7 @@ const char* jfnk_status_string(int status) {
 }
 
 const char* jfnk_last_error(const jfnk_solver* s) {
-  if (!s) return g_create_error.c_str();
+  if (!s) return g_free_error;
   return s->err.c_str();
 }
 
@@ -1279,15 +1288,15 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   *out = nullptr;
   std::string why;
   if (!problem_valid(problem, &why)) {
-    g_create_error = why;
+    set_free_error(why.c_str());
     return JFNK_ERR_ARG;
   }
   if (precision != JFNK_F64 && precision != JFNK_F32 && precision != JFNK_F16S) {
-    g_create_error = "unknown precision";
+    set_free_error("unknown precision");
     return JFNK_ERR_ARG;
   }
   if (m < 1 || m > kMaxM) {
-    g_create_error = "m must be in 1..32";
+    set_free_error("m must be in 1..32");
     return JFNK_ERR_ARG;
   }
   jfnk_solver* s = new jfnk_solver();
@@ -1401,7 +1410,7 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
     st = JFNK_ERR_HIP;
   }
   if (st != JFNK_OK) {
-    g_create_error = s->err;
+    set_free_error(s->err.c_str());
     release(s);
     delete s;
     return st;
@@ -1611,6 +1620,150 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
     st = Impl<float, __half>::newton(s, x_inout, o, info);
   info->status = st;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Newton solve without allocation (single-workgroup engine)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device workspace of jfnk_newton_solve_noalloc: the solve record, then the
+// constant part in FP64 and in the working precision, for at most
+// kNoAllocMaxN unknowns.  One copy per GPU, held until the process ends;
+// every call on a GPU shares it.
+constexpr long long kNoAllocMaxN = 4096;
+constexpr size_t kNoAllocInfoBytes = 4096;
+constexpr size_t kNoAllocScratchBytes = kNoAllocInfoBytes + 2 * (size_t)kNoAllocMaxN * sizeof(double);
+static_assert(sizeof(FusedInfo) <= kNoAllocInfoBytes, "solve record must fit its slot");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Per device: the address of `scratch` (from hipGetSymbolAddress; the array's
+// name is not a device address in host code), its compute units and LDS size.
+constexpr int kNoAllocMaxDevices = 64;
+struct NoAllocDevice {
+  unsigned char* ptr = nullptr;
+  int cu = 0;
+  size_t lds = 0;
+};
+NoAllocDevice g_noalloc_dev[kNoAllocMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Set-up on the first call on a device, with that device current.
+bool noalloc_device(NoAllocDevice* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) {
+    set_free_error("no current HIP device (or device index above 63)");
+    return false;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc_dev[dev];
+  if (d.ptr == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      set_free_error("hipGetSymbolAddress of the static workspace failed");
+      return false;
+    }
+    int cu = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0 ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0) {
+      set_free_error("device attribute query failed");
+      return false;
+    }
+    d.cu = cu;
+    d.lds = (size_t)lds;
+    d.ptr = static_cast<unsigned char*>(ptr);
+  }
+  *out = d;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+jfnk_status jfnk_newton_solve_noalloc(const jfnk_problem* problem, int precision, const double* x_prev,
+                                      const double* source, double* x_inout, const jfnk_options* opts,
+                                      jfnk_info* info, void* hip_stream) {
+  if (!problem || !x_inout || !opts || !info) {
+    set_free_error("problem, x_inout, opts and info are required");
+    return JFNK_ERR_ARG;
+  }
+  std::string why;
+  if (!problem_valid(problem, &why)) {
+    set_free_error(why.c_str());
+    return JFNK_ERR_ARG;
+  }
+  if (precision != JFNK_F64 && precision != JFNK_F32) {
+    set_free_error("the allocation-free solve runs in FP64 or FP32");
+    return JFNK_ERR_ARG;
+  }
+  const jfnk_options& o = *opts;
+  if (o.m < 1 || o.m > kMaxM || o.max_newton < 0 || o.max_newton > JFNK_MAX_ITERS || o.max_restarts < 0 ||
+      o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
+      (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0)) {
+    set_free_error("invalid options");
+    return JFNK_ERR_ARG;
+  }
+  if (o.krylov != JFNK_KRYLOV_GMRES || o.engine == JFNK_ENGINE_MULTI_KERNEL || o.precond != JFNK_PRECOND_NONE) {
+    set_free_error("the allocation-free solve runs GMRES on the single-workgroup engine, unpreconditioned");
+    return JFNK_ERR_ARG;
+  }
+  const long long n = problem_n(problem);
+  if (n > kNoAllocMaxN) {
+    set_free_error("problem exceeds the 4096 unknowns of the allocation-free solve's static workspace");
+    return JFNK_ERR_ARG;
+  }
+  const bool bvp = problem->id == JFNK_KERR2D || problem->id == JFNK_MAXWELL2D;
+  if (!bvp && x_prev == nullptr) {
+    set_free_error("x_prev is required for time-dependent problems");
+    return JFNK_ERR_ARG;
+  }
+  NoAllocDevice d;
+  if (!noalloc_device(&d)) return JFNK_ERR_HIP;
+  const size_t need = precision == JFNK_F64 ? fused_lds_bytes<double>(n, o.m) : fused_lds_bytes<float>(n, o.m);
+  if (need > d.lds) {
+    set_free_error("problem does not fit the single-workgroup engine's LDS");
+    return JFNK_ERR_ARG;
+  }
+  // a handle on the stack whose workspace pointers point into the static
+  // array (constant part in FP64, then in the working precision; the solve
+  // record, fully written by the solve kernel before the host reads it)
+  FusedInfo hrec{};
+  jfnk_solver loc;
+  loc.prob = *problem;
+  loc.prec = precision;
+  loc.m = o.m;
+  loc.stream = static_cast<hipStream_t>(hip_stream);
+  loc.pid = problem_kind(problem);
+  loc.n = n;
+  loc.npad = round_up(n, 256);
+  loc.vstride = loc.npad;
+  loc.tsize = elem_size(precision);
+  loc.vsize = loc.tsize;
+  loc.cu = d.cu;
+  loc.lds_max = d.lds;
+  loc.dinfo = reinterpret_cast<FusedInfo*>(d.ptr);
+  loc.hinfo = &hrec;
+  loc.tmp64 = reinterpret_cast<double*>(d.ptr + kNoAllocInfoBytes);
+  loc.b = d.ptr + kNoAllocInfoBytes + (size_t)kNoAllocMaxN * sizeof(double);
+  jfnk_status st = fill_problem(&loc);
+  if (st == JFNK_OK) st = jfnk_set_previous(&loc, x_prev, source);
+  if (st == JFNK_OK) {
+    std::memset(info, 0, sizeof(*info));
+    const auto t0 = std::chrono::steady_clock::now();
+    if (precision == JFNK_F64)
+      st = Impl<double, double>::newton_fused(&loc, x_inout, o, info);
+    else
+      st = Impl<float, float>::newton_fused(&loc, x_inout, o, info);
+    info->status = st;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (st != JFNK_OK && st != JFNK_ERR_NOT_CONVERGED && st != JFNK_ERR_NONFINITE) set_free_error(loc.err.c_str());
   return st;
 }
 

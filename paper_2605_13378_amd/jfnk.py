@@ -111,6 +111,9 @@ _SIGNATURES = [
                                ctypes.POINTER(Info)]),
     ("jfnk_newton_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
                                          ctypes.POINTER(Info)]),
+    ("jfnk_newton_solve_noalloc", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
+                                                 ctypes.POINTER(Info), ctypes.c_void_p]),
     ("jfnk_default_options", None, [ctypes.c_int, ctypes.POINTER(Options)]),
     ("jfnk_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("jfnk_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
@@ -379,6 +382,39 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def newton_solve_noalloc(spec: dict, precision: str, x_prev, source, x_inout, history=None, stream=None,
+                         **opts) -> dict:
+    """jfnk_newton_solve_noalloc: the single-workgroup Newton solve with no
+    solver handle and no device allocation.  x_prev, source (nullable) and
+    x_inout (updated in place) are FP64 CUDA (HIP) tensors of the problem's
+    length; history (nullable) an FP64 tensor of (max_newton + 1) * n entries
+    the caller provides.  Returns the info dict; raises JfnkError on argument
+    errors (jfnk_last_error(NULL) text)."""
+    import torch
+
+    n = problem_size(spec)
+    for name, t in (("x_prev", x_prev), ("source", source), ("x_inout", x_inout), ("history", history)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be an FP64 CUDA (HIP) tensor")
+        if not t.is_contiguous() or (name != "history" and t.numel() != n):
+            raise ValueError(f"{name} must be contiguous with {n} elements")
+    if history is not None:
+        opts["history"] = history
+    o = default_options(precision, **opts)
+    info = Info()
+    prob = make_problem(spec)
+    st = torch.cuda.current_stream() if stream is None else stream
+    rc = lib().jfnk_newton_solve_noalloc(ctypes.byref(prob), PRECISIONS[precision],
+                                         None if x_prev is None else x_prev.data_ptr(),
+                                         None if source is None else source.data_ptr(), x_inout.data_ptr(),
+                                         ctypes.byref(o), ctypes.byref(info), ctypes.c_void_p(st.cuda_stream))
+    if rc not in (0, 4, 6):
+        raise JfnkError(rc, lib().jfnk_last_error(None).decode())
+    return info.as_dict()
 
 
 class Batch:
