@@ -62,6 +62,31 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&in)[N]) {
   *reinterpret_cast<vec<T, N>*>(p) = t;
 }
 
+// Load with a non-temporal hint, for streams read once per pass (the Krylov
+// basis): on MI355X such loads stream from HBM without being kept in the
+// last-level cache, where a basis larger than that cache would only evict
+// the small vectors that are reused (multi-stream read microbenchmark, 16
+// streams of 8 MB: 5.3 TB/s with ordinary loads, 5.9 TB/s with the hint).
+template <class T, int N>
+__device__ __forceinline__ void load_vec_nt(const T* __restrict__ p, T (&out)[N]) {
+  constexpr int B = (int)sizeof(T) * N;
+  static_assert(B == 2 || B == 4 || B == 8 || B == 16, "vector access of 2, 4, 8 or 16 bytes");
+  vec<T, N> t;
+  if constexpr (B == 2) {
+    const unsigned short u = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+    __builtin_memcpy(&t, &u, B);
+  } else if constexpr (B == 4) {
+    const unsigned int u = __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p));
+    __builtin_memcpy(&t, &u, B);
+  } else {
+    typedef unsigned int uv __attribute__((ext_vector_type(B / 4)));
+    const uv u = __builtin_nontemporal_load(reinterpret_cast<const uv*>(p));
+    __builtin_memcpy(&t, &u, B);
+  }
+#pragma unroll
+  for (int e = 0; e < N; ++e) out[e] = t.a[e];
+}
+
 // The same with a non-temporal hint: for outputs that no kernel of the same
 // sequence reads back right away, so they stream to memory instead of
 // displacing cached inputs.
@@ -112,10 +137,70 @@ __device__ __forceinline__ double uniform(double x) {
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+// Cross-lane moves of an FP64 value by DPP (data-parallel primitives: the
+// lane exchange happens inside a VALU instruction, no LDS round trip), as
+// two 32-bit halves.  CTRL is the DPP control word: quad_perm [1,0,3,2] =
+// 0xB1, [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// v + (v of the lane 16 or 32 away across rows): gfx950's permlane swaps
+// exchange odd and even rows (16) or the two wavefront halves (32) between
+// two registers; swapping a value with itself leaves (own, partner) in the
+// pair, so both partners form the same sum.
+template <int D>
+__device__ __forceinline__ double swap_add_f64(double v) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(u & 0xffffffffLL), hi = (unsigned)(u >> 32);
+  unsigned l0, l1, h0, h1;
+  if constexpr (D == 16) {
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+  } else {
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+  }
+  return __longlong_as_double(((long long)h0 << 32) | (long long)l0) +
+         __longlong_as_double(((long long)h1 << 32) | (long long)l1);
+}
+
+// Sum over aligned groups of G consecutive lanes (G a power of two up to 64);
+// every lane of a group returns its group's sum.  Within a row of 16 lanes
+// the partners come from DPP moves (pairs, quads, half rows, rows, each step
+// combining two halves whose lanes already agree), across rows from the
+// permlane swaps: register-to-register exchanges, no LDS round trip.  Fixed
+// order: the result does not depend on timing.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f64<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v);
+  if constexpr (G >= 32) v = swap_add_f64<16>(v);
+  if constexpr (G >= 64) v = swap_add_f64<32>(v);
   return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<kWave>(v); }
+
+// group_sum for a group size known only at run time (uniform across the wavefront).
+__device__ __forceinline__ double group_sum_rt(double v, int G) {
+  switch (G) {
+    case 64: return group_sum<64>(v);
+    case 32: return group_sum<32>(v);
+    case 16: return group_sum<16>(v);
+    case 8: return group_sum<8>(v);
+    case 4: return group_sum<4>(v);
+    case 2: return group_sum<2>(v);
+    default: return v;
+  }
 }
 
 // Block partial sums.  A reducing kernel writes one FP64 partial sum per
@@ -191,7 +276,7 @@ __device__ __forceinline__ void reduce_partials(const Partials& p, int nr, doubl
       for (int r = 0; r < CH; ++r) s += v[r];
     }
   }
-  for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  s = group_sum_rt(s, G);
   if (col < nr && g == 0) tot[col] = s;
   __syncthreads();
 }

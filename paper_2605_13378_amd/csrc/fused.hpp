@@ -102,8 +102,8 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* sc, doubl
 }
 
 // out[i] = V_i . w for i < K (FP64 accumulation): G lanes of one wavefront
-// per vector (G a power of two, G * K <= threads), then a shuffle tree inside
-// each lane group.  Vector i starts at V + i * ldv; the padded stride puts
+// per vector (G a power of two, G * K <= threads), then a reduction inside
+// each lane group (group_sum).  Vector i starts at V + i * ldv; the padded stride puts
 // the lane groups of one wavefront on different LDS banks.  Barriers on
 // entry (earlier readers of `out`) and exit.
 template <class T>
@@ -117,7 +117,7 @@ __device__ __forceinline__ void block_dots(const T* V, int n, int ldv, int K, co
     const T* v = V + (size_t)i * ldv;
     for (int e = g; e < n; e += G) s += (double)v[e] * (double)w[e];
   }
-  for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  s = group_sum_rt(s, G);
   __syncthreads();
   if (i < K && g == 0) out[i] = s;
   __syncthreads();

@@ -205,20 +205,27 @@ struct KArgs {
   Ctl* ctl;
   Partials in;        // partials of the previous pass (B: pass A's, C: pass B's)
   PartSink out;       // this pass's partial sums
+  int nt;             // 1: basis read with the non-temporal hint
 };
 
 // Loads w and the K basis chunks at element i.  The caller zero-fills vv once:
 // chunks k >= K are never loaded and stay zero, so the arithmetic runs over
 // all KMAX slots without per-slot conditions (a zero coefficient times a zero
 // element leaves every sum unchanged, exactly).
-template <class T, class VT, int KMAX, int VEC>
+// NT: basis read with the non-temporal hint (a template parameter: a
+// run-time choice between two load sequences costs the register-resident
+// basis chunk its registers).
+template <class T, class VT, int KMAX, int VEC, bool NT>
 __device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int K, T (&w)[VEC], T (&vv)[KMAX][VEC]) {
   load_vec<T, VEC>(a.w + i, w);
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k < K) {
       VT t[VEC];
-      load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
+      if constexpr (NT)
+        load_vec_nt<VT, VEC>(a.V + k * a.vstride + i, t);
+      else
+        load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) vv[k][e] = to_c<T>(t[e]);
     }
@@ -246,7 +253,7 @@ __device__ __forceinline__ double group_dot(const T (&a)[VEC], const T (&b)[VEC]
   }
 }
 
-template <class T, class VT, int KMAX, int VEC, int MODE>
+template <class T, class VT, int KMAX, int VEC, int MODE, bool NT>
 __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
@@ -260,7 +267,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   for (int k = 0; k < KMAX; ++k)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
-  if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
 
   __shared__ double tot[KMAX + 1];
@@ -347,7 +354,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
         store_vec<VT, VEC>(a.wout + i, o);
       }
     }
-    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC>(a, i + step, K, w, vv);
+    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i + step, K, w, vv);
   }
 
   int nr = MODE == PASS_C ? 1 : K;
@@ -375,7 +382,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
 // with partial sums [V_0..V_j . U_{j+1}, ||U_{j+1}||^2] for the next column's
 // completion.  Block 0 commits h to the unrotated Hessenberg, scale_j = 1 and
 // ||w||^2.  One read of the basis per step, where CGS2 takes two.
-template <class T, class VT, int KMAX, int VEC>
+template <class T, class VT, int KMAX, int VEC, bool NT>
 __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
@@ -388,7 +395,7 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   for (int k = 0; k < KMAX; ++k)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
-  if (i < a.n) cgs_load<T, VT, KMAX, VEC>(a, i, K, w, vv);
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   if (ctl->done_col[j] != kRunning) return;  // state after column j-1
 
   __shared__ double tot[KMAX + 1];
@@ -482,7 +489,7 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
     }
     store_vec<VT, VEC>(vj_out + i, o1);
     store_vec<VT, VEC>(a.wout + i, o2);
-    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC>(a, i + step, K, w, vv);
+    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i + step, K, w, vv);
   }
   // [V_0..V_{j-1} . U_{j+1}, v_j . U_{j+1}, ||U_{j+1}||^2] (static indices keep acc in registers)
 #pragma unroll
@@ -593,9 +600,10 @@ struct VyArgs {
   PartSink out;  // partial sums of ||dx||^2
   int* host_flags;
   int lagged;    // 1: the basis comes from the delayed-second-pass Arnoldi steps
+  int nt;        // 1: basis read with the non-temporal hint
 };
 
-template <class T, class VT, int KMAX, int VEC>
+template <class T, class VT, int KMAX, int VEC, bool NT>
 __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
   __shared__ double y[kMaxM];
@@ -679,7 +687,10 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
     for (int c = 0; c < KMAX; ++c) {
       VT t[VEC];
       if (c < k) {
-        load_vec<VT, VEC>(a.V + c * a.vstride + i, t);
+        if constexpr (NT)
+          load_vec_nt<VT, VEC>(a.V + c * a.vstride + i, t);
+        else
+          load_vec<VT, VEC>(a.V + c * a.vstride + i, t);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) t[e] = VT(0);

@@ -41,42 +41,52 @@ hipError_t launch_cslp_apply(int pid, const T* x, T* z, int nx, int ny, const Co
   return hipGetLastError();
 }
 
-template <class T, class VT, int KMAX>
+template <class T, class VT, int KMAX, bool NT>
 static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
   constexpr int VEC = cgs_vec<T, KMAX>();
   const dim3 g(grid), b(kKrylovThreads);
   if (mode == PASS_A)
-    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_A>), g, b, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_A, NT>), g, b, s, a);
   else if (mode == PASS_B)
-    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_B>), g, b, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_B, NT>), g, b, s, a);
   else
-    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_C>), g, b, s, a);
+    JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_C, NT>), g, b, s, a);
   return hipGetLastError();
+}
+
+template <class T, class VT, bool NT>
+static hipError_t launch_cgs_nt(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
+  if (a.K <= 4) return cgs_by_mode<T, VT, 4, NT>(mode, a, grid, s);
+  if (a.K <= 8) return cgs_by_mode<T, VT, 8, NT>(mode, a, grid, s);
+  if (a.K <= 16) return cgs_by_mode<T, VT, 16, NT>(mode, a, grid, s);
+  return cgs_by_mode<T, VT, 32, NT>(mode, a, grid, s);
 }
 
 template <class T, class VT>
 hipError_t launch_cgs(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
-  if (a.K <= 4) return cgs_by_mode<T, VT, 4>(mode, a, grid, s);
-  if (a.K <= 8) return cgs_by_mode<T, VT, 8>(mode, a, grid, s);
-  if (a.K <= 16) return cgs_by_mode<T, VT, 16>(mode, a, grid, s);
-  return cgs_by_mode<T, VT, 32>(mode, a, grid, s);
+  return a.nt ? launch_cgs_nt<T, VT, true>(mode, a, grid, s) : launch_cgs_nt<T, VT, false>(mode, a, grid, s);
+}
+
+template <class T, class VT, bool NT>
+static hipError_t launch_dcgs_nt(const KArgs<T, VT>& a, int grid, hipStream_t s) {
+  const dim3 b(kKrylovThreads);
+  if (a.K <= 4)
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 4, cgs_vec<T, 4>(), NT>), dim3(grid), b, s, a);
+  else if (a.K <= 8)
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 8, cgs_vec<T, 8>(), NT>), dim3(grid), b, s, a);
+  else if (a.K <= 16)
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 16, cgs_vec<T, 16>(), NT>), dim3(grid), b, s, a);
+  else
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 32, cgs_vec<T, 32>(), NT>), dim3(grid), b, s, a);
+  return hipGetLastError();
 }
 
 template <class T, class VT>
 hipError_t launch_dcgs(const KArgs<T, VT>& a, int grid, hipStream_t s) {
-  const dim3 b(kKrylovThreads);
   if constexpr (!std::is_same<T, VT>::value) {
     return hipErrorInvalidValue;  // FP16 storage keeps CGS2
   } else {
-    if (a.K <= 4)
-      JFNK_LAUNCH((dcgs_kernel<T, VT, 4, cgs_vec<T, 4>()>), dim3(grid), b, s, a);
-    else if (a.K <= 8)
-      JFNK_LAUNCH((dcgs_kernel<T, VT, 8, cgs_vec<T, 8>()>), dim3(grid), b, s, a);
-    else if (a.K <= 16)
-      JFNK_LAUNCH((dcgs_kernel<T, VT, 16, cgs_vec<T, 16>()>), dim3(grid), b, s, a);
-    else
-      JFNK_LAUNCH((dcgs_kernel<T, VT, 32, cgs_vec<T, 32>()>), dim3(grid), b, s, a);
-    return hipGetLastError();
+    return a.nt ? launch_dcgs_nt<T, VT, true>(a, grid, s) : launch_dcgs_nt<T, VT, false>(a, grid, s);
   }
 }
 
@@ -87,17 +97,22 @@ hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class T, class VT>
-hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
+template <class T, class VT, bool NT>
+static hipError_t launch_vy_nt(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
   constexpr int VEC = krylov_vec<T>();
   const dim3 g(grid), b(kKrylovThreads);
   if (m <= 8)
-    JFNK_LAUNCH((vy_kernel<T, VT, 8, VEC>), g, b, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 8, VEC, NT>), g, b, s, a);
   else if (m <= 16)
-    JFNK_LAUNCH((vy_kernel<T, VT, 16, VEC>), g, b, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 16, VEC, NT>), g, b, s, a);
   else
-    JFNK_LAUNCH((vy_kernel<T, VT, 32, VEC>), g, b, s, a);
+    JFNK_LAUNCH((vy_kernel<T, VT, 32, VEC, NT>), g, b, s, a);
   return hipGetLastError();
+}
+
+template <class T, class VT>
+hipError_t launch_vy(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
+  return a.nt ? launch_vy_nt<T, VT, true>(a, m, grid, s) : launch_vy_nt<T, VT, false>(a, m, grid, s);
 }
 
 template <class T, class VT>

@@ -59,6 +59,15 @@ long long round_up(long long v, long long q) { return (v + q - 1) / q * q; }
 // 4160 351 solves/s.
 constexpr long long kBasisPad = 1056;
 
+// Basis passes read with the non-temporal hint once their working set
+// exceeds this many bytes (1.5 times the 256 MB last-level cache).  Below it
+// the basis of a restart cycle stays largely cache-resident from one pass to
+// the next and ordinary loads win; above it a cyclic sweep would only evict
+// the reused vectors.  Measured per Arnoldi step (Gray-Scott, DCGS2): 2048^2
+// FP32 from j = 8 (~400 MB) on 8-14% faster, 1024^2 FP64 faster from j = 20
+// and slower below j = 16 (~340 MB), 1024^2 FP32 slower at every step.
+constexpr double kNtBasisBytes = 384.0 * (1 << 20);
+
 }  // namespace
 
 struct jfnk_solver {
@@ -369,6 +378,7 @@ struct Impl {
       a.vstride = s->vstride;
       a.K = arn_j + 1;
       a.dots_out = sink(s, 0);
+      a.nt_basis = (double)(arn_j + 4) * s->n * sizeof(W) > kNtBasisBytes ? 1 : 0;
     }
     const int vec = stencil_vec<T>(s->pid);
     const bool vz = (s->prob.nx % vec == 0) && aligned(x, 16) && aligned(v, vec * sizeof(W)) && aligned(Jv, 16) &&
@@ -476,7 +486,8 @@ struct Impl {
         if (j >= 1) flags[j - 1] = -1;
         int nb_jvp = 0;  // the JVP carries the first projection (pass A)
         JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged, pre));
-        KArgs<T, VT> ka{s->npad, basis(s, 0), s->vstride, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1)};
+        KArgs<T, VT> ka{s->npad, basis(s, 0), s->vstride, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1),
+                        (double)(K + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
         if (lagged) {
           // one update pass: v_j completed, the next vector projected once
           ProfScope ps(s, PK_D, (double)s->n * ((K + 2) * sizeof(VT) + sizeof(T)));
@@ -501,7 +512,7 @@ struct Impl {
                          lagged ? parts(s, 1, dcgs_grid(s, jmax >= 0 ? jmax + 1 : 1))
                                 : parts(s, 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)),
                          sink(s, 4), s->dflags,
-                         lagged ? 1 : 0};
+                         lagged ? 1 : 0, (double)(jmax + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
         ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
         JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
       }

@@ -57,6 +57,7 @@ struct StencilArgs {
   const VT* Vb;          // basis, vector k at Vb + k * vstride
   long long vstride;
   int K;
+  int nt_basis;          // 1: basis rows read with the non-temporal hint
   PartSink dots_out;
   // BiCGSTAB JVPs (gate non-null): leave at once when *gate is not
   // kRunning, or, with gate_parts rows, when the square root of their
@@ -93,6 +94,24 @@ __device__ __forceinline__ void load_nodes(const S* __restrict__ base, long long
   } else {
 #pragma unroll
     for (int f = 0; f < P::NF; ++f) load_vec<S, VEC>(base + f * plane + (long long)r * nx + c, out[f]);
+  }
+}
+
+// load_nodes with the non-temporal hint (basis rows read once per pass)
+template <class P, class S, int VEC>
+__device__ __forceinline__ void load_nodes_nt(const S* __restrict__ base, long long plane, int nx, int r, int c,
+                                              S (&out)[P::NF][VEC]) {
+  if constexpr (P::kInterleaved) {
+    S tmp[2 * VEC];
+    load_vec_nt<S, 2 * VEC>(base + 2 * ((long long)r * nx + c), tmp);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      out[0][e] = tmp[2 * e];
+      out[1][e] = tmp[2 * e + 1];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f) load_vec_nt<S, VEC>(base + f * plane + (long long)r * nx + c, out[f]);
   }
 }
 
@@ -422,10 +441,19 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
 
+  // Arnoldi JVP: the outputs of the thread's rows, kept for the projection
+  // on the basis, and the number of basis vectors whose loads go out together
+  constexpr int kProjBytes = RC * NF * VEC * (int)sizeof(VT);
+  constexpr int kProjGroup0 = 256 / kProjBytes < 1 ? 1 : (256 / kProjBytes > 8 ? 8 : 256 / kProjBytes);
+  constexpr int kProjGroup = KDOT > 0 && kProjGroup0 > KDOT ? KDOT : kProjGroup0;
+  T po[KDOT > 0 ? RC : 1][NF][VEC];
+  int prow[KDOT > 0 ? RC : 1];
+
   // one tile whose loads have been issued (X, Vt at col0, r0)
   auto process = [&]() {
     const bool colok = col0 < nx;
     const int cc = colok ? col0 : 0;
+    const int pcc = cc;
     X.exchange(col0, nx, lane);
     if constexpr (OP != OP_RES) {
       Vt.exchange(col0, nx, lane);
@@ -501,33 +529,72 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
             }
         }
         if constexpr (OP != OP_RES && KDOT > 0) {
-          // first CGS projection of the new vector on the stored basis
 #pragma unroll
           for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[KDOT] += (double)o[f][e] * (double)o[f][e];
+        }
+      }
+      if constexpr (OP != OP_RES && KDOT > 0) {
+        // keep the row (zero outside the grid) for the projection below
+        prow[tt] = rr;
 #pragma unroll
-          for (int q = 0; q < KDOT; ++q) {
-            if (q < a.K) {
-              VT vq[NF][VEC];
-              load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rr, cc, vq);
-              if constexpr (sizeof(T) == 4) {
-                // FP32 sum over the thread's chunk, FP64 across chunks (as in pass B)
-                T p = T(0);
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int f = 0; f < NF; ++f)
+          for (int e = 0; e < VEC; ++e) po[tt][f][e] = ok ? o[f][e] : T(0);
+      }
+    }
+    if constexpr (OP != OP_RES && KDOT > 0) {
+      // First CGS projection of the new vector on the stored basis, over all
+      // of the thread's rows at once.  The rows of G basis vectors are loaded
+      // together before any is used (about 256 bytes in flight per lane; a
+      // load-use pair per vector and row would leave the pass waiting on one
+      // memory round trip after another).  Slots of the last group beyond K
+      // reload vector K-1 and their products are discarded.
 #pragma unroll
-                  for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[f][e]), o[f][e], p);
-                acc[q] += (double)p;
-              } else {
-                double s = 0.0;
+      for (int q0 = 0; q0 < KDOT; q0 += kProjGroup) {
+        if (q0 < a.K) {
+          VT vq[kProjGroup][RC][NF][VEC];
+          if (a.nt_basis) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f)
+            for (int u = 0; u < kProjGroup; ++u) {
+              const int q = q0 + u < a.K ? q0 + u : a.K - 1;
 #pragma unroll
-                  for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[f][e]) * (double)o[f][e];
-                acc[q] += s;
-              }
+              for (int tt = 0; tt < RC; ++tt)
+                load_nodes_nt<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, prow[tt], pcc, vq[u][tt]);
             }
+          } else {
+#pragma unroll
+            for (int u = 0; u < kProjGroup; ++u) {
+              const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+#pragma unroll
+              for (int tt = 0; tt < RC; ++tt)
+                load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, prow[tt], pcc, vq[u][tt]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kProjGroup; ++u) {
+            double s;
+            if constexpr (sizeof(T) == 4) {
+              // FP32 sum over the thread's chunk, FP64 across chunks (as in the update pass)
+              T p = T(0);
+#pragma unroll
+              for (int tt = 0; tt < RC; ++tt)
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[u][tt][f][e]), po[tt][f][e], p);
+              s = (double)p;
+            } else {
+              s = 0.0;
+#pragma unroll
+              for (int tt = 0; tt < RC; ++tt)
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[u][tt][f][e]) * (double)po[tt][f][e];
+            }
+            acc[q0 + u] += q0 + u < a.K ? s : 0.0;
           }
         }
       }
