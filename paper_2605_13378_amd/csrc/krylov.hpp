@@ -29,9 +29,11 @@ namespace jfnk {
 enum { PASS_A = 0, PASS_B = 1, PASS_C = 2 };
 
 // ---------------------------------------------------------------------------
-// Givens update of Hessenberg column j (one thread, FP64).
-// Reads hA, hB, jvn2, cs/sn[0..j-1], gp[j], tol_abs, brk_tol; the results go
-// to a GivensOut and `col`, and are committed to Ctl by block 0 only.
+// Givens update of Hessenberg column j (FP64), in the prologue of the kernel
+// that follows the pass which produced the column's last sums.  The first
+// wavefront of every block does it: the lanes check and prepare the
+// column's entries in parallel, one lane runs the rotation chain, and block 0
+// commits the result to Ctl.
 // ---------------------------------------------------------------------------
 struct GivensOut {
   double c, s, gr, gp1, est, wn;
@@ -63,32 +65,51 @@ __device__ inline void givens_gather(const Ctl* __restrict__ ctl, int j, GivensI
   }
 }
 
-__device__ inline GivensOut givens_column(const GivensIn& in, int j, double wn2, double* col) {
+// Column j = (in.h[0..j], sqrt(wn2)) rotated by G_0..G_{j-1}, the new rotation
+// G_j and the g update, written to `col` (LDS, j + 2 entries) and `out` (LDS).
+// Called by the threads of the first wavefront (tid < 64); `any_bad` is their
+// vote on a non-finite entry of in.h.  The rotated entry is carried in a
+// register from one rotation to the next, with the rotation inputs read from
+// LDS eight at a time ahead of the arithmetic, so the chain costs FP64
+// latency only (a column kept in LDS costs an LDS round trip per rotation).
+__device__ inline void givens_column(const GivensIn& in, int j, double wn2, bool any_bad, double* col,
+                                     GivensOut& out) {
+  if (threadIdx.x != 0 || threadIdx.y != 0) return;
   GivensOut o;
   o.wn = sqrt(wn2);
   o.vs = 1.0 / (o.wn * in.sig);
-  for (int i = 0; i <= j; ++i) col[i] = in.h[i];
-  col[j + 1] = o.wn;
-  bool finite = isfinite(o.wn);
-  for (int i = 0; i <= j; ++i) finite = finite && isfinite(col[i]);
-  for (int i = 0; i < j; ++i) {
-    const double t = in.cs[i] * col[i] + in.sn[i] * col[i + 1];
-    col[i + 1] = -in.sn[i] * col[i] + in.cs[i] * col[i + 1];
-    col[i] = t;
+  double a = in.h[0];
+  for (int i0 = 0; i0 < j; i0 += 8) {
+    double hb[8], cb[8], sb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u < kMaxM ? i0 + u : kMaxM - 1;  // in bounds; slots past j unused
+      hb[u] = in.h[i + 1];
+      cb[u] = in.cs[i];
+      sb[u] = in.sn[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < j) {
+        const double b = hb[u];
+        col[i0 + u] = cb[u] * a + sb[u] * b;
+        a = -sb[u] * a + cb[u] * b;
+      }
+    }
   }
   o.c = 1.0;
   o.s = 0.0;
-  if (col[j + 1] != 0.0) {
-    const double r = hypot(col[j], col[j + 1]);
-    o.c = col[j] / r;
-    o.s = col[j + 1] / r;
+  if (o.wn != 0.0) {
+    const double r = hypot(a, o.wn);
+    o.c = a / r;
+    o.s = o.wn / r;
   }
-  col[j] = o.c * col[j] + o.s * col[j + 1];
+  col[j] = o.c * a + o.s * o.wn;
   col[j + 1] = 0.0;
   o.gr = o.c * in.gp;
   o.gp1 = -o.s * in.gp;
   o.est = fabs(o.gp1);
-  finite = finite && isfinite(o.est);
+  const bool finite = !any_bad && isfinite(o.wn) && isfinite(a) && isfinite(o.est);
   o.done = kRunning;
   if (!finite)
     o.done = kNonfinite;
@@ -96,21 +117,30 @@ __device__ inline GivensOut givens_column(const GivensIn& in, int j, double wn2,
     o.done = kConverged;
   else if (o.wn <= in.brk_tol * sqrt(in.jvn2))
     o.done = kBreakdown;
-  return o;
+  out = o;
 }
 
+// Block 0's commit of column j, after a barrier: the rotated column to H and
+// the unrotated one (`ucol`, j + 2 entries in LDS) to Hu by the lanes of the
+// first wavefront, the scalars by lane 0.
 __device__ inline void givens_commit(Ctl* __restrict__ ctl, int j, const GivensOut& o, const double* col,
-                                     int* host_flags) {
+                                     const double* ucol, int* host_flags) {
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int ld = kMaxM + 1;
-  for (int i = 0; i <= j + 1; ++i) ctl->H[j * ld + i] = col[i];
-  ctl->cs[j] = o.c;
-  ctl->sn[j] = o.s;
-  ctl->gr[j] = o.gr;
-  ctl->gp[j + 1] = o.gp1;
-  ctl->res_est = o.est;
-  ctl->scale[j + 1] = o.vs;
-  ctl->done_col[j + 1] = o.done;
-  if (host_flags) host_flags[j] = o.done;
+  if (tid <= j + 1) {
+    ctl->H[j * ld + tid] = col[tid];
+    ctl->Hu[j * ld + tid] = ucol[tid];
+  }
+  if (tid == 0) {
+    ctl->cs[j] = o.c;
+    ctl->sn[j] = o.s;
+    ctl->gr[j] = o.gr;
+    ctl->gp[j + 1] = o.gp1;
+    ctl->res_est = o.est;
+    ctl->scale[j + 1] = o.vs;
+    ctl->done_col[j + 1] = o.done;
+    if (host_flags) host_flags[j] = o.done;
+  }
 }
 
 // Prologue of the kernel that follows pass C of step j (the JVP of step j+1
@@ -122,20 +152,18 @@ __device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Pa
   __shared__ double tot[1];
   __shared__ GivensIn in;
   __shared__ GivensOut out;
+  __shared__ double ucol[kMaxM + 2];
   givens_gather(ctl, j, in);
   reduce_partials(pc, 1, tot);  // ends with a barrier: `in` is complete too
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  if (tid == 0) {
-    out = givens_column(in, j, tot[0], col);
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-      givens_commit(ctl, j, out, col, host_flags);
-      // the unrotated column (no kernel on this path reads Hu)
-      const int ld = kMaxM + 1;
-      for (int i = 0; i <= j; ++i) ctl->Hu[j * ld + i] = in.h[i];
-      ctl->Hu[j * ld + j + 1] = out.wn;
-    }
+  if (tid < kWave) {
+    const bool any_bad = __any(tid <= j && !isfinite(in.h[tid])) != 0;
+    if (tid <= j) ucol[tid] = in.h[tid];
+    givens_column(in, j, tot[0], any_bad, col, out);  // lane 0 only
+    if (tid == 0) ucol[j + 1] = out.wn;
   }
   __syncthreads();
+  if (blockIdx.x == 0 && blockIdx.y == 0) givens_commit(ctl, j, out, col, ucol, host_flags);
   return out;
 }
 
@@ -151,6 +179,7 @@ __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, c
   __shared__ GivensIn in;
   __shared__ GivensOut out;
   __shared__ double ucol[kMaxM + 2];
+  __shared__ double s_beta;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int ld = kMaxM + 1;
   // the first projection comes from Hp, which no block of this kernel
@@ -168,26 +197,38 @@ __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, c
     in.jvn2 = ctl->jvn2c[c];
     in.sig = 1.0;
   }
+  __shared__ double s_b2;
+  __shared__ int s_bad;
   reduce_partials(pd, c + 2, tot);  // ends with a barrier: `in` is complete too
-  if (tid == 0) {
-    double aa = 0.0;
-    for (int i = 0; i <= c; ++i) aa += tot[i] * tot[i];
+  if (tid < kWave) {
+    // the second-pass coefficients a_i = tot[i] (lane i), ||a||^2 over the wavefront
+    const double ai = tid <= c ? tot[tid] : 0.0;
+    const double aa = wave_sum(ai * ai);
     const double uu = tot[c + 1];
     const double b2 = uu - aa;
-    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
-    for (int i = 0; i <= c; ++i) in.h[i] += tot[i];
-    out = givens_column(in, c, b2 > 0.0 ? b2 : 0.0, col);  // its norm is sqrt(b2) = beta
-    if (!isfinite(uu)) out.done = kNonfinite;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-      for (int i = 0; i <= c; ++i) ucol[i] = in.h[i];
-      ucol[c + 1] = beta;
-      givens_commit(ctl, c, out, col, host_flags);
-      for (int i = 0; i <= c + 1; ++i) ctl->Hu[c * ld + i] = ucol[i];
-      for (int i = 0; i <= c; ++i) ctl->ahat[i] = tot[i] / beta;
-      ctl->tscale[c + 1] = out.vs;
+    bool bad = false;
+    if (tid <= c) {
+      const double h = in.h[tid] + ai;
+      in.h[tid] = h;
+      ucol[tid] = h;
+      bad = !isfinite(h);
+    }
+    const bool any_bad = __any(bad) != 0;
+    if (tid == 0) {
+      s_b2 = b2 > 0.0 ? b2 : 0.0;
+      s_bad = (any_bad || !isfinite(uu)) ? 1 : 0;
+      s_beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+      ucol[c + 1] = s_beta;
     }
   }
   __syncthreads();
+  givens_column(in, c, s_b2, s_bad != 0, col, out);  // its norm is sqrt(b2) = beta; lane 0 only
+  __syncthreads();
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    givens_commit(ctl, c, out, col, ucol, host_flags);
+    if (tid <= c) ctl->ahat[tid] = tot[tid] / s_beta;
+    if (tid == 0) ctl->tscale[c + 1] = out.vs;
+  }
   return out;
 }
 
