@@ -252,20 +252,54 @@ __device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double
 }
 
 // Column sums of the first nb rows for columns k < nr into `tot` (LDS),
-// visible to the whole block on return.  Each lane issues up to 16 loads
-// before adding, so the prologue costs about one memory round trip.
-__device__ __forceinline__ void reduce_partials(const Partials& p, int nr, double* tot) {
-  constexpr int CH = 16;
+// visible to the whole block on return, in two phases: partials_fetch issues
+// each lane's first 16 loads into registers (a kernel can do this before its
+// main loads, so that the round trips overlap), partials_reduce adds them,
+// loads and adds any further rows, reduces within the lane groups and writes
+// `tot`.  G lanes share a column (G a power of two, G * nr <= threads).
+struct PartialFetch {
+  static constexpr int CH = 16;
+  double v[CH];
+};
+
+__device__ __forceinline__ int partials_group(int nr) {
   const int nthreads = blockDim.x * blockDim.y;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   int G = kWave;
   while (G > 1 && G * nr > nthreads) G >>= 1;
+  return G;
+}
+
+__device__ __forceinline__ void partials_fetch(const Partials& p, int nr, PartialFetch& f) {
+  constexpr int CH = PartialFetch::CH;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int G = partials_group(nr);
+  const int col = tid / G;
+  const int g = tid % G;
+  if (col < nr) {
+    const double* __restrict__ q = p.part + (size_t)col * p.ld;
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int b = g + r * G;
+      f.v[r] = b < p.nb ? q[b] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < CH; ++r) f.v[r] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void partials_reduce(const Partials& p, int nr, const PartialFetch& f, double* tot) {
+  constexpr int CH = PartialFetch::CH;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int G = partials_group(nr);
   const int col = tid / G;
   const int g = tid % G;
   double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < CH; ++r) s += f.v[r];
   if (col < nr) {
     const double* __restrict__ q = p.part + (size_t)col * p.ld;
-    for (int b0 = g; b0 < p.nb; b0 += G * CH) {
+    for (int b0 = g + G * CH; b0 < p.nb; b0 += G * CH) {
       double v[CH];
 #pragma unroll
       for (int r = 0; r < CH; ++r) {
@@ -279,6 +313,12 @@ __device__ __forceinline__ void reduce_partials(const Partials& p, int nr, doubl
   s = group_sum_rt(s, G);
   if (col < nr && g == 0) tot[col] = s;
   __syncthreads();
+}
+
+__device__ __forceinline__ void reduce_partials(const Partials& p, int nr, double* tot) {
+  PartialFetch f;
+  partials_fetch(p, nr, f);
+  partials_reduce(p, nr, f, tot);
 }
 
 // ---------------------------------------------------------------------------

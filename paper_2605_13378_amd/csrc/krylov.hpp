@@ -167,28 +167,45 @@ __device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Pa
   return out;
 }
 
+// Inputs of the completion of column c in the delayed form, fetched into
+// registers before a kernel's main loads (lagged_prefetch) so that their
+// round trips overlap those loads.
+struct LaggedPrefetch {
+  PartialFetch pf;
+  double h, cs, sn;
+};
+
+__device__ __forceinline__ void lagged_prefetch(const Ctl* __restrict__ ctl, int c, const Partials& pd,
+                                                LaggedPrefetch& lp) {
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int ld = kMaxM + 1;
+  partials_fetch(pd, c + 2, lp.pf);
+  lp.h = tid <= c ? ctl->Hp[c * ld + tid] : 0.0;
+  lp.cs = tid < c ? ctl->cs[tid] : 0.0;
+  lp.sn = tid < c ? ctl->sn[tid] : 0.0;
+}
+
 // Delayed second pass (the alternative Arnoldi form): column c is completed
 // by the kernel after the update pass of step c, from that pass's partial
 // sums pd = [V_0..V_c . u, u . u] of the pending vector u (once projected):
 // a = V^T u, beta = sqrt(u.u - a.a), column = (first projection + a, beta),
 // then the Givens update as for CGS2.  Block 0 commits the unrotated column,
 // the rotation, a / beta and 1 / beta (the tangent scale of step c + 1).
-__device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, const Partials& pd, int* host_flags,
-                                                 double* col) {
+__device__ __forceinline__ GivensOut finish_column_lagged_from(Ctl* __restrict__ ctl, int c, const Partials& pd,
+                                                               int* host_flags, double* col, const LaggedPrefetch& lp) {
   __shared__ double tot[kMaxM + 2];
   __shared__ GivensIn in;
   __shared__ GivensOut out;
   __shared__ double ucol[kMaxM + 2];
   __shared__ double s_beta;
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int ld = kMaxM + 1;
   // the first projection comes from Hp, which no block of this kernel
   // writes; block 0 commits the completed column to Hu, which no block of
   // this kernel reads
-  if (tid <= c) in.h[tid] = ctl->Hp[c * ld + tid];
+  if (tid <= c) in.h[tid] = lp.h;
   if (tid < c) {
-    in.cs[tid] = ctl->cs[tid];
-    in.sn[tid] = ctl->sn[tid];
+    in.cs[tid] = lp.cs;
+    in.sn[tid] = lp.sn;
   }
   if (tid == 0) {
     in.gp = ctl->gp[c];
@@ -199,7 +216,7 @@ __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, c
   }
   __shared__ double s_b2;
   __shared__ int s_bad;
-  reduce_partials(pd, c + 2, tot);  // ends with a barrier: `in` is complete too
+  partials_reduce(pd, c + 2, lp.pf, tot);  // ends with a barrier: `in` is complete too
   if (tid < kWave) {
     // the second-pass coefficients a_i = tot[i] (lane i), ||a||^2 over the wavefront
     const double ai = tid <= c ? tot[tid] : 0.0;
@@ -230,6 +247,14 @@ __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, c
     if (tid == 0) ctl->tscale[c + 1] = out.vs;
   }
   return out;
+}
+
+// The same, fetching its own inputs.
+__device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, const Partials& pd, int* host_flags,
+                                                 double* col) {
+  LaggedPrefetch lp;
+  lagged_prefetch(ctl, c, pd, lp);
+  return finish_column_lagged_from(ctl, c, pd, host_flags, col, lp);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,15 +455,13 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   const int j = K - 1;
   const long long step = (long long)gridDim.x * blockDim.x * VEC;
   long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  T w[VEC];
-  T vv[KMAX][VEC];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
-  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   if (ctl->done_col[j] != kRunning) return;  // state after column j-1
 
+  // The prologue's loads (partial sums, control-block inputs) go out together
+  // and before the basis chunk: issued after it, each would wait for the
+  // whole chunk to arrive (vector loads complete in order).
+  PartialFetch pf;
+  partials_fetch(a.in, K + 1, pf);
   __shared__ double tot[KMAX + 1];
   __shared__ double sh_ah[KMAX], sh_sc[KMAX], sh_b[KMAX], sh_ha[KMAX + 1];
   __shared__ double sh_cv[KMAX], sh_cw[KMAX];
@@ -457,7 +480,7 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
     sh_sc[tid] = ctl->scale[tid];
   }
   if (tid == 0) sh_ts = ctl->tscale[j];
-  reduce_partials(a.in, K + 1, tot);  // ends with a barrier
+  partials_reduce(a.in, K + 1, pf, tot);  // ends with a barrier
   if (tid < j) sh_b[tid] = tot[tid] * sh_sc[tid];
   if (tid <= j) {
     // (H a^)_i over the completed columns 0..j-1 (row j only has column j-1)
@@ -487,6 +510,13 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
     }
   }
   __syncthreads();
+  T w[VEC];
+  T vv[KMAX][VEC];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   T cv[KMAX], cw[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {

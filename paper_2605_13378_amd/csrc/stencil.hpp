@@ -363,8 +363,16 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       }
     }
   };
-  // the first tile's loads go out before the stop check and the prologue
-  // reductions (in-bounds either way; unused if the cycle has stopped)
+  // Arnoldi JVP of the delayed form: the loads of the column completion in
+  // the prologue go out first, then the first tile's (in-bounds either way;
+  // unused if the cycle has stopped), so that the two sets of round trips
+  // overlap (vector loads complete in order: issued after the tile, the
+  // prologue's loads would wait for all of it).
+  LaggedPrefetch lpf;
+  const bool lag_pre = OP != OP_RES && a.ctl != nullptr && a.lagged && a.arn_j > 0;
+  if constexpr (OP != OP_RES) {
+    if (lag_pre) lagged_prefetch(a.ctl, a.arn_j - 1, a.pc, lpf);
+  }
   if (t_begin < t_end) {
     tile_origin(t_begin, col0, r0);
     const int cc = col0 < nx ? col0 : 0;
@@ -409,7 +417,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         vscale = a.ctl->scale[0];
       } else {
         __shared__ double gcol[kMaxM + 1];
-        const GivensOut g = a.lagged ? finish_column_lagged(a.ctl, j - 1, a.pc, a.host_flags, gcol)
+        const GivensOut g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
                                      : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
         if (g.done != kRunning) return;  // uniform: every block computed the same update
         vscale = g.vs;
