@@ -3,7 +3,9 @@
 Workload: implicit (backward-Euler) step of the two-species Gray-Scott
 reaction-diffusion system on a 1024 x 1024 periodic grid (D = 2e-5,
 Dv = 1e-5, F = 0.04, k = 0.06, dt = 1, h = sqrt(D dt)), seeded random square
-patches, solved by Newton with line search around GMRES(30) with CGS2 Arnoldi
+patches, solved by Newton with line search around GMRES(30) with classical
+Gram-Schmidt applied twice, the second pass delayed one step (DCGS2, two
+passes over the basis per Arnoldi step; --orth cgs2 runs the three-pass form),
 and FP64 Givens.  One step = one whole Newton solve of that implicit step
 (residuals, JVPs, every Arnoldi pass, Givens, V y updates, line search), with
 the inputs resident in HBM before the timed region starts.
@@ -141,6 +143,89 @@ def jvp_bandwidth(s, torch, n, prec, mode, reps=200, scrub=None):
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9 if st["ms"] > 0 else 0.0
     return dict(avg_us=round(avg_us, 3), gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4),
                 bytes_per_launch=st["bytes"] / max(1, st["launches"]), launches=st["launches"])
+
+
+def jvp_bandwidth_hbm(torch, spec, xp, src, prec, mode, min_bytes=1 << 30, min_reps=100):
+    """The same measurement with operands the last-level cache cannot hold: R solvers (each with
+    its own constant part b, read by the FD JVP) and R distinct (x, v, Jv) triples, R chosen so
+    that the operands of one sweep exceed `min_bytes` (1 GiB, four times the 256 MB cache), used
+    in turn, so every launch reads vectors last touched R - 1 launches (>= 1 GiB of traffic) ago.
+    No scrub writes are involved: eviction is driven by the JVP reads themselves."""
+    import workloads as W
+    from paper_2605_13378_amd import Solver
+
+    n = W.n_unknowns(spec)
+    esz = 8 if prec == "f64" else 4
+    per_call = (3 if mode == "ad" else 4) * n * esz
+    R = max(2, math.ceil(min_bytes / per_call))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(2)
+    x_prev = torch.tensor(xp, dtype=torch.float64, device="cuda")
+    source = None if src is None else torch.tensor(src, dtype=torch.float64, device="cuda")
+    solvers, xs, vs, outs = [], [], [], []
+    for _ in range(R):
+        sv = Solver(spec, prec, m=1)
+        sv.set_previous(x_prev, source)
+        solvers.append(sv)
+        xs.append(x_prev.to(dt) + 0.1 * torch.randn(n, device="cuda", dtype=dt, generator=g))
+        vs.append(torch.randn(n, device="cuda", dtype=dt, generator=g))
+        outs.append(torch.empty(n, device="cuda", dtype=dt))
+    reps = max(min_reps, 3 * R)
+    for k in range(R):
+        solvers[k].jvp(xs[k], vs[k], mode=mode, out=outs[k])
+    torch.cuda.synchronize()
+    for sv in solvers:
+        sv.profile_reset()
+        sv.profile(True)
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(QUEUE_SPIN_CYCLES)
+    for i in range(reps):
+        k = i % R
+        solvers[k].jvp(xs[k], vs[k], mode=mode, out=outs[k])
+    torch.cuda.synchronize()
+    key = "jvp_ad" if mode == "ad" else "jvp_fd"
+    ms = byt = 0.0
+    launches = 0
+    for sv in solvers:
+        st = sv.profile_read()[key]
+        ms += st["ms"]
+        byt += st["bytes"]
+        launches += st["launches"]
+        sv.profile(False)
+        sv.close()
+    avg_us = ms * 1e3 / max(1, launches)
+    gbs = byt / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return dict(avg_us=round(avg_us, 3), gbs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4),
+                bytes_per_launch=byt / max(1, launches), launches=launches, operand_sets=R,
+                sweep_bytes=R * per_call)
+
+
+def copy_ceiling_hbm(torch, vector_bytes, min_bytes=1 << 30, reps=100):
+    """Reference for the "-hbm" JVP rows: a plain device copy (torch's copy kernel, one read and one
+    write stream) of one vector of `vector_bytes`, rotating over distinct (src, dst) pairs that
+    total >= `min_bytes`, queued back to back; GB/s counts read + written bytes.  It is what a
+    kernel with no arithmetic at all reaches for transfers of this size from HBM."""
+    nel = vector_bytes // 4
+    R = max(2, math.ceil(min_bytes / (2 * vector_bytes)))
+    pairs = [(torch.ones(nel, dtype=torch.float32, device="cuda"), torch.empty(nel, dtype=torch.float32,
+                                                                               device="cuda")) for _ in range(R)]
+    for a, b in pairs:
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(QUEUE_SPIN_CYCLES)
+    e0.record()
+    for i in range(reps):
+        a, b = pairs[i % R]
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    gbs = 2 * vector_bytes / (us * 1e-6) / 1e9
+    del pairs
+    return dict(vector_mb=round(vector_bytes / 1e6, 1), avg_us=round(us, 3), gbs=round(gbs, 1),
+                frac=round(gbs / PEAK_HBM_GBS, 4), pairs=R)
 
 
 def latency_c1(torch, repeats, seeds):
@@ -634,7 +719,7 @@ def main():
               f"package is single-GPU by design", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
+    import numpy as np
     import torch
 
     import workloads as W
@@ -700,37 +785,48 @@ def main():
                     launches=dom["launches"], bytes_per_launch_avg=bpl)
 
     # ---- JVP bandwidth: AD vs FD -------------------------------------------
+    # "-hbm" rows rotate over >= 1 GiB of distinct operands (the HBM figures);
+    # the plain rows re-use one operand set, which the 256 MB last-level cache
+    # then largely serves (labelled context, not HBM bandwidth).
     jvp = {}
     for pr in (() if args.no_jvp_rows else ("f32", "f64")):
         sj = s if pr == prec else make_solver(spec, pr, xp, torch)
         for mode in ("ad", "fd"):
-            jvp[f"{pr}-{mode}"] = jvp_bandwidth(sj, torch, n, pr, mode)
-            log(f"[bench] jvp {pr}-{mode}: {jvp[f'{pr}-{mode}']}")
+            jvp[f"{pr}-{mode}-hot"] = jvp_bandwidth(sj, torch, n, pr, mode)
+            jvp[f"{pr}-{mode}-hbm"] = jvp_bandwidth_hbm(torch, spec, xp, None, pr, mode)
+            log(f"[bench] jvp {pr}-{mode}: hbm {jvp[f'{pr}-{mode}-hbm']} hot {jvp[f'{pr}-{mode}-hot']}")
         if sj is not s:
             sj.close()
 
-    # ---- JVP bandwidth at the 2D Burgers 2048^2 shape (100-134 MB per call), hot and cold
+    # ---- JVP bandwidth at the 2D Burgers 2048^2 shape (100-134 MB per call)
     jvp2048 = {}
     spec_b, xp_b, _ = W.config("burgers2d", seed=0)
     n_b = W.n_unknowns(spec_b)
-    scrub = torch.zeros(128 << 20, dtype=torch.float32, device="cuda")  # 512 MB
     for pr in (() if args.no_jvp_rows else ("f32", "f64")):
         sb = make_solver(spec_b, pr, xp_b, torch)
         for mode in ("ad", "fd"):
-            jvp2048[f"{pr}-{mode}"] = jvp_bandwidth(sb, torch, n_b, pr, mode, reps=100)
-            jvp2048[f"{pr}-{mode}-cold"] = jvp_bandwidth(sb, torch, n_b, pr, mode, reps=50, scrub=scrub)
-            log(f"[bench] jvp 2048^2 {pr}-{mode}: {jvp2048[f'{pr}-{mode}']} cold {jvp2048[f'{pr}-{mode}-cold']}")
+            jvp2048[f"{pr}-{mode}-hot"] = jvp_bandwidth(sb, torch, n_b, pr, mode, reps=100)
+            jvp2048[f"{pr}-{mode}-hbm"] = jvp_bandwidth_hbm(torch, spec_b, xp_b, None, pr, mode)
+            log(f"[bench] jvp 2048^2 {pr}-{mode}: hbm {jvp2048[f'{pr}-{mode}-hbm']}")
         sb.close()
-    del scrub
 
     # ---- JVP bandwidth on the Helmholtz-Kerr 1024^2 grid (complex64 / complex128)
     jvpkerr = {}
     for pr in (() if args.no_jvp_rows else ("f32", "f64")):
         sk, spec_k = kerr_solver(torch, pr)
+        src_k = W.kerr_gaussian_source(1024)
         for mode in ("ad", "fd"):
-            jvpkerr[f"{pr}-{mode}"] = jvp_bandwidth(sk, torch, W.n_unknowns(spec_k), pr, mode)
-            log(f"[bench] jvp kerr 1024^2 {pr}-{mode}: {jvpkerr[f'{pr}-{mode}']}")
+            jvpkerr[f"{pr}-{mode}-hot"] = jvp_bandwidth(sk, torch, W.n_unknowns(spec_k), pr, mode)
+            jvpkerr[f"{pr}-{mode}-hbm"] = jvp_bandwidth_hbm(torch, spec_k, np.zeros(W.n_unknowns(spec_k)), src_k,
+                                                            pr, mode)
+            log(f"[bench] jvp kerr 1024^2 {pr}-{mode}: hbm {jvpkerr[f'{pr}-{mode}-hbm']}")
         sk.close()
+
+    # ---- plain-copy reference at the vector sizes of those rows -------------
+    copy_ref = {}
+    for mb in (() if args.no_jvp_rows else (8, 16, 32, 64)):
+        copy_ref[f"{mb}MiB"] = copy_ceiling_hbm(torch, mb << 20)
+        log(f"[bench] copy reference {mb} MiB: {copy_ref[f'{mb}MiB']}")
 
     # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
     variants = {}
@@ -750,11 +846,25 @@ def main():
                     t_all += el
                     lat_v += l1
                     cnt += 1
+                # one more solve with HIP events on every kernel: the Arnoldi kernels of this
+                # variant (for FP16 storage, the JVP whose tangent and projection basis are FP16)
+                sv.profile_reset()
+                sv.profile(True)
+                run_solves(sv, x0, torch, 1, o)
+                kst = sv.profile_read()
+                sv.profile(False)
+                sv.profile_reset()
+                vk = {k: dict(launches=v["launches"], avg_us=round(v["ms"] * 1e3 / max(1, v["launches"]), 3),
+                              gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0.0,
+                              frac=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if v["ms"] > 0 else 0.0)
+                      for k, v in kst.items() if v["launches"] and k in ("jvp_ad", "jvp_fd", "dcgs_update", "cgs_b",
+                                                                          "cgs_c", "vy")}
                 variants[f"{pr}-{mode}"] = dict(solves_per_s=round(cnt / t_all, 3), solves=cnt,
                                                 p50_ms=round(1e3 * percentile(lat_v, 0.5), 3),
                                                 p99_ms=round(1e3 * percentile(lat_v, 0.99), 3),
                                                 newton_iters=inf["newton_iters"], krylov_iters=inf["krylov_iters"],
-                                                converged=inf["converged"], final_rel_res=inf["rel_res"][-1])
+                                                converged=inf["converged"], final_rel_res=inf["rel_res"][-1],
+                                                kernels=vk)
                 log(f"[bench] variant {pr}-{mode}: {variants[f'{pr}-{mode}']}")
             if sv is not s:
                 sv.close()
@@ -836,6 +946,7 @@ def main():
         "jvp": jvp,
         "jvp_burgers2d_2048": jvp2048,
         "jvp_kerr_1024": jvpkerr,
+        "copy_reference_hbm": copy_ref,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
         "bicgstab_newton": bicg,

@@ -115,6 +115,28 @@ __device__ __forceinline__ void load_nodes_nt(const S* __restrict__ base, long l
   }
 }
 
+// The pointwise term b of the RC centre rows starting at r0 (zero when not used).
+template <class P, class T, int VEC, int RC>
+__device__ __forceinline__ void load_b_rows(const T* __restrict__ b, long long plane, int nx, int ny, int r0, int cc,
+                                            bool use, T (&bv)[RC][P::NF][VEC]) {
+#pragma unroll
+  for (int tt = 0; tt < RC; ++tt) {
+    T t[P::NF][VEC];
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) t[f][e] = T(0);
+    if (use) {
+      const int r = r0 + tt;
+      load_nodes<P, T, VEC>(b, plane, nx, P::kDim2 ? (r < ny ? r : 0) : 0, cc, t);
+    }
+#pragma unroll
+    for (int f = 0; f < P::NF; ++f)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) bv[tt][f][e] = t[f][e];
+  }
+}
+
 template <class P, class S>
 __device__ __forceinline__ S load_node(const S* __restrict__ base, long long plane, int nx, int r, int c, int f) {
   if constexpr (P::kInterleaved) return base[2 * ((long long)r * nx + c) + f];
@@ -308,6 +330,66 @@ __global__ void __launch_bounds__(256) cslp_apply_kernel(const T* __restrict__ x
   }
 }
 
+// First CGS projection of an Arnoldi JVP's outputs on the stored basis:
+// acc[q] += V_q . o over the R rows `rows` (column cc) of this thread, for
+// q < a.K.  The rows of G basis vectors are loaded together before any is
+// used (G chosen for about 256 bytes in flight per lane; a load-use pair per
+// vector and row would leave the pass waiting on one memory round trip after
+// another).  Slots of the last group beyond K reload vector K-1 and their
+// products are discarded.
+template <class P, class T, class VT, int VEC, int R, int G, int KDOT>
+__device__ __forceinline__ void project_rows(const StencilArgs<T, VT>& a, int nx, int cc, const int (&rows)[R],
+                                             const T (&o)[R][P::NF][VEC], double (&acc)[KDOT + 1]) {
+  constexpr int NF = P::NF;
+#pragma unroll
+  for (int q0 = 0; q0 < KDOT; q0 += G) {
+    if (q0 < a.K) {
+      VT vq[G][R][NF][VEC];
+      if (a.nt_basis) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+#pragma unroll
+          for (int tt = 0; tt < R; ++tt)
+            load_nodes_nt<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+#pragma unroll
+          for (int tt = 0; tt < R; ++tt)
+            load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        double sum;
+        if constexpr (sizeof(T) == 4) {
+          // FP32 sum over the thread's chunk, FP64 across chunks (as in the update pass)
+          T p = T(0);
+#pragma unroll
+          for (int tt = 0; tt < R; ++tt)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[u][tt][f][e]), o[tt][f][e], p);
+          sum = (double)p;
+        } else {
+          sum = 0.0;
+#pragma unroll
+          for (int tt = 0; tt < R; ++tt)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) sum += (double)to_c<T>(vq[u][tt][f][e]) * (double)o[tt][f][e];
+        }
+        acc[q0 + u] += q0 + u < a.K ? sum : 0.0;
+      }
+    }
+  }
+}
+
 // Persistent launch: the grid holds at most a bounded number of blocks and
 // each block walks a contiguous range of tiles (vertically adjacent row
 // bands, so the halo rows of one tile are still in cache for the next).  A
@@ -346,39 +428,26 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   // the tile so that its latency overlaps the exchange; the AD tangent alone
   // does not involve it
   constexpr bool kNeedB = OP != OP_AD || WITHF;
-  T bval[RC][NF][VEC];
-  const bool use_b = a.b != nullptr;
-  auto load_b = [&](int cc) {
-#pragma unroll
-    for (int tt = 0; tt < RC; ++tt) {
-      const int r = r0 + tt;
-      const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
-      if (kNeedB && use_b) {
-        load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, bval[tt]);
-      } else {
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) bval[tt][f][e] = T(0);
-      }
-    }
-  };
+  // early only while the rows fit 64 bytes per lane (operators with four
+  // fields and corner halos load them row by row, as their registers are full)
+  constexpr bool kEarlyB = RC * NF * VEC * (int)sizeof(T) <= 64;
+  T bval[kEarlyB ? RC : 1][NF][VEC];
+  const bool use_b = kNeedB && a.b != nullptr;
   // Arnoldi JVP of the delayed form: the loads of the column completion in
   // the prologue go out first, then the first tile's (in-bounds either way;
   // unused if the cycle has stopped), so that the two sets of round trips
   // overlap (vector loads complete in order: issued after the tile, the
   // prologue's loads would wait for all of it).
   LaggedPrefetch lpf;
-  const bool lag_pre = OP != OP_RES && a.ctl != nullptr && a.lagged && a.arn_j > 0;
-  if constexpr (OP != OP_RES) {
-    if (lag_pre) lagged_prefetch(a.ctl, a.arn_j - 1, a.pc, lpf);
+  if constexpr (OP != OP_RES && KDOT > 0) {
+    if (a.ctl != nullptr && a.lagged && a.arn_j > 0) lagged_prefetch(a.ctl, a.arn_j - 1, a.pc, lpf);
   }
   if (t_begin < t_end) {
     tile_origin(t_begin, col0, r0);
     const int cc = col0 < nx ? col0 : 0;
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
-    load_b(cc);
+    if constexpr (kEarlyB) load_b_rows<P, T, VEC, RC>(a.b, a.plane, nx, ny, r0, cc, use_b, bval);
   }
 
   // Arnoldi mode: leave at once if the cycle has already stopped
@@ -417,8 +486,13 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         vscale = a.ctl->scale[0];
       } else {
         __shared__ double gcol[kMaxM + 1];
-        const GivensOut g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
-                                     : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
+        GivensOut g;
+        if constexpr (KDOT > 0)
+          g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
+                       : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
+        else  // Arnoldi mode always fuses the projection; kept for completeness
+          g = a.lagged ? finish_column_lagged(a.ctl, j - 1, a.pc, a.host_flags, gcol)
+                       : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
         if (g.done != kRunning) return;  // uniform: every block computed the same update
         vscale = g.vs;
       }
@@ -449,13 +523,16 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
 
-  // Arnoldi JVP: the outputs of the thread's rows, kept for the projection
-  // on the basis, and the number of basis vectors whose loads go out together
-  constexpr int kProjBytes = RC * NF * VEC * (int)sizeof(VT);
+  // Arnoldi JVP: the projection on the basis covers all of the thread's rows
+  // at once when their outputs fit 64 bytes per lane (kept in po), else it
+  // runs row by row; kProjGroup basis vectors' loads go out together
+  constexpr bool kProjAll = RC * NF * VEC * (int)sizeof(T) <= 64;
+  constexpr int PR = kProjAll ? RC : 1;
+  constexpr int kProjBytes = PR * NF * VEC * (int)sizeof(VT);
   constexpr int kProjGroup0 = 256 / kProjBytes < 1 ? 1 : (256 / kProjBytes > 8 ? 8 : 256 / kProjBytes);
   constexpr int kProjGroup = KDOT > 0 && kProjGroup0 > KDOT ? KDOT : kProjGroup0;
-  T po[KDOT > 0 ? RC : 1][NF][VEC];
-  int prow[KDOT > 0 ? RC : 1];
+  T po[KDOT > 0 ? PR : 1][NF][VEC];
+  int prow[KDOT > 0 ? PR : 1];
 
   // one tile whose loads have been issued (X, Vt at col0, r0)
   auto process = [&]() {
@@ -476,6 +553,19 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       const int r = r0 + tt;
       const bool ok = colok && (!P::kDim2 || r < ny);
       const int rr = P::kDim2 ? (r < ny ? r : 0) : 0;
+      T brow[NF][VEC];
+      if constexpr (kEarlyB) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) brow[f][e] = bval[tt][f][e];
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) brow[f][e] = T(0);
+        if (use_b) load_nodes<P, T, VEC>(a.b, a.plane, nx, rr, cc, brow);
+      }
       T o[NF][VEC];
       T o2[NF][VEC];
 #pragma unroll
@@ -488,7 +578,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           P::template N<T, T>(k, xn, n);
 #pragma unroll
           for (int f = 0; f < NF; ++f)
-            o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * bval[tt][f][e];
+            o[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f]) + beta * brow[f][e];
         } else if constexpr (OP == OP_AD) {
           Nbr<T> vn[NF];
           Vt.nbr(tt, e, vn);
@@ -500,7 +590,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
             o[f][e] = bnd ? vn[f].c : alpha * vn[f].c + cN * n[f].t;
-            o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * bval[tt][f][e];
+            o2[f][e] = bnd ? xn[f].c : (alpha * xn[f].c + cN * n[f].v) + beta * brow[f][e];
           }
         } else {
           Nbr<T> vn[NF];
@@ -513,8 +603,8 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           P::template N<T, T>(k, yn, n1);
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
-            const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * bval[tt][f][e];
-            const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * bval[tt][f][e];
+            const T f0 = bnd ? xn[f].c : (alpha * xn[f].c + cN * n0[f]) + beta * brow[f][e];
+            const T f1 = bnd ? yn[f].c : (alpha * yn[f].c + cN * n1[f]) + beta * brow[f][e];
             o[f][e] = (f1 - f0) * inv_eps;
           }
         }
@@ -544,69 +634,18 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         }
       }
       if constexpr (OP != OP_RES && KDOT > 0) {
-        // keep the row (zero outside the grid) for the projection below
-        prow[tt] = rr;
+        // keep the row (zero outside the grid) for the projection
+        const int pt = kProjAll ? tt : 0;
+        prow[pt] = rr;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) po[tt][f][e] = ok ? o[f][e] : T(0);
+          for (int e = 0; e < VEC; ++e) po[pt][f][e] = ok ? o[f][e] : T(0);
+        if constexpr (!kProjAll) project_rows<P, T, VT, VEC, 1, kProjGroup, KDOT>(a, nx, cc, prow, po, acc);
       }
     }
-    if constexpr (OP != OP_RES && KDOT > 0) {
-      // First CGS projection of the new vector on the stored basis, over all
-      // of the thread's rows at once.  The rows of G basis vectors are loaded
-      // together before any is used (about 256 bytes in flight per lane; a
-      // load-use pair per vector and row would leave the pass waiting on one
-      // memory round trip after another).  Slots of the last group beyond K
-      // reload vector K-1 and their products are discarded.
-#pragma unroll
-      for (int q0 = 0; q0 < KDOT; q0 += kProjGroup) {
-        if (q0 < a.K) {
-          VT vq[kProjGroup][RC][NF][VEC];
-          if (a.nt_basis) {
-#pragma unroll
-            for (int u = 0; u < kProjGroup; ++u) {
-              const int q = q0 + u < a.K ? q0 + u : a.K - 1;
-#pragma unroll
-              for (int tt = 0; tt < RC; ++tt)
-                load_nodes_nt<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, prow[tt], pcc, vq[u][tt]);
-            }
-          } else {
-#pragma unroll
-            for (int u = 0; u < kProjGroup; ++u) {
-              const int q = q0 + u < a.K ? q0 + u : a.K - 1;
-#pragma unroll
-              for (int tt = 0; tt < RC; ++tt)
-                load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, prow[tt], pcc, vq[u][tt]);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < kProjGroup; ++u) {
-            double s;
-            if constexpr (sizeof(T) == 4) {
-              // FP32 sum over the thread's chunk, FP64 across chunks (as in the update pass)
-              T p = T(0);
-#pragma unroll
-              for (int tt = 0; tt < RC; ++tt)
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                  for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[u][tt][f][e]), po[tt][f][e], p);
-              s = (double)p;
-            } else {
-              s = 0.0;
-#pragma unroll
-              for (int tt = 0; tt < RC; ++tt)
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                  for (int e = 0; e < VEC; ++e) s += (double)to_c<T>(vq[u][tt][f][e]) * (double)po[tt][f][e];
-            }
-            acc[q0 + u] += q0 + u < a.K ? s : 0.0;
-          }
-        }
-      }
-    }
+    if constexpr (OP != OP_RES && KDOT > 0 && kProjAll)
+      project_rows<P, T, VT, VEC, RC, kProjGroup, KDOT>(a, nx, pcc, prow, po, acc);
   };
 
   if (t_begin < t_end) process();
@@ -615,7 +654,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     const int cc = col0 < nx ? col0 : 0;
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
-    load_b(cc);
+    if constexpr (kEarlyB) load_b_rows<P, T, VEC, RC>(a.b, a.plane, nx, ny, r0, cc, use_b, bval);
     process();
   }
 

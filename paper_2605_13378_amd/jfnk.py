@@ -273,10 +273,10 @@ class Solver:
         self._check(lib().jfnk_residual(self._h, x.data_ptr(), out.data_ptr()))
         return out
 
-    def jvp(self, x, v, mode="ad", eps=0.0, eps_rule="paper", want_F=False):
+    def jvp(self, x, v, mode="ad", eps=0.0, eps_rule="paper", want_F=False, out=None):
         x = self._vec(x, self.wdtype, "x")
         v = self._vec(v, self.wdtype, "v")
-        jv = self._new()
+        jv = self._new() if out is None else self._vec(out, self.wdtype, "out")
         F = self._new() if (want_F and mode == "ad") else None
         self._check(lib().jfnk_jvp(self._h, x.data_ptr(), v.data_ptr(), jv.data_ptr(),
                                    None if F is None else F.data_ptr(), MODES[mode], float(eps),
