@@ -70,7 +70,7 @@ __device__ inline void givens_gather(const Ctl* __restrict__ ctl, int j, GivensI
 // Called by the threads of the first wavefront (tid < 64); `any_bad` is their
 // vote on a non-finite entry of in.h.  The rotated entry is carried in a
 // register from one rotation to the next, with the rotation inputs read from
-// LDS eight at a time ahead of the arithmetic, so the chain costs FP64
+// LDS four at a time ahead of the arithmetic, so the chain costs FP64
 // latency only (a column kept in LDS costs an LDS round trip per rotation).
 __device__ inline void givens_column(const GivensIn& in, int j, double wn2, bool any_bad, double* col,
                                      GivensOut& out) {
@@ -79,17 +79,17 @@ __device__ inline void givens_column(const GivensIn& in, int j, double wn2, bool
   o.wn = sqrt(wn2);
   o.vs = 1.0 / (o.wn * in.sig);
   double a = in.h[0];
-  for (int i0 = 0; i0 < j; i0 += 8) {
-    double hb[8], cb[8], sb[8];
+  for (int i0 = 0; i0 < j; i0 += 4) {
+    double hb[4], cb[4], sb[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const int i = i0 + u < kMaxM ? i0 + u : kMaxM - 1;  // in bounds; slots past j unused
       hb[u] = in.h[i + 1];
       cb[u] = in.cs[i];
       sb[u] = in.sn[i];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       if (i0 + u < j) {
         const double b = hb[u];
         col[i0 + u] = cb[u] * a + sb[u] * b;

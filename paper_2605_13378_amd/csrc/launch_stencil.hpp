@@ -16,8 +16,10 @@ static hipError_t stencil_kdot(const StencilArgs<T, VT>& a, const Coefs& c, dim3
     if (a.Vb != nullptr) return hipErrorInvalidValue;
     JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
   } else {
-    if (a.Vb == nullptr)
+    if (a.Vb == nullptr) {
+      if (a.ctl != nullptr) return hipErrorInvalidValue;  // Arnoldi mode always fuses the projection
       JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 0>), grid, block, s, a, c);
+    }
     else if (a.K <= 4)
       JFNK_LAUNCH((stencil_kernel<P, T, VT, VEC, RY, OP, false, 4>), grid, block, s, a, c);
     else if (a.K <= 8)

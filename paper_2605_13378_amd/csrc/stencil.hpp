@@ -42,9 +42,10 @@ struct StencilArgs {
   double alpha, cN, beta;
   const double* vscale;  // device scalar, nullable -> 1
   EpsSpec eps;
-  // Arnoldi JVP of step arn_j (ctl non-null): finishes the Givens update of
-  // column arn_j - 1 from pass C's partials `pc`, stops early once the cycle
-  // is done, and takes the basis scale from that update.
+  // Arnoldi JVP of step arn_j (ctl non-null, with the fused projection: Vb
+  // set): finishes the Givens update of column arn_j - 1 from pass C's
+  // partials `pc`, stops early once the cycle is done, and takes the basis
+  // scale from that update.
   Ctl* ctl;
   int arn_j;
   int lagged;            // delayed-second-pass Arnoldi: pc holds the update pass's sums
@@ -450,8 +451,9 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     if constexpr (kEarlyB) load_b_rows<P, T, VEC, RC>(a.b, a.plane, nx, ny, r0, cc, use_b, bval);
   }
 
-  // Arnoldi mode: leave at once if the cycle has already stopped
-  if constexpr (OP != OP_RES) {
+  // Arnoldi mode (only instances with the fused projection, KDOT > 0): leave
+  // at once if the cycle has already stopped
+  if constexpr (OP != OP_RES && KDOT > 0) {
     if (a.ctl != nullptr) {
       const int j = a.arn_j;
       const int prev = a.ctl->done_col[j > 0 ? j - 1 : 0];
@@ -480,25 +482,23 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 
   double vscale = 1.0;
   if constexpr (OP != OP_RES) {
-    if (a.ctl != nullptr) {
-      const int j = a.arn_j;
-      if (j == 0) {
-        vscale = a.ctl->scale[0];
-      } else {
-        __shared__ double gcol[kMaxM + 1];
-        GivensOut g;
-        if constexpr (KDOT > 0)
-          g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
-                       : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
-        else  // Arnoldi mode always fuses the projection; kept for completeness
-          g = a.lagged ? finish_column_lagged(a.ctl, j - 1, a.pc, a.host_flags, gcol)
-                       : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
-        if (g.done != kRunning) return;  // uniform: every block computed the same update
-        vscale = g.vs;
+    bool arnoldi = false;
+    if constexpr (KDOT > 0) {
+      if (a.ctl != nullptr) {
+        arnoldi = true;
+        const int j = a.arn_j;
+        if (j == 0) {
+          vscale = a.ctl->scale[0];
+        } else {
+          __shared__ double gcol[kMaxM + 1];
+          const GivensOut g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
+                                       : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
+          if (g.done != kRunning) return;  // uniform: every block computed the same update
+          vscale = g.vs;
+        }
       }
-    } else if (a.vscale != nullptr) {
-      vscale = *a.vscale;
     }
+    if (!arnoldi && a.vscale != nullptr) vscale = *a.vscale;
   }
   double eps = 0.0;
   T eps_s = T(0);
