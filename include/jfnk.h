@@ -224,10 +224,15 @@ jfnk_status jfnk_set_previous(jfnk_solver* s, const double* x_prev, const double
 /* F = F(x; x*) in the working precision (paper, Section 2). */
 jfnk_status jfnk_residual(jfnk_solver* s, const void* x, void* F);
 
-/* Jv = J(x) v.  mode AD: fused dual-number pass; if F_or_null is given it
+/* Jv = J(x) v (paper, Section 2: the JVP by forward-mode AD or by finite
+ * differences).  mode AD: fused dual-number pass; if F_or_null is given it
  * also receives F(x).  mode FD: (F(x + eps v) - F(x)) / eps with both
  * residuals evaluated in one pass; eps > 0 is used as given, eps <= 0 takes
- * eps_rule (jfnk_eps_rule) with norms computed on the device. */
+ * eps_rule (jfnk_eps_rule) with norms computed on the device.  On a
+ * JFNK_F16S solver the tangent is stored in FP16 first, as Krylov vectors
+ * are: v times the power of two sigma that maps ||v|| / sqrt(n) near 1,
+ * rounded to nearest, read back divided by sigma (the normalized FD rule
+ * takes ||v|| of the FP32 v). */
 jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, void* F_or_null,
                      int mode, double eps, int eps_rule);
 

@@ -352,7 +352,7 @@ struct Ctl {
   double jvn2;       // ||J v_j||^2 of the current step (pass A, written by pass B)
   double fnorm2;     // ||F||^2 of the latest residual evaluation
   double xnorm2;     // ||x||^2 of the latest residual evaluation (must follow fnorm2)
-  double dxnorm2;    // spare norm slot
+  double dxnorm2;    // 1 / (FP16 storage scale) of a standalone JVP tangent (FP16S solvers)
   double aux2;       // ||v||^2 for standalone FD JVP calls
   double gp[kMaxM + 1];              // g entry j before rotation j (gp[0] = beta)
   double gr[kMaxM];                  // g entry j after rotation j

@@ -11,6 +11,12 @@ hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream
   return hipGetLastError();
 }
 
+hipError_t launch_fp16_tangent(long long n, const float* v, __half* out, const double* vn2, double* inv_sigma,
+                               int grid, hipStream_t s) {
+  JFNK_LAUNCH(fp16_tangent_kernel<0>, dim3(grid), dim3(kStreamThreads), s, n, v, out, vn2, inv_sigma);
+  return hipGetLastError();
+}
+
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s) {
   JFNK_LAUNCH(cycle_begin_kernel<0>, dim3(1), dim3(kStreamThreads), s, c, in, m, n, fp16);
   return hipGetLastError();

@@ -639,6 +639,22 @@ __global__ void __launch_bounds__(256) cycle_begin_kernel(Ctl* ctl, Partials in,
   if (threadIdx.x >= 1 && threadIdx.x <= m) ctl->done_col[threadIdx.x] = kRunning;
 }
 
+// FP16 storage of a caller's tangent (standalone JVP of an FP16S solver):
+// sigma = fp16_scale(||v||) from the FP64 norm at *vn2, out = half(v sigma)
+// (n entries, any alignment) and *inv_sigma = 1 / sigma, the scale the JVP
+// folds back in.
+template <int kUnused = 0>
+__global__ void __launch_bounds__(256) fp16_tangent_kernel(long long n, const float* __restrict__ v,
+                                                           __half* __restrict__ out, const double* vn2,
+                                                           double* inv_sigma) {
+  const double sig = fp16_scale(sqrt(*vn2), n);
+  const float sf = (float)sig;
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+    out[i] = __float2half_rn(v[i] * sf);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *inv_sigma = 1.0 / sig;
+}
+
 // FP16 storage of the first basis vector: V_0 = half(r * vsig[0]).
 template <class T, class VT, int VEC>
 __global__ void __launch_bounds__(256) store_basis0_kernel(long long n, const T* __restrict__ r, VT* __restrict__ V0,

@@ -202,6 +202,9 @@ template <class T>
 hipError_t launch_cg(int kind, const CgArgs<T>& a, double tol, int grid, hipStream_t s);
 
 hipError_t launch_ctl_begin(Ctl* c, double tol, double brk_tol, int m, hipStream_t s);
+// out = half(v sigma), sigma = fp16_scale(sqrt(*vn2)), *inv_sigma = 1 / sigma.
+hipError_t launch_fp16_tangent(long long n, const float* v, __half* out, const double* vn2, double* inv_sigma,
+                               int grid, hipStream_t s);
 hipError_t launch_cycle_begin(Ctl* c, Partials in, int m, long long n, int fp16, hipStream_t s);
 hipError_t launch_finish_sums(Partials in, int nr, double* out0, double* out1, hipStream_t s);
 // Copies the first `words` 32-bit words of the control block to mapped host

@@ -1109,6 +1109,20 @@ jfnk_status device_norm2(jfnk_solver* s, const T* p, double* out) {
   return JFNK_OK;
 }
 
+// Standalone JVP of an FP16S solver: the tangent is stored in FP16 with a
+// power-of-two scale first (basis slot 0 holds it), as Krylov vectors are,
+// and the JVP reads it from there.
+jfnk_status jvp_api_f16s(jfnk_solver* s, const float* x, const float* v, float* Jv, float* F, int mode, double eps,
+                         int rule) {
+  EpsSpec e = eps_spec(s, eps, rule, &s->ctl->aux2);
+  JFNK_TRY(device_norm2<float>(s, v, &s->ctl->aux2));
+  if (mode == JFNK_JVP_FD && !(eps > 0.0)) JFNK_TRY(device_norm2<float>(s, x, &s->ctl->xnorm2));
+  __half* vh = static_cast<__half*>(s->V);
+  JFNK_HIP(s, launch_fp16_tangent(s->n, v, vh, &s->ctl->aux2, &s->ctl->dxnorm2, stream_grid(s, 1), s->stream));
+  return Impl<float, __half>::template jvp<__half>(s, x, vh, &s->ctl->dxnorm2, Jv, mode == JFNK_JVP_AD ? F : nullptr,
+                                                   mode, e);
+}
+
 template <class T>
 jfnk_status jvp_api(jfnk_solver* s, const T* x, const T* v, T* Jv, T* F, int mode, double eps, int rule) {
   EpsSpec e = eps_spec(s, eps, rule, &s->ctl->aux2);
@@ -1537,6 +1551,8 @@ jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, voi
   if (s->prec == JFNK_F64)
     return jvp_api<double>(s, (const double*)x, (const double*)v, (double*)Jv, (double*)F_or_null, mode, eps,
                            eps_rule);
+  if (s->prec == JFNK_F16S)
+    return jvp_api_f16s(s, (const float*)x, (const float*)v, (float*)Jv, (float*)F_or_null, mode, eps, eps_rule);
   return jvp_api<float>(s, (const float*)x, (const float*)v, (float*)Jv, (float*)F_or_null, mode, eps, eps_rule);
 }
 

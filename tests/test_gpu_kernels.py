@@ -108,6 +108,49 @@ def test_fd_jvp_parity(kind, nx, ny, prec, rule):
     assert float(np.abs(got - ref).max()) <= bound + TOL[prec] * max(1.0, float(np.abs(ref).max()))
 
 
+def fp16_stored(v, n):
+    """The tangent as an FP16S solver stores it: v (FP32) times the power of two sigma that
+    maps a typical entry ||v|| / sqrt(n) near 1, rounded to FP16 (nearest even), divided by
+    sigma again (exact).  Computed here from that rule, independently of the kernels."""
+    v32 = np.asarray(v, dtype=np.float32)
+    nrm = float(np.sqrt(np.sum(v32.astype(np.float64) ** 2)))
+    sig = 2.0 ** (-np.rint(np.log2(nrm / np.sqrt(n))))
+    return (v32 * np.float32(sig)).astype(np.float16).astype(np.float64) / sig
+
+
+@pytest.mark.parametrize("mode", ["ad", "fd"])
+@pytest.mark.parametrize("kind,nx,ny", [("grayscott", 130, 37), ("burgers2d", 48, 40), ("kerr", 40, 24),
+                                        ("burgers1d", 1000, None), ("maxwell", 64, 64), ("grayscott", 1024, 1024)])
+def test_f16s_jvp_parity(kind, nx, ny, mode):
+    """FP16-storage JVP (the tangent stored in FP16 with a power-of-two scale, FP32 arithmetic)
+    element by element against the oracle fed the same FP16-rounded tangent and FP32 state:
+    the FP32 bound for AD, the FD rounding bound for FD."""
+    spec, xp, src = case(kind, nx, ny) if nx < 1024 else W.config("grayscott")
+    p = Problem.from_spec(spec)
+    x, v = state_and_direction(spec, xp, 23)
+    x32 = x.astype(np.float32).astype(np.float64)
+    v16 = fp16_stored(v, p.n)
+    s = make_solver(spec, "f16s", xp, src)
+    if mode == "ad":
+        Fref, Jref = jvp_ad(p, x32, v16, xp, src)
+        jv, F = s.jvp(dev(x, wdtype("f32")), dev(v, wdtype("f32")), mode="ad", want_F=True)
+        assert rel_err(host(jv), Jref, v16) <= TOL["f32"]
+        assert elem_err(host(jv), Jref, local_scale(spec, Jref, v16)) <= TOL["f32"]
+        assert rel_err(host(F), Fref, x32) <= TOL["f32"]
+    else:
+        em = EPS_MACH["f32"]
+        eps = fd_step("paper", em, x32, v16)
+        ref = jvp_fd(p, x32, v16, eps, xp, src)
+        got = host(s.jvp(dev(x, wdtype("f32")), dev(v, wdtype("f32")), mode="fd", eps_rule="paper"))
+        S = max(1.0, float(np.abs(residual(p, x32, xp, src)).max()), float(np.abs(x32).max()))
+        bound = 32 * (em / 2) * S / eps * max(1.0, float(np.abs(v16).max()))
+        assert float(np.abs(got - ref).max()) <= bound + TOL["f32"] * max(1.0, float(np.abs(ref).max()))
+    # the FP16 rounding is really applied: the FP32 tangent's product differs beyond the bound
+    if mode == "ad" and kind == "grayscott" and nx < 1024:
+        J32 = jvp_ad(p, x32, v.astype(np.float32).astype(np.float64), xp, src)[1]
+        assert rel_err(J32, Jref, v16) > 10 * TOL["f32"]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_fixed_eps_fd(prec):
     spec, xp, src = case("grayscott", 64, 40)
