@@ -81,12 +81,36 @@ class NewtonInfo:
 
 
 def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=None,
-                 x0: np.ndarray | None = None, record: bool = False):
-    """Solve F(x; x*) = 0 starting from x0 (default x* = x_prev); returns (x, NewtonInfo)."""
+                 x0: np.ndarray | None = None, record: bool = False, perm: np.ndarray | None = None):
+    """Solve F(x; x*) = 0 starting from x0 (default x* = x_prev); returns (x, NewtonInfo).
+
+    ``perm`` (a permutation of the unknowns, test use) runs the same method on the
+    reordered system P F(P^T y) = 0: the Krylov solve sees P J P^T and -P F, and the merit
+    norms are taken over P F.  In exact arithmetic nothing changes; in floating point every
+    dot product and norm is summed in another order, which measures how much the iterates
+    depend on summation order alone."""
+    if perm is None:
+        def fwd(v):
+            return v
+
+        bwd = fwd
+    else:
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(len(perm))
+
+        def fwd(v):  # P v
+            return v[perm]
+
+        def bwd(y):  # P^T y
+            return y[inv]
+
+    def merit(F):
+        return float(np.linalg.norm(fwd(F)))
+
     x = (x_prev if x0 is None else x0).astype(np.float64).copy()
     info = NewtonInfo()
     F = residual(p, x, x_prev, source)
-    n0 = float(np.linalg.norm(F))
+    n0 = merit(F)
     info.f0_norm = n0
     fk = n0
     if record:
@@ -107,15 +131,19 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
             return x, info
 
         if opts.mode == "ad":
-            def matvec(v, _x=x):
+            def jv(v, _x=x):
                 return jvp_ad(p, _x, v, x_prev, source)[1]
         else:
             Fx = F
 
-            def matvec(v, _x=x, _F=Fx):
+            def jv(v, _x=x, _F=Fx):
                 eps = opts.fd_eps if opts.fd_eps > 0.0 else fd_step(opts.eps_rule, opts.eps_mach, _x, v)
                 return jvp_fd(p, _x, v, eps, x_prev, source, Fx=_F)
 
+        def matvec(y, _jv=jv):  # the Krylov solver's operator (P J P^T; J itself without perm)
+            return fwd(_jv(bwd(y)))
+
+        rhs = -fwd(F)
         if opts.precond == "cslp":
             # right preconditioning (Appendix A.4): GMRES on J M^{-1}, dx = M^{-1} z
             if opts.krylov != "gmres":
@@ -125,21 +153,24 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
                 return cslp_solve(p, _x, v)
 
             def pmatvec(z, _mv=matvec, _minv=minv):
-                return _mv(_minv(z))
+                return _mv(fwd(_minv(bwd(z))))
 
-            z, ginfo = gm.gmres(pmatvec, -F, m=opts.m, tol=opts.tol_krylov, max_restarts=opts.max_restarts,
+            z, ginfo = gm.gmres(pmatvec, rhs, m=opts.m, tol=opts.tol_krylov, max_restarts=opts.max_restarts,
                                 breakdown_tol=opts.breakdown_tol, orth=opts.orth)
-            dx = minv(z)
+            dx = minv(bwd(z))
             info.restarts += ginfo.cycles
         elif opts.precond != "none":
             raise ValueError(opts.precond)
         elif opts.krylov == "bicgstab":
-            dx, ginfo = bicgstab(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+            dy, ginfo = bicgstab(matvec, rhs, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+            dx = bwd(dy)
         elif opts.krylov == "cg":
-            dx, ginfo = cg(matvec, -F, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+            dy, ginfo = cg(matvec, rhs, tol=opts.tol_krylov, maxiter=opts.max_restarts)
+            dx = bwd(dy)
         else:
-            dx, ginfo = gm.gmres(matvec, -F, m=opts.m, tol=opts.tol_krylov,
+            dy, ginfo = gm.gmres(matvec, rhs, m=opts.m, tol=opts.tol_krylov,
                                  max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol, orth=opts.orth)
+            dx = bwd(dy)
             info.restarts += ginfo.cycles
         info.krylov_iters += ginfo.iters
         info.lin_iters.append(ginfo.iters)
@@ -152,7 +183,7 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
         for t in range(opts.ls_max_backtracks + 1):
             xt = x + alpha * dx
             Ft = residual(p, xt, x_prev, source)
-            ft = float(np.linalg.norm(Ft))
+            ft = merit(Ft)
             if math.isfinite(ft) and ft <= (1.0 - opts.ls_c * alpha) * fk:
                 accepted = True
                 break

@@ -130,10 +130,14 @@ def test_cslp_gmres_f16_storage():
 
 @pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
 def test_newton_maxwell_cslp_from_born(orth):
-    spec = W.maxwell_spec(16, omega=2.5)
-    src = W.maxwell_source(16, omega=2.5)
-    info, ref = compare_newton(spec, np.zeros(4 * 16 * 16), src, "f64", "ad", 1e-6, orth=orth, precond="cslp",
-                               krylov_slack=0.1, max_newton=20)
+    # bounds: FACTOR times the oracle's own summation-order spread on this case
+    # (order_spread "maxwell16_cslp"); the tiny-grid cases at the contract bound
+    # run in test_gpu_maxwell
+    import order_spread as OS
+
+    spec, xp, src, opts, _, _, _ = OS.case("maxwell16_cslp")
+    tol, tol_x = OS.gpu_bounds("maxwell16_cslp")
+    info, ref = compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, orth=orth, krylov_slack=0.1, **opts)
     assert info["converged"]
 
 

@@ -134,9 +134,12 @@ def test_newton_dcgs2(kind, nx, ny, prec, tol):
 
 
 def test_newton_dcgs2_kerr_f64():
-    spec = dict(W.kerr_spec(12, chi3=0.3, cells_per_wavelength=64.0, eps_im=0.05), ny=10)
-    src = W.kerr_gaussian_source(12, amp=1.0, sigma=2.0, ny=10)
-    compare_newton(spec, np.zeros(2 * 12 * 10), src, "f64", "ad", 1e-10, max_newton=20, orth="dcgs2")
+    # bounds from the oracle's own summation-order spread on this case (order_spread)
+    import order_spread as OS
+
+    spec, xp, src, opts, _, _, _ = OS.case("kerr12x10_cpw64_chi0.3")
+    tol, tol_x = OS.gpu_bounds("kerr12x10_cpw64_chi0.3")
+    compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, orth="dcgs2", **opts)
 
 
 @pytest.mark.parametrize("rule", ["paper", "normalized"])

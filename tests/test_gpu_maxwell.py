@@ -43,8 +43,30 @@ def test_maxwell_guard_born_operator(prec, tol):
 
 @pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
 def test_newton_maxwell_from_born(orth):
-    spec = W.maxwell_spec(16, omega=2.5)
-    src = W.maxwell_source(16, omega=2.5)
-    info, ref = compare_newton(spec, np.zeros(4 * 16 * 16), src, "f64", "ad", 1e-6, orth=orth, krylov_slack=0.1,
-                               max_newton=20)
+    # bounds: FACTOR times the oracle's own summation-order spread on this case
+    # (order_spread "maxwell16": rho 1e-9, x 2e-8 measured, ceilings 2e-9 / 4e-8)
+    import order_spread as OS
+
+    spec, xp, src, opts, _, _, _ = OS.case("maxwell16")
+    tol, tol_x = OS.gpu_bounds("maxwell16")
+    info, ref = compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, orth=orth, krylov_slack=0.1, **opts)
+    assert info["converged"]
+
+
+@pytest.mark.parametrize("pre", ["none", "cslp"])
+@pytest.mark.parametrize("n", [4, 6])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_newton_maxwell_tiny_grid_at_contract_bound(n, pre, prec, tol):
+    """On 4 x 4 and 6 x 6 node grids GMRES reaches a 1e-13 Krylov tolerance in a few dozen
+    steps and the oracle's iterates are independent of summation order to 1e-13
+    (test_oracle_summation_order): every Newton iterate at the contract bound, FP64 and FP32,
+    with and without the CSLP preconditioner."""
+    spec = W.maxwell_spec(n, omega=2.5)
+    src = W.maxwell_source(n, omega=2.5)
+    kw = dict(tol_krylov=1e-13, tol_newton=1e-10) if prec == "f64" else dict(tol_krylov=1e-6)
+    # at a 1e-13 Krylov tolerance the stopping step of a solve moves with summation order
+    # (the oracle against itself: up to 11 steps of ~60 on 6 x 6; plain CGS2 against the
+    # delayed form: 11 of 45), the iterates do not
+    info, ref = compare_newton(spec, np.zeros(4 * n * n), src, prec, "ad", tol, precond=pre, orth="dcgs2",
+                               max_newton=20, krylov_slack=0.3, **kw)
     assert info["converged"]

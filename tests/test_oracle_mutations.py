@@ -302,9 +302,9 @@ def test_cslp_mistakes_fail_a_pin(monkeypatch, old, new, pin):
 
 def test_cslp_update_left_in_the_preconditioned_space(monkeypatch):
     src = inspect.getsource(onewton.newton_solve)
-    assert "dx = minv(z)" in src
+    assert "dx = minv(bwd(z))" in src
     ns = dict(vars(onewton))
-    exec(compile(src.replace("dx = minv(z)", "dx = z", 1), "newton_mutant", "exec"), ns)
+    exec(compile(src.replace("dx = minv(bwd(z))", "dx = bwd(z)", 1), "newton_mutant", "exec"), ns)
     monkeypatch.setattr(tcs, "newton_solve", ns["newton_solve"])
     _expect_failure(tcs.test_newton_with_cslp_reaches_the_same_field)
 
