@@ -156,9 +156,11 @@ typedef enum { JFNK_PRECOND_NONE = 0, JFNK_PRECOND_CSLP = 1 } jfnk_precond;
  *          ||u||^2 - ||V^T u||^2, the next JVP is applied to the once-
  *          projected vector and corrected through the Arnoldi relation):
  *          two passes over the basis per step.  Same basis and Hessenberg
- *          matrix in exact arithmetic.  FP64 and FP32 only (FP16 storage
- *          keeps CGS2); the SINGLE_WORKGROUP engine always runs CGS2.
- * The defaults are DCGS2 in FP64 and FP32 and CGS2 with FP16 storage. */
+ *          matrix in exact arithmetic.  With FP16 storage (F16S) the
+ *          pending and the completed vector are each rounded to FP16 as they
+ *          are written, and the second pass and the norms are taken over the
+ *          stored values.  The SINGLE_WORKGROUP engine always runs CGS2.
+ * The default is DCGS2 in every precision. */
 typedef enum { JFNK_ORTH_CGS2 = 0, JFNK_ORTH_DCGS2 = 1 } jfnk_orth;
 
 /* The Krylov method of each Newton step (paper, Section 2: GMRES(m) or
@@ -238,7 +240,7 @@ jfnk_status jfnk_jvp(jfnk_solver* s, const void* x, const void* v, void* Jv, voi
 
 /* Solve J(x) dx = rhs by restarted GMRES(m) (paper, Section 2) from dx = 0,
  * with the Gram-Schmidt form set by jfnk_set_orthogonalization (DCGS2 by
- * default in FP64/FP32, CGS2 with FP16 storage) and FP64 Givens least
+ * default) and FP64 Givens least
  * squares; tolerance relative to ||rhs||.  Reaching the cycle cap returns
  * JFNK_OK with info->converged = 0. */
 jfnk_status jfnk_gmres(jfnk_solver* s, const void* x, const void* rhs, void* dx, int m, double tol,
@@ -310,9 +312,8 @@ jfnk_status jfnk_newton_solve_noalloc(const jfnk_problem* problem, int precision
                                       jfnk_info* info, void* hip_stream);
 
 /* Gram-Schmidt form (jfnk_orth) of later jfnk_gmres calls on this solver
- * (default DCGS2 in FP64 and FP32, CGS2 with FP16 storage); jfnk_newton_solve
- * takes it from its options instead (jfnk_default_options: the same).
- * DCGS2 on an FP16S solver returns JFNK_ERR_ARG. */
+ * (default DCGS2); jfnk_newton_solve takes it from its options instead
+ * (jfnk_default_options: the same).  An unknown form returns JFNK_ERR_ARG. */
 jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth);
 
 /* Preconditioner (jfnk_precond) of later jfnk_gmres calls on this solver

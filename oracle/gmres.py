@@ -36,6 +36,16 @@ In exact arithmetic both forms give the same basis and Hessenberg matrix;
 the delayed form reads the basis twice per step instead of three times.
 After the last step the pending vector completes the last column.
 
+``store="fp16"`` keeps the basis as a reduced-precision store would (the
+paper's reduced-precision discussion; the storage format is this package's
+reading): every vector written to the basis is rounded to binary16 after
+scaling by a power of two that brings its typical entry near 1 (the scale
+changes no significand for entries in binary16's normal range).  What is
+written: r (then v_0 = stored r / ||r||, the norm of r before rounding),
+with CGS2 each new w (v_{j+1} = stored w / ||w||), with DCGS2 each pending
+u (its second pass and norm are taken over the stored u) and each v_j.
+Everything else stays in FP64.
+
 "Krylov iterations" counts Arnoldi steps.
 """
 
@@ -81,11 +91,31 @@ def back_substitute(R: np.ndarray, g: np.ndarray) -> np.ndarray:
     return y
 
 
+def store_fp16(v: np.ndarray) -> np.ndarray:
+    """v as held by an FP16 store: rounded to binary16 (nearest even) after
+    scaling by 2^-round(log2(||v|| / sqrt(n))), returned unscaled in FP64."""
+    nrm = float(np.linalg.norm(v))
+    if not (nrm > 0.0 and math.isfinite(nrm)):
+        return v.copy()
+    sig = 2.0 ** -round(math.log2(nrm / math.sqrt(v.shape[0])))
+    return (v * sig).astype(np.float16).astype(np.float64) / sig
+
+
+def _store_fn(store):
+    if store is None:
+        return lambda v: v
+    if store == "fp16":
+        return store_fp16
+    raise ValueError(store)
+
+
 def gmres(matvec, rhs: np.ndarray, m: int = 30, tol: float = 1e-8, max_restarts: int = 100,
-          breakdown_tol: float = 1e-14, record: bool = False, orth: str = "cgs2"):
-    """Solve J x = rhs; returns (x, GmresInfo).  orth: 'cgs2' or 'dcgs2'."""
+          breakdown_tol: float = 1e-14, record: bool = False, orth: str = "cgs2", store: str | None = None):
+    """Solve J x = rhs; returns (x, GmresInfo).  orth: 'cgs2' or 'dcgs2';
+    store: None (FP64 basis) or 'fp16' (basis rounded as stored in binary16)."""
+    st = _store_fn(store)
     if orth == "dcgs2":
-        return _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record)
+        return _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record, st)
     if orth != "cgs2":
         raise ValueError(orth)
     n = rhs.shape[0]
@@ -113,7 +143,7 @@ def gmres(matvec, rhs: np.ndarray, m: int = 30, tol: float = 1e-8, max_restarts:
         if cycle == max_restarts:
             return x, info
         info.cycles += 1
-        V = [r / beta]
+        V = [st(r) / beta]
         H = np.zeros((m + 1, m))  # rotated in place
         Hraw = np.zeros((m + 1, m))
         cs = np.zeros(m)
@@ -158,7 +188,7 @@ def gmres(matvec, rhs: np.ndarray, m: int = 30, tol: float = 1e-8, max_restarts:
             if wnorm <= breakdown_tol * jv_norm:
                 info.breakdowns += 1
                 break
-            V.append(w / wnorm)
+            V.append(st(w) / wnorm)
         y = back_substitute(H[:k, :k], g[:k])
         for i in range(k):
             x = x + y[i] * V[i]
@@ -182,7 +212,7 @@ def _rotate_column(H, cs, sn, g, j):
     g[j] = cs[j] * g[j]
 
 
-def _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record):
+def _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record, st):
     n = rhs.shape[0]
     x = np.zeros(n)
     info = GmresInfo()
@@ -208,7 +238,7 @@ def _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record):
         if cycle == max_restarts:
             return x, info
         info.cycles += 1
-        V = [r / beta0]
+        V = [st(r) / beta0]
         H = np.zeros((m + 1, m))  # rotated in place
         Hraw = np.zeros((m + 1, m))
         cs = np.zeros(m)
@@ -262,7 +292,7 @@ def _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record):
             d = float(np.dot(uh, w))
             if j == 0:
                 h = np.array([d])
-                u = w - d * V[0]
+                u = st(w - d * V[0])
             else:
                 Ha = Hraw[: j + 1, :j] @ ah  # J v_j = w - sum_i Ha_i v_i
                 gamma = d - float(np.dot(ah, b))
@@ -275,7 +305,8 @@ def _gmres_dcgs2(matvec, rhs, m, tol, max_restarts, breakdown_tol, record):
                 u = w - gamma * uh
                 for i in range(j):
                     u = u - (Ha[i] + h[i] - gamma * ah[i]) * V[i]
-                V.append(vj)
+                u = st(u)
+                V.append(st(vj))
             Hraw[: j + 1, j] = h
         if not stopped:
             a, beta, stop = complete(m - 1, u)

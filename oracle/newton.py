@@ -52,6 +52,7 @@ class NewtonOptions:
     krylov: str = "gmres"  # 'gmres' | 'bicgstab' | 'cg' (the last two capped at max_restarts iterations)
     orth: str = "cgs2"  # GMRES Gram-Schmidt: 'cgs2' or 'dcgs2' (second pass delayed one step)
     precond: str = "none"  # 'none' | 'cslp' (Maxwell-Kerr, GMRES only: right preconditioning)
+    store: str | None = None  # GMRES basis storage: None (FP64) or 'fp16' (see oracle.gmres)
 
     @classmethod
     def for_precision(cls, precision: str, **kw) -> "NewtonOptions":
@@ -156,7 +157,7 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
                 return _mv(fwd(_minv(bwd(z))))
 
             z, ginfo = gm.gmres(pmatvec, rhs, m=opts.m, tol=opts.tol_krylov, max_restarts=opts.max_restarts,
-                                breakdown_tol=opts.breakdown_tol, orth=opts.orth)
+                                breakdown_tol=opts.breakdown_tol, orth=opts.orth, store=opts.store)
             dx = minv(bwd(z))
             info.restarts += ginfo.cycles
         elif opts.precond != "none":
@@ -169,7 +170,8 @@ def newton_solve(p: Problem, x_prev: np.ndarray, opts: NewtonOptions, source=Non
             dx = bwd(dy)
         else:
             dy, ginfo = gm.gmres(matvec, rhs, m=opts.m, tol=opts.tol_krylov,
-                                 max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol, orth=opts.orth)
+                                 max_restarts=opts.max_restarts, breakdown_tol=opts.breakdown_tol, orth=opts.orth,
+                                 store=opts.store)
             dx = bwd(dy)
             info.restarts += ginfo.cycles
         info.krylov_iters += ginfo.iters

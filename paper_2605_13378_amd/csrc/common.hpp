@@ -110,6 +110,37 @@ template <> __device__ __forceinline__ float to_c<float, __half>(__half x) { ret
 template <class S, class C> __device__ __forceinline__ S to_s(C x) { return static_cast<S>(x); }
 template <> __device__ __forceinline__ __half to_s<__half, float>(float x) { return __float2half_rn(x); }
 
+// Two FP32 values rounded to FP16 (nearest even), packed low then high.
+__device__ __forceinline__ unsigned int pack_half2(float lo, float hi) {
+  return (unsigned int)__half_as_ushort(__float2half_rn(lo)) |
+         ((unsigned int)__half_as_ushort(__float2half_rn(hi)) << 16);
+}
+
+// Dot product of N packed FP16 pairs, accumulated in FP32 (the products are
+// exact), returned in FP64.
+template <int N>
+__device__ __forceinline__ double dot_half2(const unsigned int (&a)[N], const unsigned int (&b)[N]) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  float p = 0.0f;
+#pragma unroll
+  for (int q = 0; q < N; ++q) p = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, a[q]), __builtin_bit_cast(h2, b[q]), p, false);
+  return (double)p;
+}
+
+// a * (FP16 element `hi` of the packed pair h2, widened) + c in one fused
+// operation.  The compiler forms this instruction itself for a widened FP16
+// operand with a single use; written out where one element feeds two sums,
+// which the compiler would otherwise serve from a register per widened
+// element.  `hi` must be a compile-time constant.
+__device__ __forceinline__ float fma_mix_half(float a, unsigned int h2, int hi, float c) {
+  float d;
+  if (hi)
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "=v"(d) : "s"(a), "v"(h2), "v"(c));
+  else
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,1,0]" : "=v"(d) : "s"(a), "v"(h2), "v"(c));
+  return d;
+}
+
 template <class VT> constexpr bool is_half() { return false; }
 template <> constexpr bool is_half<__half>() { return true; }
 

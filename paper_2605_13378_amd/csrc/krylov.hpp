@@ -187,10 +187,12 @@ __device__ __forceinline__ void lagged_prefetch(const Ctl* __restrict__ ctl, int
 
 // Delayed second pass (the alternative Arnoldi form): column c is completed
 // by the kernel after the update pass of step c, from that pass's partial
-// sums pd = [V_0..V_c . u, u . u] of the pending vector u (once projected):
+// sums pd = [v_0..v_c . u, u . u] of the pending vector u (once projected):
 // a = V^T u, beta = sqrt(u.u - a.a), column = (first projection + a, beta),
 // then the Givens update as for CGS2.  Block 0 commits the unrotated column,
-// the rotation, a / beta and 1 / beta (the tangent scale of step c + 1).
+// the rotation, a / beta and 1 / (beta sigma) (the tangent scale of step
+// c + 1; sigma = vsig[c + 1] is the FP16 storage scale of u, 1 otherwise).
+template <bool HALF>
 __device__ __forceinline__ GivensOut finish_column_lagged_from(Ctl* __restrict__ ctl, int c, const Partials& pd,
                                                                int* host_flags, double* col, const LaggedPrefetch& lp) {
   __shared__ double tot[kMaxM + 2];
@@ -212,7 +214,7 @@ __device__ __forceinline__ GivensOut finish_column_lagged_from(Ctl* __restrict__
     in.tol_abs = ctl->tol_abs;
     in.brk_tol = ctl->brk_tol;
     in.jvn2 = ctl->jvn2c[c];
-    in.sig = 1.0;
+    in.sig = HALF ? ctl->vsig[c + 1] : 1.0;
   }
   __shared__ double s_b2;
   __shared__ int s_bad;
@@ -250,11 +252,12 @@ __device__ __forceinline__ GivensOut finish_column_lagged_from(Ctl* __restrict__
 }
 
 // The same, fetching its own inputs.
+template <bool HALF>
 __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, const Partials& pd, int* host_flags,
                                                  double* col) {
   LaggedPrefetch lp;
   lagged_prefetch(ctl, c, pd, lp);
-  return finish_column_lagged_from(ctl, c, pd, host_flags, col, lp);
+  return finish_column_lagged_from<HALF>(ctl, c, pd, host_flags, col, lp);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,28 +277,70 @@ struct KArgs {
   int nt;             // 1: basis read with the non-temporal hint
 };
 
-// Loads w and the K basis chunks at element i.  The caller zero-fills vv once:
-// chunks k >= K are never loaded and stay zero, so the arithmetic runs over
+// One thread's chunks of the K basis vectors (VEC consecutive elements of
+// each), held in registers in the working precision T.  FP16 storage keeps
+// them as loaded, two elements to a 32-bit register, and converts an element
+// where it is used: twice the elements per load for the same registers.
+// Chunks k >= K are never loaded and stay zero, so the arithmetic runs over
 // all KMAX slots without per-slot conditions (a zero coefficient times a zero
 // element leaves every sum unchanged, exactly).
 // NT: basis read with the non-temporal hint (a template parameter: a
 // run-time choice between two load sequences costs the register-resident
 // basis chunk its registers).
+template <class T, class VT, int KMAX, int VEC>
+struct Chunks {
+  T v[KMAX][VEC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v[k][e] = T(0);
+  }
+  template <bool NT>
+  __device__ __forceinline__ void load(const VT* p, int k) {
+    VT t[VEC];
+    if constexpr (NT)
+      load_vec_nt<VT, VEC>(p, t);
+    else
+      load_vec<VT, VEC>(p, t);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[k][e] = to_c<T>(t[e]);
+  }
+  __device__ __forceinline__ T get(int k, int e) const { return v[k][e]; }
+};
+
+template <int KMAX, int VEC>
+struct Chunks<float, __half, KMAX, VEC> {
+  static_assert(VEC % 2 == 0, "FP16 chunks hold element pairs");
+  unsigned int v[KMAX][VEC / 2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+      for (int e = 0; e < VEC / 2; ++e) v[k][e] = 0u;
+  }
+  template <bool NT>
+  __device__ __forceinline__ void load(const __half* p, int k) {
+    if constexpr (NT)
+      load_vec_nt<unsigned int, VEC / 2>(reinterpret_cast<const unsigned int*>(p), v[k]);
+    else
+      load_vec<unsigned int, VEC / 2>(reinterpret_cast<const unsigned int*>(p), v[k]);
+  }
+  __device__ __forceinline__ float get(int k, int e) const {
+    const unsigned int u = v[k][e >> 1];
+    const unsigned short h = (unsigned short)((e & 1) ? (u >> 16) : (u & 0xffffu));
+    return __half2float(__ushort_as_half(h));
+  }
+};
+
+// Loads w and the K basis chunks at element i.
 template <class T, class VT, int KMAX, int VEC, bool NT>
-__device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int K, T (&w)[VEC], T (&vv)[KMAX][VEC]) {
+__device__ __forceinline__ void cgs_load(const KArgs<T, VT>& a, long long i, int K, T (&w)[VEC],
+                                         Chunks<T, VT, KMAX, VEC>& vv) {
   load_vec<T, VEC>(a.w + i, w);
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      VT t[VEC];
-      if constexpr (NT)
-        load_vec_nt<VT, VEC>(a.V + k * a.vstride + i, t);
-      else
-        load_vec<VT, VEC>(a.V + k * a.vstride + i, t);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) vv[k][e] = to_c<T>(t[e]);
-    }
-  }
+  for (int k = 0; k < KMAX; ++k)
+    if (k < K) vv.template load<NT>(a.V + k * a.vstride + i, k);
 }
 
 // Dot product of one thread's VEC-element chunks, returned in FP64 for the
@@ -319,6 +364,22 @@ __device__ __forceinline__ double group_dot(const T (&a)[VEC], const T (&b)[VEC]
   }
 }
 
+// The same with basis chunk k as the first operand.
+template <class T, class VT, int KMAX, int VEC>
+__device__ __forceinline__ double group_dot(const Chunks<T, VT, KMAX, VEC>& a, int k, const T (&b)[VEC]) {
+  if constexpr (sizeof(T) == 4) {
+    T p = a.get(k, 0) * b[0];
+#pragma unroll
+    for (int e = 1; e < VEC; ++e) p = fmaf(a.get(k, e), b[e], p);
+    return (double)p;
+  } else {
+    double p = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) p += (double)a.get(k, e) * (double)b[e];
+    return p;
+  }
+}
+
 template <class T, class VT, int KMAX, int VEC, int MODE, bool NT>
 __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
@@ -328,11 +389,8 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
   // the first chunk's loads go out before the stop check and the coefficient
   // reduction (in-bounds either way; unused if the cycle has stopped)
   T w[VEC];
-  T vv[KMAX][VEC];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
+  Chunks<T, VT, KMAX, VEC> vv;
+  vv.zero();
   if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   if (ctl->done_col[K - 1] != kRunning) return;  // state after the Givens update of column K-2
 
@@ -386,7 +444,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
       for (int kb = 0; kb < KMAX; kb += 4)
         if (kb < K)
 #pragma unroll
-          for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], w);
+          for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot(vv, kb + u, w);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)w[e] * (double)w[e];
     } else {
@@ -395,7 +453,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
       for (int e = 0; e < VEC; ++e) {
         T x = w[e];
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) x = x - coef[k] * vv[k][e];
+        for (int k = 0; k < KMAX; ++k) x = x - coef[k] * vv.get(k, e);
         wn[e] = x;
       }
       if constexpr (MODE == PASS_B) {
@@ -405,7 +463,7 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
         for (int kb = 0; kb < KMAX; kb += 4)
           if (kb < K)
 #pragma unroll
-            for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], wn);
+            for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot(vv, kb + u, wn);
         if constexpr (is_half<VT>()) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];
@@ -445,9 +503,18 @@ __global__ void __launch_bounds__(512) cgs_kernel(const KArgs<T, VT> a) {
 // and streams
 //   V_j     <- tscale_j U_j - sum_i a^_i V_i           (v_j, unit norm)
 //   U_{j+1} <- w - sum_i ((H a^)_i + h_i - gamma a^_i) V_i - gamma tscale_j U_j
-// with partial sums [V_0..V_j . U_{j+1}, ||U_{j+1}||^2] for the next column's
-// completion.  Block 0 commits h to the unrotated Hessenberg, scale_j = 1 and
+// with partial sums [v_0..v_j . U_{j+1}, ||U_{j+1}||^2] for the next column's
+// completion.  Block 0 commits h to the unrotated Hessenberg, scale_j and
 // ||w||^2.  One read of the basis per step, where CGS2 takes two.
+//
+// FP16 storage: both written vectors are stored times a scale fixed before
+// the stream starts, sigma_v = fp16_scale(1) for the unit v_j (scale_j =
+// 1 / sigma_v; at j = 0 sigma_v = 1 / tscale_0, which leaves the stored V_0
+// as it is) and sigma_u = fp16_scale(||U_{j+1}||) from the orthogonal
+// projection identity ||U_{j+1}||^2 ~ ||w||^2 - ||h||^2 (vsig[j + 1], folded
+// into the next tangent scale by the completion).  The sums for the
+// completion are taken over the rounded stored values, so the second pass
+// projects what the basis actually holds.
 template <class T, class VT, int KMAX, int VEC, bool NT>
 __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   Ctl* ctl = a.ctl;
@@ -455,11 +522,12 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   const int j = K - 1;
   const long long step = (long long)gridDim.x * blockDim.x * VEC;
   long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  if (ctl->done_col[j] != kRunning) return;  // state after column j-1
+  const int state = ctl->done_col[j];  // state after column j-1, tested once the loads below are out
 
-  // The prologue's loads (partial sums, control-block inputs) go out together
-  // and before the basis chunk: issued after it, each would wait for the
-  // whole chunk to arrive (vector loads complete in order).
+  // The prologue's loads (partial sums, control-block inputs) go out first,
+  // then the first basis chunk, whose round trip then overlaps the prologue's
+  // arithmetic (vector loads complete in order: the prologue waits only for
+  // its own, older loads).  If the cycle has stopped the loads are unused.
   PartialFetch pf;
   partials_fetch(a.in, K + 1, pf);
   __shared__ double tot[KMAX + 1];
@@ -467,10 +535,10 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   __shared__ double sh_cv[KMAX], sh_cw[KMAX];
   __shared__ double sh_hu[KMAX * KMAX];  // completed columns 0..j-1, rows 0..j (stride j + 1)
   __shared__ double sh_ts;
+  __shared__ double sh_sv, sh_su;  // FP16 storage scales of v_j and U_{j+1}
   const int tid = threadIdx.x;
   const int ld = kMaxM + 1;
-  // control-block inputs staged into LDS by all threads at once, their loads
-  // in flight together with the partial-sum reduction
+  // control-block inputs staged into LDS by all threads at once
   for (int idx = tid; idx < j * (j + 1); idx += blockDim.x) {
     const int l = idx / (j + 1), r = idx - l * (j + 1);
     sh_hu[idx] = ctl->Hu[l * ld + r];
@@ -480,6 +548,11 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
     sh_sc[tid] = ctl->scale[tid];
   }
   if (tid == 0) sh_ts = ctl->tscale[j];
+  T w[VEC];
+  Chunks<T, VT, KMAX, VEC> vv;
+  vv.zero();
+  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
+  if (state != kRunning) return;
   partials_reduce(a.in, K + 1, pf, tot);  // ends with a barrier
   if (tid < j) sh_b[tid] = tot[tid] * sh_sc[tid];
   if (tid <= j) {
@@ -489,34 +562,45 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
     sh_ha[tid] = s;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid < kWave) {
+    // the coefficients, lane l for vector l (j < 64), sums across the wavefront
+    const int l = tid;
     const double ts = sh_ts;
-    const double d = ts * tot[j];
-    double ab = 0.0;
-    for (int l = 0; l < j; ++l) ab += sh_ah[l] * sh_b[l];
-    const double gamma = d - ab;
-    for (int l = 0; l < j; ++l) {
-      const double h = sh_b[l] - sh_ha[l];
-      sh_cv[l] = -sh_ah[l] * sh_sc[l];
-      sh_cw[l] = (sh_ha[l] + h - gamma * sh_ah[l]) * sh_sc[l];
-      if (blockIdx.x == 0) ctl->Hp[j * ld + l] = h;
+    const double ahl = l < j ? sh_ah[l] : 0.0;
+    const double bl = l < j ? sh_b[l] : 0.0;
+    const double gamma = ts * tot[j] - wave_sum(ahl * bl);
+    double hl = 0.0;
+    if (l < j) {
+      hl = bl - sh_ha[l];
+      sh_cv[l] = -ahl * sh_sc[l];
+      sh_cw[l] = (sh_ha[l] + hl - gamma * ahl) * sh_sc[l];
+    } else if (l == j) {
+      hl = gamma - sh_ha[j];
+      sh_cv[j] = ts;
+      sh_cw[j] = gamma * ts;
     }
-    sh_cv[j] = ts;
-    sh_cw[j] = gamma * ts;
-    if (blockIdx.x == 0) {
-      ctl->Hp[j * ld + j] = gamma - sh_ha[j];
-      ctl->scale[j] = 1.0;
-      ctl->jvn2c[j] = tot[K];
+    if (blockIdx.x == 0 && l <= j) ctl->Hp[j * ld + l] = hl;
+    double sv = 1.0, su = 1.0;
+    if constexpr (is_half<VT>()) {
+      const double hh = wave_sum(hl * hl);
+      const double ww = tot[K];
+      const double uu = ww - hh;
+      // v_0 = tscale_0 U_0 is U_0 itself: stored with the inverse scale, the
+      // rewrite returns its FP16 values unchanged instead of rounding again
+      sv = j == 0 ? 1.0 / ts : fp16_scale(1.0, a.n);
+      su = fp16_scale(sqrt(uu > 1e-6 * ww ? uu : 1e-6 * ww), a.n);
+    }
+    if (l == 0) {
+      sh_sv = sv;
+      sh_su = su;
+      if (blockIdx.x == 0) {
+        ctl->scale[j] = 1.0 / sv;
+        ctl->vsig[j + 1] = su;
+        ctl->jvn2c[j] = tot[K];
+      }
     }
   }
   __syncthreads();
-  T w[VEC];
-  T vv[KMAX][VEC];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) vv[k][e] = T(0);
-  if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   T cv[KMAX], cw[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
@@ -528,41 +612,86 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
   double accv = 0.0;
   VT* vj_out = a.wout - a.vstride;  // slot j (wout is slot j + 1)
-  for (; i < a.n; i += step) {
-    T vn[VEC], wn[VEC];
+  if constexpr (is_half<VT>()) {
+    // FP16 storage: both vectors are rounded to their scaled FP16 values as
+    // they are formed, and the sums are taken over those stored values with
+    // packed FP16 dot products (the products of two FP16 numbers are exact in
+    // FP32, the chunk sums carry a few 2^-24) -- the basis chunks are used in
+    // their packed form, with no second conversion
+    const float sv = (float)sh_sv, su = (float)sh_su;
+    for (; i < a.n; i += step) {
+      // vector by vector, so that each converted element is used at once
+      float x[VEC], y[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      T x = T(0);
-      T y = w[e];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        x = x + cv[k] * vv[k][e];
-        y = y - cw[k] * vv[k][e];
+      for (int e = 0; e < VEC; ++e) {
+        x[e] = 0.0f;
+        y[e] = w[e];
       }
-      vn[e] = x;
-      wn[e] = y;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          x[e] = fma_mix_half(cv[k], vv.v[k][e >> 1], e & 1, x[e]);
+          y[e] = y[e] - cw[k] * vv.get(k, e);
+        }
+      unsigned int p1[VEC / 2], p2[VEC / 2];
+#pragma unroll
+      for (int e = 0; e < VEC; e += 2) {
+        p1[e / 2] = pack_half2(x[e] * sv, x[e + 1] * sv);
+        p2[e / 2] = pack_half2(y[e] * su, y[e + 1] * su);
+      }
+#pragma unroll
+      for (int kb = 0; kb < KMAX; kb += 4)
+        if (kb < K)
+#pragma unroll
+          for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += dot_half2<VEC / 2>(vv.v[kb + u], p2);
+      accv += dot_half2<VEC / 2>(p1, p2);
+      acc[KMAX] += dot_half2<VEC / 2>(p2, p2);
+      store_vec<unsigned int, VEC / 2>(reinterpret_cast<unsigned int*>(vj_out + i), p1);
+      store_vec<unsigned int, VEC / 2>(reinterpret_cast<unsigned int*>(a.wout + i), p2);
+      if (i + step < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i + step, K, w, vv);
     }
-    // groups of four slots behind one uniform branch; slot j's product (with
-    // U_j) is replaced by the one with the new v_j below
+    // back to unscaled sums: V_i = v_i / scale_i (i < j), the stored v_j and
+    // U_{j+1} carry sigma_v and sigma_u (powers of two, exact, except for
+    // v_0's scale: one FP64 rounding)
+    const double isu = 1.0 / sh_su;
 #pragma unroll
-    for (int kb = 0; kb < KMAX; kb += 4)
-      if (kb < K)
+    for (int k = 0; k < KMAX; ++k)
+      if (k < j) acc[k] *= sh_sc[k] * isu;
+    accv *= isu / sh_sv;
+    acc[KMAX] *= isu * isu;
+  } else {
+    for (; i < a.n; i += step) {
+      T vn[VEC], wn[VEC];
 #pragma unroll
-        for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot<T, VEC>(vv[kb + u], wn);
-    accv += group_dot<T, VEC>(vn, wn);
+      for (int e = 0; e < VEC; ++e) {
+        T x = T(0);
+        T y = w[e];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];
-    VT o1[VEC], o2[VEC];
+        for (int k = 0; k < KMAX; ++k) {
+          const T v = vv.get(k, e);
+          x = x + cv[k] * v;
+          y = y - cw[k] * v;
+        }
+        vn[e] = x;
+        wn[e] = y;
+      }
+      // groups of four slots behind one uniform branch; slot j's product (with
+      // U_j) is replaced by the one with the new v_j below
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      o1[e] = to_s<VT>(vn[e]);
-      o2[e] = to_s<VT>(wn[e]);
+      for (int kb = 0; kb < KMAX; kb += 4)
+        if (kb < K)
+#pragma unroll
+          for (int u = 0; u < 4 && kb + u < KMAX; ++u) acc[kb + u] += group_dot(vv, kb + u, wn);
+      accv += group_dot<T, VEC>(vn, wn);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[KMAX] += (double)wn[e] * (double)wn[e];
+      store_vec<VT, VEC>(vj_out + i, vn);
+      store_vec<VT, VEC>(a.wout + i, wn);
+      if (i + step < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i + step, K, w, vv);
     }
-    store_vec<VT, VEC>(vj_out + i, o1);
-    store_vec<VT, VEC>(a.wout + i, o2);
-    if (i + step < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i + step, K, w, vv);
   }
-  // [V_0..V_{j-1} . U_{j+1}, v_j . U_{j+1}, ||U_{j+1}||^2] (static indices keep acc in registers)
+  // [v_0..v_{j-1} . U_{j+1}, v_j . U_{j+1}, ||U_{j+1}||^2] (static indices keep acc in registers)
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k == j) acc[k] = accv;
@@ -723,7 +852,7 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   const bool pending = a.jmax >= 0 && k == a.jmax + 1;
   __shared__ int lastdone;
   if (pending) {
-    const GivensOut g = a.lagged ? finish_column_lagged(ctl, a.jmax, a.pc, a.host_flags, lastcol)
+    const GivensOut g = a.lagged ? finish_column_lagged<is_half<VT>()>(ctl, a.jmax, a.pc, a.host_flags, lastcol)
                                  : finish_column(ctl, a.jmax, a.pc, a.host_flags, lastcol);
     if (tid == 0) {
       lastgr = g.gr;
@@ -770,21 +899,15 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
     } else {
       load_vec<T, VEC>(a.dx + i, d);
     }
+    Chunks<T, VT, KMAX, VEC> t;
+    t.zero();
 #pragma unroll
-    for (int c = 0; c < KMAX; ++c) {
-      VT t[VEC];
-      if (c < k) {
-        if constexpr (NT)
-          load_vec_nt<VT, VEC>(a.V + c * a.vstride + i, t);
-        else
-          load_vec<VT, VEC>(a.V + c * a.vstride + i, t);
-      } else {
+    for (int c = 0; c < KMAX; ++c)
+      if (c < k) t.template load<NT>(a.V + c * a.vstride + i, c);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) t[e] = VT(0);
-      }
+    for (int c = 0; c < KMAX; ++c)
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) d[e] = d[e] + coef[c] * to_c<T>(t[e]);
-    }
+      for (int e = 0; e < VEC; ++e) d[e] = d[e] + coef[c] * t.get(c, e);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[0] += (double)d[e] * (double)d[e];
     store_vec<T, VEC>(a.dx + i, d);

@@ -65,9 +65,12 @@ template <class T>
 constexpr int krylov_vec() {
   return (int)(16 / sizeof(T));
 }
-template <class T, int KMAX>
+// Elements per thread of the Krylov passes: 16-byte loads of the basis (FP16
+// storage: eight elements), one FP64 element when 32 vectors would not fit
+// the registers at two.
+template <class T, class VT, int KMAX>
 constexpr int cgs_vec() {
-  return (sizeof(T) == 8 && KMAX > 16) ? 1 : (int)(16 / sizeof(T));
+  return sizeof(VT) == 2 ? 8 : ((sizeof(T) == 8 && KMAX > 16) ? 1 : (int)(16 / sizeof(T)));
 }
 
 constexpr int kStencilThreads = 256;

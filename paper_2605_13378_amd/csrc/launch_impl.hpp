@@ -43,7 +43,7 @@ hipError_t launch_cslp_apply(int pid, const T* x, T* z, int nx, int ny, const Co
 
 template <class T, class VT, int KMAX, bool NT>
 static hipError_t cgs_by_mode(int mode, const KArgs<T, VT>& a, int grid, hipStream_t s) {
-  constexpr int VEC = cgs_vec<T, KMAX>();
+  constexpr int VEC = cgs_vec<T, VT, KMAX>();
   const dim3 g(grid), b(kKrylovThreads);
   if (mode == PASS_A)
     JFNK_LAUNCH((cgs_kernel<T, VT, KMAX, VEC, PASS_A, NT>), g, b, s, a);
@@ -71,23 +71,19 @@ template <class T, class VT, bool NT>
 static hipError_t launch_dcgs_nt(const KArgs<T, VT>& a, int grid, hipStream_t s) {
   const dim3 b(kKrylovThreads);
   if (a.K <= 4)
-    JFNK_LAUNCH((dcgs_kernel<T, VT, 4, cgs_vec<T, 4>(), NT>), dim3(grid), b, s, a);
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 4, cgs_vec<T, VT, 4>(), NT>), dim3(grid), b, s, a);
   else if (a.K <= 8)
-    JFNK_LAUNCH((dcgs_kernel<T, VT, 8, cgs_vec<T, 8>(), NT>), dim3(grid), b, s, a);
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 8, cgs_vec<T, VT, 8>(), NT>), dim3(grid), b, s, a);
   else if (a.K <= 16)
-    JFNK_LAUNCH((dcgs_kernel<T, VT, 16, cgs_vec<T, 16>(), NT>), dim3(grid), b, s, a);
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 16, cgs_vec<T, VT, 16>(), NT>), dim3(grid), b, s, a);
   else
-    JFNK_LAUNCH((dcgs_kernel<T, VT, 32, cgs_vec<T, 32>(), NT>), dim3(grid), b, s, a);
+    JFNK_LAUNCH((dcgs_kernel<T, VT, 32, cgs_vec<T, VT, 32>(), NT>), dim3(grid), b, s, a);
   return hipGetLastError();
 }
 
 template <class T, class VT>
 hipError_t launch_dcgs(const KArgs<T, VT>& a, int grid, hipStream_t s) {
-  if constexpr (!std::is_same<T, VT>::value) {
-    return hipErrorInvalidValue;  // FP16 storage keeps CGS2
-  } else {
-    return a.nt ? launch_dcgs_nt<T, VT, true>(a, grid, s) : launch_dcgs_nt<T, VT, false>(a, grid, s);
-  }
+  return a.nt ? launch_dcgs_nt<T, VT, true>(a, grid, s) : launch_dcgs_nt<T, VT, false>(a, grid, s);
 }
 
 template <class T, class VT>
@@ -99,7 +95,7 @@ hipError_t launch_init(const InitArgs<T, VT>& a, int grid, hipStream_t s) {
 
 template <class T, class VT, bool NT>
 static hipError_t launch_vy_nt(const VyArgs<T, VT>& a, int m, int grid, hipStream_t s) {
-  constexpr int VEC = krylov_vec<T>();
+  constexpr int VEC = sizeof(VT) == 2 ? 8 : krylov_vec<T>();  // 16-byte basis loads
   const dim3 g(grid), b(kKrylovThreads);
   if (m <= 8)
     JFNK_LAUNCH((vy_kernel<T, VT, 8, VEC, NT>), g, b, s, a);

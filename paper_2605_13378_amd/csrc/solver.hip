@@ -302,7 +302,7 @@ struct Impl {
   // K = 24).  Consumers of a pass's partial sums use the same grid.
   static int cgs_grid(const jfnk_solver* s, int K) {
     const int kmax = K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 16 ? 16 : 32));
-    const int vec = (sizeof(T) == 8 && kmax > 16) ? 1 : (int)(16 / sizeof(T));
+    const int vec = sizeof(VT) == 2 ? 8 : ((sizeof(T) == 8 && kmax > 16) ? 1 : (int)(16 / sizeof(T)));
     const bool two = kmax <= 16;
     const long long need = (s->npad + (long long)kKrylovThreads * vec - 1) / ((long long)kKrylovThreads * vec);
     return (int)std::max<long long>(1, std::min<long long>(need, (two ? 2LL : 1LL) * s->cu));
@@ -411,7 +411,6 @@ struct Impl {
                            int mode, double fixed_eps, int eps_rule, double brk, GOut& go, bool lagged = false,
                            bool pre = false) {
     go = GOut{};
-    if constexpr (!std::is_same<T, VT>::value) lagged = false;  // FP16 storage keeps CGS2
     T* dxi = static_cast<T*>(s->dx);
     T* w = static_cast<T*>(s->w);
     const int kgrid = krylov_grid(s, KVEC);
@@ -1278,7 +1277,7 @@ void jfnk_default_options(int precision, jfnk_options* o) {
   o->mode = JFNK_JVP_AD;
   o->eps_rule = JFNK_EPS_PAPER;
   o->engine = JFNK_ENGINE_AUTO;
-  o->orth = precision == JFNK_F16S ? JFNK_ORTH_CGS2 : JFNK_ORTH_DCGS2;
+  o->orth = JFNK_ORTH_DCGS2;
   if (precision == JFNK_F64) {
     o->tol_newton = 1e-6;
     o->tol_krylov = 1e-8;
@@ -1335,7 +1334,7 @@ jfnk_status jfnk_create(const jfnk_problem* problem, int precision, int m, void*
   s->vstride = s->npad + kBasisPad;
   s->tsize = elem_size(precision);
   s->vsize = basis_elem_size(precision);
-  s->orth = precision == JFNK_F16S ? JFNK_ORTH_CGS2 : JFNK_ORTH_DCGS2;
+  s->orth = JFNK_ORTH_DCGS2;
   int dev = 0;
   hipDeviceProp_t prop{};
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
@@ -1448,10 +1447,6 @@ jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth) {
   if (!s) return JFNK_ERR_ARG;
   if (orth != JFNK_ORTH_CGS2 && orth != JFNK_ORTH_DCGS2) {
     s->err = "unknown Gram-Schmidt form";
-    return JFNK_ERR_ARG;
-  }
-  if (orth == JFNK_ORTH_DCGS2 && s->prec == JFNK_F16S) {
-    s->err = "DCGS2 runs in FP64 or FP32 (FP16 storage keeps CGS2)";
     return JFNK_ERR_ARG;
   }
   s->orth = orth;
@@ -1624,10 +1619,6 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
       o.krylov < JFNK_KRYLOV_GMRES || o.krylov > JFNK_KRYLOV_CG || o.orth < JFNK_ORTH_CGS2 ||
       o.orth > JFNK_ORTH_DCGS2) {
     s->err = "invalid options";
-    return JFNK_ERR_ARG;
-  }
-  if (o.orth == JFNK_ORTH_DCGS2 && s->prec == JFNK_F16S) {
-    s->err = "DCGS2 runs in FP64 or FP32 (FP16 storage keeps CGS2)";
     return JFNK_ERR_ARG;
   }
   if (o.krylov != JFNK_KRYLOV_GMRES && !short_recurrence_fits(s, o.krylov, &s->err)) return JFNK_ERR_ARG;

@@ -491,7 +491,8 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
           vscale = a.ctl->scale[0];
         } else {
           __shared__ double gcol[kMaxM + 1];
-          const GivensOut g = a.lagged ? finish_column_lagged_from(a.ctl, j - 1, a.pc, a.host_flags, gcol, lpf)
+          const GivensOut g = a.lagged ? finish_column_lagged_from<is_half<VT>()>(a.ctl, j - 1, a.pc, a.host_flags,
+                                                                                  gcol, lpf)
                                        : finish_column(a.ctl, j - 1, a.pc, a.host_flags, gcol);
           if (g.done != kRunning) return;  // uniform: every block computed the same update
           vscale = g.vs;

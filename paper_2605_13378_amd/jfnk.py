@@ -284,7 +284,7 @@ class Solver:
         return (jv, F) if want_F else jv
 
     def set_orthogonalization(self, orth: str):
-        """Gram-Schmidt form of later gmres() calls: 'cgs2' or 'dcgs2' (default in FP64/FP32)."""
+        """Gram-Schmidt form of later gmres() calls: 'cgs2' or 'dcgs2' (the default)."""
         self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
 
     def set_preconditioner(self, precond: str):

@@ -75,7 +75,7 @@ def test_default_options_follow_the_paper(jlib):
     assert (o32.tol_newton, o32.tol_krylov) == (1e-4, 1e-6)
     assert o64.max_newton == 15 and o64.max_restarts == 100 and o64.m == 30
     assert o64.krylov == jfnk.KRYLOV["gmres"] and o64.engine == jfnk.ENGINES["auto"]
-    assert o64.orth == jfnk.ORTH["dcgs2"] and jfnk.default_options("f16s").orth == jfnk.ORTH["cgs2"]
+    assert o64.orth == jfnk.ORTH["dcgs2"] and jfnk.default_options("f16s").orth == jfnk.ORTH["dcgs2"]
 
 
 def test_invalid_create_is_rejected_without_gpu(jlib):

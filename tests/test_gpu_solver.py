@@ -331,7 +331,8 @@ def test_full_size_burgers2d_f16s_ad():
 
 @pytest.mark.parametrize("kind,nx,ny", [("grayscott", 64, 64), ("burgers2d", 48, 40), ("grayscott", 1024, 1024)])
 @pytest.mark.parametrize("mode", ["ad", "fd"])
-def test_newton_f16s(kind, nx, ny, mode):
+@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+def test_newton_f16s(kind, nx, ny, mode, orth):
     """FP16-stored basis and tangent, FP32 arithmetic, FP64 Givens/update/merit.
 
     Not a per-iterate parity case (FP16 storage perturbs every basis vector by
@@ -344,7 +345,7 @@ def test_newton_f16s(kind, nx, ny, mode):
     o = NewtonOptions.for_precision("f32", mode=mode, eps_rule="normalized")
     x_ref, ref = newton_solve(p, xp, o, source=src)
     s = solver(spec, "f16s", xp, src)
-    x, info = s.newton_solve(dev(xp, wdtype("f64")), mode=mode, eps_rule="normalized")
+    x, info = s.newton_solve(dev(xp, wdtype("f64")), mode=mode, eps_rule="normalized", orth=orth)
     assert info["converged"] and ref.converged, (info, ref)
     assert info["rel_res"][-1] < o.tol_newton
     bound = 2 * o.tol_newton * ref.f0_norm + 1e-6 * np.linalg.norm(x_ref)
