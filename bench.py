@@ -412,9 +412,17 @@ def serving_pass(batch, reqs, inputs, rate_scale, saturate):
     span = max(done) - t0
     bad = sum(1 for r in results if r[1]["rc"] not in (0, 6))
     unconv = sum(1 for r in results if not r[1]["converged"])
-    return dict(solves_per_s=round(len(reqs) / span, 2), makespan_s=round(span, 3),
-                p50_ms=round(1e3 * percentile(lat, 0.5), 3), p99_ms=round(1e3 * percentile(lat, 0.99), 3),
-                failed=bad, not_converged=unconv)
+    out = dict(solves_per_s=round(len(reqs) / span, 2), makespan_s=round(span, 3),
+               p50_ms=round(1e3 * percentile(lat, 0.5), 3), p99_ms=round(1e3 * percentile(lat, 0.99), 3),
+               failed=bad, not_converged=unconv)
+    if bad:
+        # status codes of the failed requests (jfnk_status) and which requests
+        codes = {}
+        for i, r in enumerate(results):
+            if r[1]["rc"] not in (0, 6):
+                codes.setdefault(str(r[1]["rc"]), []).append(f"{reqs[i]['kind']}:{reqs[i]['size']}")
+        out["failed_status"] = codes
+    return out
 
 
 def serving_bench(count, slots, budget_gib, seed=0):
@@ -438,6 +446,18 @@ def serving_bench(count, slots, budget_gib, seed=0):
     mu1 = sat1["solves_per_s"]
     out["saturation"] = {"one_at_a_time": sat1, "batched": satm}
     log(f"[bench] serving saturation: one-at-a-time {sat1} batched {satm}")
+    # saturation throughput against the slot count (a process gets 4 hardware queues here,
+    # so streams beyond 4 share them)
+    by_slots = {"1": sat1, str(slots): satm}
+    for k in (2, 4, 8, 16):
+        if str(k) in by_slots:
+            continue
+        bk = Batch("f32", m=30, max_slots=k, budget_bytes=budget)
+        serving_pass(bk, reqs[:warm], inputs[:warm], 1.0, True)
+        by_slots[str(k)] = serving_pass(bk, reqs, inputs, 1.0, True)
+        bk.close()
+        log(f"[bench] serving saturation with {k} slots: {by_slots[str(k)]}")
+    out["saturation_by_slots"] = dict(sorted(by_slots.items(), key=lambda kv: int(kv[0])))
     rows = []
     for lam in (0.5, 1.0, 2.0, 4.0):
         rate = lam * mu1  # requests/s; the stream was drawn at 1 request/s
@@ -450,6 +470,41 @@ def serving_bench(count, slots, budget_gib, seed=0):
     single.close()
     multi.close()
     return out
+
+
+def _oracle_serving_request(req):
+    """One serving request through the oracle (a worker process of serving_oracle)."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import NewtonOptions, Problem, newton_solve
+
+    spec, xp = W.serving_request_inputs(req)
+    with threadpool_limits(1):
+        _, info = newton_solve(Problem.from_spec(spec), xp, NewtonOptions.for_precision("f32", mode="ad"))
+    return info.converged
+
+
+def serving_oracle(sample=32, seed=0, workers=None):
+    """The serving stream's first `sample` requests through the oracle on P worker
+    processes (one core each): requests per second of the whole sample."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import workloads as W
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    reqs = W.serving_stream(count=2000, seed=seed, rate=1.0)[:sample]
+    # spawned children: a fresh interpreter, nothing inherited from this GPU process
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_oracle_serving_request, [dict(id=0, kind="burgers1d", size=256, seed=1)] * workers))
+        t0 = time.perf_counter()
+        conv = list(ex.map(_oracle_serving_request, reqs))
+        el = time.perf_counter() - t0
+    return dict(value=round(sample / el, 3), unit="solves/s", cores=workers, kind="oracle",
+                sample=f"the first {sample} requests of the serving stream (seed {seed}; FP32 tolerances, FP64 "
+                       f"arithmetic), one request per worker process at a time; {sum(conv)} converged",
+                seconds=round(el, 2))
 
 
 def bicgstab_rows(torch, spec, xp, x0, steps, budget_s=8.0):
@@ -921,6 +976,10 @@ def main():
         log("[bench] CPU oracle baseline (1 solve)")
         cpu = cpu_baseline(spec, xp, prec)
         log(f"[bench] cpu: {cpu}")
+        if serving is not None:
+            log("[bench] CPU oracle beside the serving stream")
+            serving["cpu_oracle"] = serving_oracle()
+            log(f"[bench] serving cpu oracle: {serving['cpu_oracle']}")
 
     out = {
         "metric": "Newton solves/sec and JVP HBM GB/s, AD vs FD, FP64/FP32/FP16; p99 latency",

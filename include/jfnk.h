@@ -357,6 +357,10 @@ jfnk_status jfnk_profile_reset(jfnk_solver* s);
  * concurrently on their slots' streams, so their kernels overlap on the
  * device.  Solver workspaces stay on the device between requests of the same
  * shape (least recently used ones are released when the budget needs room).
+ * Device memory is returned only while no request is on the device (a device
+ * free waits for every stream): a workspace to be released is held, its
+ * bytes still counted, until the running requests have finished, and a
+ * request that needs that room waits for it.
  * Every kernel's launch shape depends only on the problem, so a request's
  * result is bitwise the same whether it runs alone or in a mix.
  * ------------------------------------------------------------------------ */
@@ -376,6 +380,7 @@ typedef struct {
   int max_running;          /* most requests seen on the device at once */
   size_t bytes_in_use;      /* workspaces held now */
   size_t peak_bytes;        /* most workspace bytes held at once (never above the budget) */
+  long long frees_while_running; /* device frees made while a request was on the device (0) */
 } jfnk_batch_stats;
 
 /* Create a batch; the calling thread's current device is used. */

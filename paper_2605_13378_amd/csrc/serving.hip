@@ -8,9 +8,17 @@
 // recently used order.  It then runs the whole Newton solve on its own
 // stream, so requests admitted while others are on the device overlap with
 // them; when the solve ends the workspace goes back to the cache (or is
-// freed) and waiting workers re-check the queue head.  Admission is strictly
-// first come, first served: a head request that does not fit yet is not
-// overtaken, which bounds every request's wait by the work queued before it.
+// released) and waiting workers re-check the queue head.  Admission is
+// strictly first come, first served: a head request that does not fit yet is
+// not overtaken, which bounds every request's wait by the work queued before
+// it.
+//
+// Device memory goes back only while nothing runs: a device free waits for
+// every stream of the device, so one issued while other slots compute would
+// stall them.  Workspaces to be released wait in `doomed` (their bytes still
+// counted against the budget); the worker that sees the device idle frees
+// them, with admission closed meanwhile.  A head request that needs the room
+// of idle cached workspaces waits for the device to go idle first.
 //
 // A workspace is one jfnk_solver (its GMRES/Newton arrays) plus FP64 device
 // arrays for the iterate, the previous state and the optional source; its
@@ -81,6 +89,8 @@ struct jfnk_batch {
   std::deque<std::shared_ptr<Request>> queue;
   std::map<long long, std::shared_ptr<Request>> reqs;
   std::list<Workspace*> idle;  // front = most recently used
+  std::vector<Workspace*> doomed;  // released, freed once no request runs
+  bool freeing = false;        // a worker is freeing `doomed`: admission closed
   size_t in_use = 0;           // bytes of every live workspace plus reservations
   long long next_ticket = 1;
   bool stop = false;
@@ -180,7 +190,13 @@ void worker_main(jfnk_batch* b) {
       std::unique_lock<std::mutex> lk(b->mu);
       for (;;) {
         if (b->stop) break;
-        if (!b->queue.empty()) {
+        if (b->running == 0 && !b->freeing && !b->doomed.empty()) {
+          // the device is idle: free what was released while others ran
+          evicted.swap(b->doomed);
+          b->freeing = true;
+          break;
+        }
+        if (!b->queue.empty() && !b->freeing) {
           const std::shared_ptr<Request>& head = b->queue.front();
           auto it = std::find_if(b->idle.begin(), b->idle.end(),
                                  [&](const Workspace* w) { return same_shape(w->prob, head->prob) && w->n == head->n &&
@@ -188,18 +204,20 @@ void worker_main(jfnk_batch* b) {
           if (it != b->idle.end()) {
             ws = *it;
             b->idle.erase(it);
-          } else {
+          } else if (b->in_use + head->footprint <= b->cfg.budget_bytes) {
+            b->in_use += head->footprint;
+            create = true;
+          } else if (b->running == 0 && !b->idle.empty()) {
+            // release least recently used idle workspaces (the device is idle)
             while (b->in_use + head->footprint > b->cfg.budget_bytes && !b->idle.empty()) {
               Workspace* v = b->idle.back();
               b->idle.pop_back();
-              b->in_use -= v->bytes;
               b->stats.workspaces_released += 1;
-              evicted.push_back(v);
+              b->doomed.push_back(v);
             }
-            if (b->in_use + head->footprint <= b->cfg.budget_bytes) {
-              b->in_use += head->footprint;
-              create = true;
-            }
+            evicted.swap(b->doomed);
+            b->freeing = true;
+            break;
           }
           if (ws || create) {
             r = head;
@@ -213,18 +231,31 @@ void worker_main(jfnk_batch* b) {
             break;
           }
         }
-        if (!evicted.empty()) break;  // release them, then look again
         b->cv_work.wait(lk);
       }
       if (!r && b->stop && evicted.empty()) break;
     }
-    for (Workspace* v : evicted) free_workspace(v, st);
+    if (!evicted.empty()) {
+      // admission is closed and nothing runs: these frees stall no one
+      size_t freed = 0;
+      for (Workspace* v : evicted) {
+        freed += v->bytes;
+        free_workspace(v, st);
+      }
+      {
+        std::lock_guard<std::mutex> lk(b->mu);
+        if (b->running > 0) b->stats.frees_while_running += 1;
+        b->in_use -= freed;
+        b->freeing = false;
+      }
+      b->cv_work.notify_all();
+      continue;
+    }
     if (!r) continue;
 
     jfnk_status rc = JFNK_OK;
     if (create) rc = create_workspace(b, *r, st, &ws);
     if (rc == JFNK_OK) rc = run_request(*r, ws, st, stage);
-    Workspace* drop = nullptr;
     {
       std::lock_guard<std::mutex> lk(b->mu);
       r->status = rc;
@@ -239,14 +270,12 @@ void worker_main(jfnk_batch* b) {
       } else if (b->cfg.keep_workspaces && rc != JFNK_ERR_HIP) {
         b->idle.push_front(ws);
       } else {
-        b->in_use -= ws->bytes;
         b->stats.workspaces_released += 1;
-        drop = ws;
+        b->doomed.push_back(ws);  // freed once no request runs
       }
     }
     b->cv_done.notify_all();
     b->cv_work.notify_all();
-    if (drop) free_workspace(drop, st);
   }
   if (st) (void)hipStreamDestroy(st);
 }
@@ -289,7 +318,9 @@ jfnk_status jfnk_batch_destroy(jfnk_batch* b) {
   for (auto& t : b->workers) t.join();
   hipStream_t st = nullptr;
   for (Workspace* w : b->idle) free_workspace(w, st);
+  for (Workspace* w : b->doomed) free_workspace(w, st);
   b->idle.clear();
+  b->doomed.clear();
   delete b;
   return JFNK_OK;
 }

@@ -73,7 +73,8 @@ class BatchConfig(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
                 ("workspaces_created", ctypes.c_longlong), ("workspaces_released", ctypes.c_longlong),
-                ("max_running", ctypes.c_int), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+                ("max_running", ctypes.c_int), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("frees_while_running", ctypes.c_longlong)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

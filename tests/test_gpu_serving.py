@@ -128,8 +128,55 @@ def test_budget_binds_and_results_stay_equal():
     b.close()
     assert st["peak_bytes"] <= budget, st
     assert st["completed"] == len(reqs)
+    # the budget forced releases, and every device free waited for an idle device
+    assert st["workspaces_released"] > 0 and st["frees_while_running"] == 0, st
     for (xa, _), (xm, _) in zip(alone, mixed):
         assert np.array_equal(xa, xm)
+
+
+def test_no_cache_frees_wait_for_idle_device():
+    """keep_workspaces = 0: every finished request's workspace is released, but its
+    device memory goes back only while no request runs; results unchanged."""
+    from paper_2605_13378_amd import Batch
+
+    reqs = small_stream(count=10, seed=4)
+    alone = run_alone(reqs)
+    b = Batch("f32", m=30, max_slots=4, keep_workspaces=False)
+    tickets = []
+    for req in reqs:
+        spec, xp = W.serving_request_inputs(req)
+        tickets.append(b.submit(spec, xp))
+    mixed = [b.wait(t) for t in tickets]
+    st = b.stats()
+    b.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["workspaces_released"] == len(reqs) and st["frees_while_running"] == 0, st
+    for (xa, _), (xm, _) in zip(alone, mixed):
+        assert np.array_equal(xa, xm)
+
+
+def test_full_serving_range_alone_equals_mix():
+    """The serving stream itself (1D Burgers N = 2^8..2^16, Gray-Scott side 2^6..2^10,
+    Gray-Scott 1024^2 included): each result bitwise the same alone and among 8 slots."""
+    from paper_2605_13378_amd import Batch
+
+    reqs = W.serving_stream(count=2000, seed=0, rate=1.0)[:24]
+    sizes = {(r["kind"], r["size"]) for r in reqs}
+    assert ("grayscott", 1024) in sizes and max(r["size"] for r in reqs if r["kind"] == "burgers1d") >= 2 ** 15
+    alone = run_alone(reqs)
+    b = Batch("f32", m=30, max_slots=8)
+    tickets = []
+    for req in reqs:
+        spec, xp = W.serving_request_inputs(req)
+        tickets.append(b.submit(spec, xp))
+    mixed = [b.wait(t) for t in tickets]
+    st = b.stats()
+    b.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["max_running"] >= 2, st
+    for req, (xa, ia), (xm, im) in zip(reqs, alone, mixed):
+        assert ia["rc"] == 0 and im["rc"] == 0, req
+        assert np.array_equal(xa, xm), req
+        assert ia["krylov_iters"] == im["krylov_iters"], req
 
 
 def test_submit_rejects_oversized_and_invalid():
