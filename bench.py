@@ -376,7 +376,7 @@ def kerr_newton(torch, max_newton=50):
     return out
 
 
-def serving_pass(batch, reqs, inputs, rate_scale, saturate):
+def serving_pass(batch, reqs, inputs, rate_scale, saturate, opts=None):
     """Feed `reqs` to `batch` (Poisson arrivals scaled by 1/rate_scale, or all at
     once) and return solves/s and arrival-to-result latency percentiles."""
     import threading
@@ -403,7 +403,7 @@ def serving_pass(batch, reqs, inputs, rate_scale, saturate):
                     break
                 time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
         spec, xp = inputs[i]
-        tickets[i] = batch.submit(spec, xp)
+        tickets[i] = batch.submit(spec, xp, **(opts or {}))
         arrivals.append(target)
         submitted.release()
     th.join()
@@ -458,6 +458,13 @@ def serving_bench(count, slots, budget_gib, seed=0):
         bk.close()
         log(f"[bench] serving saturation with {k} slots: {by_slots[str(k)]}")
     out["saturation_by_slots"] = dict(sorted(by_slots.items(), key=lambda kv: int(kv[0])))
+    # every request on the multi-kernel engine with captured restart cycles (HIP graphs), against
+    # the default engine choice (single-workgroup engine for the requests that fit it)
+    serving_pass(multi, reqs[:warm], inputs[:warm], 1.0, True, opts=dict(engine="graph"))
+    out["saturation_graph_engine"] = serving_pass(multi, reqs, inputs, 1.0, True, opts=dict(engine="graph"))
+    out["saturation_multi_engine"] = serving_pass(multi, reqs, inputs, 1.0, True, opts=dict(engine="multi"))
+    log(f"[bench] serving saturation, graph engine {out['saturation_graph_engine']}, "
+        f"multi-kernel engine {out['saturation_multi_engine']}")
     rows = []
     for lam in (0.5, 1.0, 2.0, 4.0):
         rate = lam * mu1  # requests/s; the stream was drawn at 1 request/s
@@ -505,6 +512,34 @@ def serving_oracle(sample=32, seed=0, workers=None):
                 sample=f"the first {sample} requests of the serving stream (seed {seed}; FP32 tolerances, FP64 "
                        f"arithmetic), one request per worker process at a time; {sum(conv)} converged",
                 seconds=round(el, 2))
+
+
+def graph_engine_row(torch, spec, xp, steps, prec="f32"):
+    """The headline solve on the multi-kernel engine launched directly and with each restart
+    cycle replayed from a captured HIP graph (a solver on a stream of its own: the null stream
+    cannot be captured)."""
+    from paper_2605_13378_amd import Solver
+
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    out = {}
+    with torch.cuda.stream(st):
+        s = Solver(spec, prec, m=30, stream=st)
+        x0 = torch.tensor(xp, dtype=torch.float64, device="cuda")
+        s.set_previous(x0)
+        o = options_for(prec, "ad")
+        for eng in ("multi", "graph"):
+            s.newton_solve(x0, engine=eng, **o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, info = s.newton_solve(x0, engine=eng, **o)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[eng] = dict(solves_per_s=round(steps / el, 2), krylov_iters=info["krylov_iters"])
+        out["cycle_graphs"] = s.cycle_graphs()
+        s.close()
+    return out
 
 
 def bicgstab_rows(torch, spec, xp, x0, steps, budget_s=8.0):
@@ -598,16 +633,17 @@ def suolson_rows(torch, steps, budget_s=3.0, config="suolson"):
     return rows
 
 
-def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50, budget_s=25.0):
+def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50):
     """Paper-form Maxwell-Kerr (2D TE): JVP bandwidth at 512^2 and a frequency sweep at n^2 with
     continuation: the first frequency starts from the Born guess (E = 0, whose first Newton step
     is the Born solve), each later one from the previous converged field; a frequency fails when
     Newton does not reach tol_Newton within max_newton iterations, and the next one then starts
-    again from the Born guess."""
+    again from the Born guess; the run fails when more than 20% of the frequencies fail.  Also
+    the same sweep at 256^2 with a Newton cap of 8."""
     import workloads as W
     from paper_2605_13378_amd import Solver
 
-    out = {"jvp_512": {}, "arnoldi_jvp_512": {}, "sweep": [], "sweep_cslp": []}
+    out = {"jvp_512": {}, "arnoldi_jvp_512": {}}
     spec, x0, src = W.config("maxwell")
     nn = W.n_unknowns(spec)
     for pr in ("f32", "f64"):
@@ -636,25 +672,26 @@ def maxwell_rows(torch, n=16, omegas=(2.0, 2.5, 3.0, 3.5, 4.0), max_newton=50, b
         s.set_preconditioner("none")
         log(f"[bench] maxwell arnoldi jvp 512^2 {pr}: {out['arnoldi_jvp_512']}")
         s.close()
-    for pc, key in (("none", "sweep"), ("cslp", "sweep_cslp")):
-        x = torch.zeros(4 * n * n, dtype=torch.float64, device="cuda")
-        t_start = time.perf_counter()
-        for om in omegas:
-            if time.perf_counter() - t_start > budget_s / 2:
-                break
-            s = Solver(W.maxwell_spec(n, omega=om), "f64", m=30)
-            s.set_previous(None, torch.tensor(W.maxwell_source(n, omega=om), dtype=torch.float64, device="cuda"))
+    # the continuation itself runs in the library (jfnk_frequency_sweep): at n^2 to convergence,
+    # and at the paper's smallest GPU grid (256^2) with a short Newton cap
+    from paper_2605_13378_amd import frequency_sweep
+
+    for ns, cap in ((n, max_newton), (256, 8)):
+        for pc in ("none", "cslp"):
+            key = ("sweep" if ns == n else f"sweep_{ns}") + ("_cslp" if pc == "cslp" else "")
+            specs = [W.maxwell_spec(ns, omega=om) for om in omegas]
+            srcs = [W.maxwell_source(ns, omega=om) for om in omegas]
             t0 = time.perf_counter()
-            xn, info = s.newton_solve(x, max_newton=max_newton, precond=pc)
+            _, infos, failed = frequency_sweep(specs, srcs, "f64", max_newton=cap, precond=pc)
             el = time.perf_counter() - t0
-            ok = info["converged"]
-            row = dict(omega=om, converged=ok, newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
-                       final_rel_res=info["rel_res"][-1], seconds=round(el, 3),
-                       start="previous" if bool(x.abs().sum() > 0) else "born")
-            out[key].append(row)
-            log(f"[bench] maxwell sweep {n}^2 precond {pc}: {row}")
-            x = xn if ok else torch.zeros_like(x)
-            s.close()
+            rows, prev_ok = [], False
+            for om, inf in zip(omegas, infos):
+                rows.append(dict(omega=om, start="previous" if prev_ok else "born", converged=inf["converged"],
+                                 newton_iters=inf["newton_iters"], krylov_iters=inf["krylov_iters"],
+                                 final_rel_res=inf["rel_res"][-1]))
+                prev_ok = inf["converged"]
+            out[key] = dict(grid=ns, max_newton=cap, rows=rows, run_failed=failed, seconds=round(el, 3))
+            log(f"[bench] maxwell sweep {ns}^2 precond {pc}: {out[key]}")
     return out
 
 
@@ -884,6 +921,11 @@ def main():
         copy_ref[f"{mb}MiB"] = copy_ceiling_hbm(torch, mb << 20)
         log(f"[bench] copy reference {mb} MiB: {copy_ref[f'{mb}MiB']}")
 
+    # ---- the same solve with captured restart cycles (HIP graph engine) ----
+    graph_row = None if args.no_variants else graph_engine_row(torch, spec, xp, args.steps, prec)
+    if graph_row:
+        log(f"[bench] graph engine: {graph_row}")
+
     # ---- variants: AD vs FD, FP64 vs FP32 (solves/s, iterations) -----------
     variants = {}
     if not args.no_variants:
@@ -1009,6 +1051,7 @@ def main():
         "copy_reference_hbm": copy_ref,
         "copy_calibration_gbs": copy_gbs,
         "variants": variants,
+        "graph_engine": graph_row,
         "bicgstab_newton": bicg,
         "reaction_diffusion_512": rd,
         "burgers2d_256_tgv_dsl": pb,

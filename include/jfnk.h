@@ -180,8 +180,23 @@ typedef enum { JFNK_KRYLOV_GMRES = 0, JFNK_KRYLOV_BICGSTAB = 1, JFNK_KRYLOV_CG =
  *          every vector in LDS (the latency path for small problems: about
  *          n (m + 6) * sizeof(working type) + 16 n bytes must fit the
  *          device's LDS per workgroup; FP64 and FP32 only).  Requesting it
- *          for a problem that does not fit returns JFNK_ERR_ARG. */
-typedef enum { JFNK_ENGINE_AUTO = 0, JFNK_ENGINE_MULTI_KERNEL = 1, JFNK_ENGINE_SINGLE_WORKGROUP = 2 } jfnk_engine;
+ *          for a problem that does not fit returns JFNK_ERR_ARG;
+ *   MULTI_KERNEL_GRAPH: the multi-kernel engine with each GMRES restart
+ *          cycle (its m Arnoldi steps and the V y update) launched as one
+ *          HIP graph, captured on first use per launch configuration and
+ *          kept by the solver: one host launch per cycle instead of two or
+ *          three per step, all m steps queued at once (steps after the one
+ *          that stopped the cycle leave at once on the device), the same
+ *          kernels in the same order, so the same results bit for bit as
+ *          MULTI_KERNEL.  GMRES only (JFNK_ERR_ARG otherwise); a solver on the
+ *          null stream, which cannot be captured, or with profiling on runs
+ *          the cycles directly. */
+typedef enum {
+  JFNK_ENGINE_AUTO = 0,
+  JFNK_ENGINE_MULTI_KERNEL = 1,
+  JFNK_ENGINE_SINGLE_WORKGROUP = 2,
+  JFNK_ENGINE_MULTI_KERNEL_GRAPH = 3
+} jfnk_engine;
 
 #define JFNK_MAX_ITERS 64
 
@@ -288,6 +303,31 @@ jfnk_status jfnk_cg(jfnk_solver* s, const void* x, const void* rhs, void* dx, do
  * three cases. */
 jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_options* opts,
                               jfnk_info* info);
+
+/* Number of captured GMRES-cycle graphs the solver holds (one per launch
+ * configuration the MULTI_KERNEL_GRAPH engine has met; released by
+ * jfnk_destroy); -1 for a null solver. */
+int jfnk_cycle_graphs(const jfnk_solver* s);
+
+/* Frequency continuation of a frequency-domain problem (paper, Section 3.1:
+ * the outer loop advances the angular frequency; Section 3.2 and Appendix
+ * A.4: the initial guess is the Born solution, the problem linearized at
+ * E = 0, i.e. the first Newton step from E = 0; Section 3.4: a run fails when
+ * more than 20% of its frequency steps do not reach the Newton tolerance).
+ * problems[0..count-1] are the frequencies in order (one unknown count n for
+ * all; JFNK_ERR_ARG otherwise); sources[i] (nullable array, nullable
+ * entries) host FP64 sources of n entries.  Frequency i starts from
+ * frequency i-1's converged field; the first, and every frequency after one
+ * that did not converge (cap, non-finite value or breakdown), starts from
+ * E = 0.  fields (host, count * n FP64, frequency-major) receives each
+ * frequency's last iterate, infos (nullable, count entries) each Newton
+ * record, *run_failed the 20% rule.  One solver per frequency is created and
+ * destroyed on hip_stream (device memory: one solver plus 2 n doubles at a
+ * time).  Returns JFNK_OK when every frequency ran (converged or not), else
+ * the first argument, allocation or HIP error. */
+jfnk_status jfnk_frequency_sweep(const jfnk_problem* problems, const double* const* sources, int count,
+                                 int precision, const jfnk_options* opts, void* hip_stream, double* fields,
+                                 jfnk_info* infos, int* run_failed);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the Newton

@@ -20,6 +20,8 @@ Newton-Krylov Solvers via Automatic Differentiation"):
   problem (Appendix A.4), applied on the right of GMRES.
 * ``newton``: inexact Newton with backtracking line search and the
   failure classification of Section 3.4.
+* ``sweep``: the Maxwell frequency continuation (Section 3.1's outer loop,
+  the Born start of Appendix A.4, the 20% failure rule of Section 3.4).
 
 Parity pins: every function here is checked by ``tests/test_oracle_*.py``
 against closed forms, independent hand-derived Jacobians, complex-step
@@ -29,7 +31,7 @@ the paper does not fix: they are a reading, pinned only by the Armijo property
 (parity of the constants themselves unpinned).
 """
 
-from . import bicgstab, cg, dual, gmres, jvp, newton, precond, problems  # noqa: F401
+from . import bicgstab, cg, dual, gmres, jvp, newton, precond, problems, sweep  # noqa: F401
 from .bicgstab import BicgstabInfo, bicgstab as bicgstab_solve  # noqa: F401
 from .cg import CgInfo, cg as cg_solve  # noqa: F401
 from .gmres import GmresInfo, gmres as gmres_solve  # noqa: F401
@@ -37,3 +39,4 @@ from .jvp import EPS_MACH, EPS_NORMALIZED, EPS_PAPER, fd_step, jvp_ad, jvp_fd  #
 from .newton import NewtonInfo, NewtonOptions, newton_solve, run_failed, step_failed  # noqa: F401
 from .precond import cslp_diagonal, cslp_solve  # noqa: F401
 from .problems import Problem, residual  # noqa: F401
+from .sweep import SweepInfo, frequency_sweep  # noqa: F401

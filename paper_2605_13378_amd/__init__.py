@@ -22,6 +22,7 @@ from .jfnk import (  # noqa: F401
     default_options,
     exported_symbols,
     footprint_bytes,
+    frequency_sweep,
     lib,
     make_problem,
     newton_solve_noalloc,

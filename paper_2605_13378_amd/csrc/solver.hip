@@ -119,6 +119,14 @@ struct jfnk_solver {
   std::string err;
   bool prof = false;
   int cur_step = -1;
+  // MULTI_KERNEL_GRAPH engine: the Arnoldi steps and V y update of a restart
+  // cycle, captured once per launch configuration and replayed
+  struct CycleGraph {
+    long long key[8];
+    hipGraphExec_t exec;
+  };
+  bool graph = false;  // the current solve replays captured cycles
+  std::vector<CycleGraph> graphs;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   long long p_count[kNumProf] = {};
@@ -401,6 +409,91 @@ struct Impl {
 
   static VT* basis(jfnk_solver* s, int i) { return static_cast<VT*>(s->V) + (long long)i * s->vstride; }
 
+  // Arnoldi step j of a cycle: the JVP of basis vector j with the first
+  // projection fused in, then the Gram-Schmidt pass(es).
+  static jfnk_status arnoldi_step(jfnk_solver* s, const T* x, int j, int mode, const EpsSpec& eps_arnoldi,
+                                  bool lagged, bool pre) {
+    T* w = static_cast<T*>(s->w);
+    s->cur_step = j;
+    const int K = j + 1;
+    int nb_jvp = 0;  // the JVP carries the first projection (pass A)
+    JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged, pre));
+    KArgs<T, VT> ka{s->npad, basis(s, 0), s->vstride, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1),
+                    (double)(K + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
+    if (lagged) {
+      // one update pass: v_j completed, the next vector projected once
+      ProfScope ps(s, PK_D, (double)s->n * ((K + 2) * sizeof(VT) + sizeof(T)));
+      JFNK_HIP(s, launch_dcgs<T, VT>(ka, dcgs_grid(s, K), s->stream));
+    } else {
+      {
+        ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
+        JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, cgs_grid(s, K), s->stream));
+      }
+      ka.in = parts(s, 1, cgs_grid(s, K));
+      ka.out = sink(s, 2);
+      ProfScope ps(s, PK_C, (double)s->n * (K * sizeof(VT) + sizeof(T) + sizeof(VT)));
+      JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, cgs_grid(s, K), s->stream));
+    }
+    return JFNK_OK;
+  }
+
+  // End of a cycle whose last enqueued step is jmax: the V y update.
+  static jfnk_status cycle_end(jfnk_solver* s, int jmax, int first, int m, bool lagged, int kgrid) {
+    VyArgs<T, VT> va{s->npad, basis(s, 0), s->vstride, static_cast<T*>(s->dx), first, jmax, s->ctl,
+                     lagged ? parts(s, 1, dcgs_grid(s, jmax >= 0 ? jmax + 1 : 1))
+                            : parts(s, 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)),
+                     sink(s, 4), s->dflags,
+                     lagged ? 1 : 0, (double)(jmax + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
+    ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
+    JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
+    return JFNK_OK;
+  }
+
+  // The captured graph of one cycle's m Arnoldi steps and V y update for
+  // this launch configuration (every kernel argument is fixed by it: the
+  // solver's buffers, m, the JVP kind and step rule, the Gram-Schmidt form,
+  // the preconditioner and whether dx is overwritten or accumulated),
+  // captured on the first use and kept until the solver is destroyed.
+  static jfnk_status cycle_graph(jfnk_solver* s, const T* x, int m, int mode, const EpsSpec& eps, bool lagged,
+                                 bool pre, int first, int kgrid, hipGraphExec_t* out) {
+    long long fe = 0;
+    std::memcpy(&fe, &eps.fixed, sizeof(fe));
+    const long long key[8] = {(long long)(uintptr_t)x, m, mode, fe, eps.rule, lagged ? 1 : 0, pre ? 1 : 0, first};
+    for (const auto& g : s->graphs)
+      if (std::equal(key, key + 8, g.key)) {
+        *out = g.exec;
+        return JFNK_OK;
+      }
+    JFNK_HIP(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    jfnk_status st = JFNK_OK;
+    for (int j = 0; j < m && st == JFNK_OK; ++j) st = arnoldi_step(s, x, j, mode, eps, lagged, pre);
+    s->cur_step = -1;
+    if (st == JFNK_OK) st = cycle_end(s, m - 1, first, m, lagged, kgrid);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s->stream, &g);  // ends the capture on every path
+    if (st != JFNK_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) {
+      s->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+      return JFNK_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      s->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+      return JFNK_ERR_HIP;
+    }
+    jfnk_solver::CycleGraph cg{};
+    std::copy(key, key + 8, cg.key);
+    cg.exec = exec;
+    s->graphs.push_back(cg);
+    *out = exec;
+    return JFNK_OK;
+  }
+
   // Restarted GMRES(m) on J(x) dx = sign * R (R internal, padded), dx internal.
   // With `pre` (right preconditioning by the problem's diagonal M, frozen at
   // x) every JVP of the solve is applied to M^{-1} times its vector, so the
@@ -413,6 +506,9 @@ struct Impl {
     go = GOut{};
     T* dxi = static_cast<T*>(s->dx);
     T* w = static_cast<T*>(s->w);
+    // captured cycles need a stream of their own (the null stream cannot be
+    // captured) and no per-kernel timing events
+    const bool use_graph = s->graph && s->stream != nullptr && !s->prof;
     const int kgrid = krylov_grid(s, KVEC);
     const int sgrid = stream_grid(s, KVEC);
     const EpsSpec eps_arnoldi = eps_spec(s, fixed_eps, eps_rule, nullptr);  // ||v_j|| = 1
@@ -478,43 +574,28 @@ struct Impl {
       // delayed-second-pass form runs two kernels per step (JVP with the
       // first projection and the completion of column j-1 in its prologue,
       // then one update pass) with the same flag protocol.
+      if (use_graph) {
+        // the whole cycle from its captured graph: every step is launched;
+        // steps after the one that stopped the cycle find the stop state in
+        // the control block and leave at once (as the up to two steps the
+        // direct path queues ahead do)
+        hipGraphExec_t ge = nullptr;
+        JFNK_TRY(cycle_graph(s, x, m, mode, eps_arnoldi, lagged, pre, updated ? 0 : 1, kgrid, &ge));
+        JFNK_HIP(s, hipGraphLaunch(ge, s->stream));
+        updated = true;
+        pending_vy = true;
+        continue;
+      }
       int jmax = -1;
       for (int j = 0; j < m; ++j) {
-        s->cur_step = j;
-        const int K = j + 1;
         if (j >= 1) flags[j - 1] = -1;
-        int nb_jvp = 0;  // the JVP carries the first projection (pass A)
-        JFNK_TRY(jvp<VT>(s, x, basis(s, j), nullptr, w, nullptr, mode, eps_arnoldi, j, &nb_jvp, lagged, pre));
-        KArgs<T, VT> ka{s->npad, basis(s, 0), s->vstride, w, basis(s, K), K, s->ctl, parts(s, 0, nb_jvp), sink(s, 1),
-                        (double)(K + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
-        if (lagged) {
-          // one update pass: v_j completed, the next vector projected once
-          ProfScope ps(s, PK_D, (double)s->n * ((K + 2) * sizeof(VT) + sizeof(T)));
-          JFNK_HIP(s, launch_dcgs<T, VT>(ka, dcgs_grid(s, K), s->stream));
-        } else {
-          {
-            ProfScope ps(s, PK_B, (double)s->n * (K * sizeof(VT) + 2 * sizeof(T)));
-            JFNK_HIP(s, launch_cgs<T, VT>(PASS_B, ka, cgs_grid(s, K), s->stream));
-          }
-          ka.in = parts(s, 1, cgs_grid(s, K));
-          ka.out = sink(s, 2);
-          ProfScope ps(s, PK_C, (double)s->n * (K * sizeof(VT) + sizeof(T) + sizeof(VT)));
-          JFNK_HIP(s, launch_cgs<T, VT>(PASS_C, ka, cgs_grid(s, K), s->stream));
-        }
+        JFNK_TRY(arnoldi_step(s, x, j, mode, eps_arnoldi, lagged, pre));
         jmax = j;
         if (j >= 2 && (!wait_flag(s, flags, j - 2) || flags[j - 2] != kRunning)) break;
       }
       s->cur_step = -1;
       flags[jmax] = -1;
-      {
-        VyArgs<T, VT> va{s->npad, basis(s, 0), s->vstride, dxi, updated ? 0 : 1, jmax, s->ctl,
-                         lagged ? parts(s, 1, dcgs_grid(s, jmax >= 0 ? jmax + 1 : 1))
-                                : parts(s, 2, cgs_grid(s, jmax >= 0 ? jmax + 1 : 1)),
-                         sink(s, 4), s->dflags,
-                         lagged ? 1 : 0, (double)(jmax + 3) * s->n * sizeof(VT) > kNtBasisBytes ? 1 : 0};
-        ProfScope ps(s, PK_VY, 0.0);  // bytes filled in once k is known
-        JFNK_HIP(s, launch_vy<T, VT>(va, m, kgrid, s->stream));
-      }
+      JFNK_TRY(cycle_end(s, jmax, updated ? 0 : 1, m, lagged, kgrid));
       updated = true;
       pending_vy = true;
     }
@@ -817,8 +898,9 @@ struct Impl {
       s->err = "the single-workgroup engine needs FP64 or FP32 and a problem that fits in LDS";
       return JFNK_ERR_ARG;
     }
-    if (o.krylov == JFNK_KRYLOV_GMRES && o.engine != JFNK_ENGINE_MULTI_KERNEL && o.precond == JFNK_PRECOND_NONE &&
-        fused_fits(s, o.m))
+    if (o.krylov == JFNK_KRYLOV_GMRES &&
+        (o.engine == JFNK_ENGINE_AUTO || o.engine == JFNK_ENGINE_SINGLE_WORKGROUP) &&
+        o.precond == JFNK_PRECOND_NONE && fused_fits(s, o.m))
       return newton_fused(s, x_user, o, info);
     const long long n = s->n;
     const bool f64 = std::is_same<T, double>::value;
@@ -1065,6 +1147,8 @@ jfnk_status malloc_dev(jfnk_solver* s, T** p, size_t bytes) {
 }
 
 void release(jfnk_solver* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
   void* bufs[] = {s->V, s->w, s->R, s->dx, s->F, s->Ft, s->xw, s->xwt, s->b, s->x64, s->x64t, s->tmp64,
                   s->parts, s->ctl};
   for (void* p : bufs)
@@ -1615,10 +1699,14 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
   if (o.m < 1 || o.m > s->m || o.max_newton < 0 || o.max_newton > JFNK_MAX_ITERS || o.max_restarts < 0 ||
       o.ls_max_backtracks < 0 || (o.mode != JFNK_JVP_AD && o.mode != JFNK_JVP_FD) ||
       (o.eps_rule != JFNK_EPS_PAPER && o.eps_rule != JFNK_EPS_NORMALIZED) || !(o.tol_krylov >= 0.0) ||
-      o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_SINGLE_WORKGROUP ||
+      o.engine < JFNK_ENGINE_AUTO || o.engine > JFNK_ENGINE_MULTI_KERNEL_GRAPH ||
       o.krylov < JFNK_KRYLOV_GMRES || o.krylov > JFNK_KRYLOV_CG || o.orth < JFNK_ORTH_CGS2 ||
       o.orth > JFNK_ORTH_DCGS2) {
     s->err = "invalid options";
+    return JFNK_ERR_ARG;
+  }
+  if (o.engine == JFNK_ENGINE_MULTI_KERNEL_GRAPH && o.krylov != JFNK_KRYLOV_GMRES) {
+    s->err = "the graph engine replays GMRES cycles (BiCGSTAB and CG run on the multi-kernel engine)";
     return JFNK_ERR_ARG;
   }
   if (o.krylov != JFNK_KRYLOV_GMRES && !short_recurrence_fits(s, o.krylov, &s->err)) return JFNK_ERR_ARG;
@@ -1630,12 +1718,14 @@ jfnk_status jfnk_newton_solve(jfnk_solver* s, double* x_inout, const jfnk_option
   std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   jfnk_status st;
+  s->graph = o.engine == JFNK_ENGINE_MULTI_KERNEL_GRAPH;
   if (s->prec == JFNK_F64)
     st = Impl<double, double>::newton(s, x_inout, o, info);
   else if (s->prec == JFNK_F32)
     st = Impl<float, float>::newton(s, x_inout, o, info);
   else
     st = Impl<float, __half>::newton(s, x_inout, o, info);
+  s->graph = false;
   info->status = st;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
@@ -1727,7 +1817,8 @@ jfnk_status jfnk_newton_solve_noalloc(const jfnk_problem* problem, int precision
     set_free_error("invalid options");
     return JFNK_ERR_ARG;
   }
-  if (o.krylov != JFNK_KRYLOV_GMRES || o.engine == JFNK_ENGINE_MULTI_KERNEL || o.precond != JFNK_PRECOND_NONE) {
+  if (o.krylov != JFNK_KRYLOV_GMRES || o.engine == JFNK_ENGINE_MULTI_KERNEL ||
+      o.engine == JFNK_ENGINE_MULTI_KERNEL_GRAPH || o.precond != JFNK_PRECOND_NONE) {
     set_free_error("the allocation-free solve runs GMRES on the single-workgroup engine, unpreconditioned");
     return JFNK_ERR_ARG;
   }
@@ -1815,6 +1906,77 @@ jfnk_status jfnk_profile_reset(jfnk_solver* s) {
     s->p_bytes[i] = 0.0;
   }
   return JFNK_OK;
+}
+
+int jfnk_cycle_graphs(const jfnk_solver* s) { return s ? (int)s->graphs.size() : -1; }
+
+jfnk_status jfnk_frequency_sweep(const jfnk_problem* problems, const double* const* sources, int count,
+                                 int precision, const jfnk_options* opts, void* hip_stream, double* fields,
+                                 jfnk_info* infos, int* run_failed) {
+  if (!problems || count < 1 || !opts || !fields || !run_failed) {
+    set_free_error("jfnk_frequency_sweep: null argument or count < 1");
+    return JFNK_ERR_ARG;
+  }
+  const size_t n = jfnk_problem_size(&problems[0]);
+  for (int i = 0; i < count; ++i)
+    if (n == 0 || jfnk_problem_size(&problems[i]) != n) {
+      set_free_error("jfnk_frequency_sweep: the problems differ in size or are invalid");
+      return JFNK_ERR_ARG;
+    }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t vb = n * sizeof(double);
+  double* d_x = nullptr;
+  double* d_src = nullptr;
+  if (hipMalloc(&d_x, vb) != hipSuccess || hipMalloc(&d_src, vb) != hipSuccess) {
+    if (d_x) (void)hipFree(d_x);
+    set_free_error("jfnk_frequency_sweep: device allocation failed");
+    return JFNK_ERR_OOM;
+  }
+  const std::vector<double> zeros(n, 0.0);
+  jfnk_status out = JFNK_OK;
+  int failed = 0;
+  bool have_prev = false;  // d_x holds the previous frequency's converged field
+  for (int i = 0; i < count && out == JFNK_OK; ++i) {
+    jfnk_solver* s = nullptr;
+    jfnk_status rc = jfnk_create(&problems[i], precision, opts->m, hip_stream, &s);
+    if (rc != JFNK_OK) {
+      out = rc;
+      break;
+    }
+    const double* src = (sources && sources[i]) ? sources[i] : nullptr;
+    if (src && hipMemcpyAsync(d_src, src, vb, hipMemcpyHostToDevice, st) != hipSuccess) rc = JFNK_ERR_HIP;
+    if (rc == JFNK_OK) rc = jfnk_set_previous(s, nullptr, src ? d_src : nullptr);
+    if (rc == JFNK_OK && !have_prev &&
+        hipMemcpyAsync(d_x, zeros.data(), vb, hipMemcpyHostToDevice, st) != hipSuccess)
+      rc = JFNK_ERR_HIP;
+    jfnk_info info{};
+    if (rc == JFNK_OK) {
+      rc = jfnk_newton_solve(s, d_x, opts, &info);
+      const bool ran = rc == JFNK_OK || rc == JFNK_ERR_NOT_CONVERGED || rc == JFNK_ERR_NONFINITE ||
+                       rc == JFNK_ERR_BREAKDOWN;
+      if (ran) {
+        if (hipMemcpyAsync(fields + (size_t)i * n, d_x, vb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          rc = JFNK_ERR_HIP;
+        } else {
+          if (infos) infos[i] = info;
+          const bool conv = rc == JFNK_OK && info.converged;
+          failed += conv ? 0 : 1;
+          have_prev = conv;
+          rc = JFNK_OK;
+        }
+      }
+    }
+    if (rc != JFNK_OK) {
+      set_free_error(jfnk_last_error(s));
+      out = rc;
+    }
+    (void)jfnk_destroy(s);
+  }
+  (void)hipFree(d_x);
+  (void)hipFree(d_src);
+  if (out == JFNK_OK) *run_failed = 5 * failed > count ? 1 : 0;  // more than 20% of the frequencies
+  return out;
 }
 
 }  // extern "C"

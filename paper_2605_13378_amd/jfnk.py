@@ -21,7 +21,7 @@ PROBLEM_IDS = {"burgers1d": 0, "burgers2d": 1, "grayscott": 2, "kerr": 3, "rd2d"
 PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 MODES = {"ad": 0, "fd": 1}
 EPS_RULES = {"paper": 0, "normalized": 1}
-ENGINES = {"auto": 0, "multi": 1, "single": 2}
+ENGINES = {"auto": 0, "multi": 1, "single": 2, "graph": 3}
 KRYLOV = {"gmres": 0, "bicgstab": 1, "cg": 2}
 ORTH = {"cgs2": 0, "dcgs2": 1}
 PRECOND = {"none": 0, "cslp": 1}
@@ -115,6 +115,10 @@ _SIGNATURES = [
     ("jfnk_newton_solve_noalloc", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
                                                  ctypes.POINTER(Info), ctypes.c_void_p]),
+    ("jfnk_cycle_graphs", ctypes.c_int, [ctypes.c_void_p]),
+    ("jfnk_frequency_sweep", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                            ctypes.c_int, ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(Info), ctypes.POINTER(ctypes.c_int)]),
     ("jfnk_default_options", None, [ctypes.c_int, ctypes.POINTER(Options)]),
     ("jfnk_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("jfnk_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
@@ -284,6 +288,10 @@ class Solver:
                                    EPS_RULES[eps_rule]))
         return (jv, F) if want_F else jv
 
+    def cycle_graphs(self) -> int:
+        """Captured GMRES-cycle graphs this solver holds (MULTI_KERNEL_GRAPH engine)."""
+        return int(lib().jfnk_cycle_graphs(self._h))
+
     def set_orthogonalization(self, orth: str):
         """Gram-Schmidt form of later gmres() calls: 'cgs2' or 'dcgs2' (the default)."""
         self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
@@ -416,6 +424,33 @@ def newton_solve_noalloc(spec: dict, precision: str, x_prev, source, x_inout, hi
     if rc not in (0, 4, 6):
         raise JfnkError(rc, lib().jfnk_last_error(None).decode())
     return info.as_dict()
+
+
+def frequency_sweep(specs: list, sources: list, precision: str = "f64", stream=None, **opts):
+    """jfnk_frequency_sweep: the problems of `specs` (one per frequency, in order)
+    with their host FP64 sources (numpy, or None) by frequency continuation.
+    Returns (fields: numpy array [count, n], infos: list of dicts, run_failed)."""
+    import numpy as np
+    import torch
+
+    count = len(specs)
+    n = problem_size(specs[0])
+    probs = (Problem * count)(*[make_problem(sp) for sp in specs])
+    srcs = [None if f is None else np.ascontiguousarray(f, dtype=np.float64) for f in sources]
+    for f in srcs:
+        if f is not None and f.size != n:
+            raise ValueError(f"every source must have {n} entries")
+    ptrs = (ctypes.c_void_p * count)(*[None if f is None else f.ctypes.data for f in srcs])
+    fields = np.empty((count, n), dtype=np.float64)
+    infos = (Info * count)()
+    failed = ctypes.c_int(0)
+    o = default_options(precision, **opts)
+    st = torch.cuda.current_stream() if stream is None else stream
+    rc = lib().jfnk_frequency_sweep(probs, ptrs, count, PRECISIONS[precision], ctypes.byref(o),
+                                    ctypes.c_void_p(st.cuda_stream), fields.ctypes.data, infos, ctypes.byref(failed))
+    if rc != 0:
+        raise JfnkError(rc, lib().jfnk_last_error(None).decode())
+    return fields, [i.as_dict() for i in infos], bool(failed.value)
 
 
 class Batch:

@@ -57,3 +57,28 @@ def gpu_bounds(name):
     """(rho bound, x bound) for a GPU-vs-oracle per-iterate comparison in FP64."""
     _, _, _, _, crho, cx, _ = case(name)
     return max(1e-12, FACTOR * crho), max(1e-12, FACTOR * cx)
+
+
+# Frequency continuation (oracle.frequency_sweep) of the Maxwell-Kerr problem on 16 x 16 at
+# omega = 2.5, 3.0, 3.5, 4.0 (Born start at 2.5; FP64 tolerances, Newton cap 20):
+# name -> (preconditioner, ceiling of max_i ||E_i - E'_i|| / ||E_i||, ceiling of the
+# per-frequency Krylov-count change).  Measured: fields 1.25e-10 / 1.22e-10, counts 89 / 169.
+SWEEP_OMEGAS = (2.5, 3.0, 3.5, 4.0)
+SWEEP_CASES = {
+    "maxwell16_sweep": ("none", 2.5e-10, 200),
+    "maxwell16_sweep_cslp": ("cslp", 2.5e-10, 200),
+}
+
+
+def sweep_case(name, n=16):
+    """(problem specs, sources, oracle options dict, field ceiling, count ceiling)."""
+    pc, cx, ck = SWEEP_CASES[name]
+    specs = [W.maxwell_spec(n, omega=om) for om in SWEEP_OMEGAS]
+    srcs = [W.maxwell_source(n, omega=om) for om in SWEEP_OMEGAS]
+    return specs, srcs, dict(max_newton=20, precond=pc), cx, ck
+
+
+def sweep_gpu_bounds(name):
+    """(field bound, Krylov-count slack) of a GPU-vs-oracle sweep comparison."""
+    _, _, _, cx, ck = sweep_case(name)
+    return FACTOR * cx, int(FACTOR * ck)

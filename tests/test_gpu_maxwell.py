@@ -17,7 +17,7 @@ import pytest
 
 import workloads as W
 from gpu_cases import dev, gpu_available, host, wdtype
-from oracle import Problem, jvp_ad
+from oracle import NewtonOptions, Problem, jvp_ad
 from test_gpu_solver import compare_newton, solver
 
 pytestmark = pytest.mark.gpu
@@ -70,3 +70,41 @@ def test_newton_maxwell_tiny_grid_at_contract_bound(n, pre, prec, tol):
     info, ref = compare_newton(spec, np.zeros(4 * n * n), src, prec, "ad", tol, precond=pre, orth="dcgs2",
                                max_newton=20, krylov_slack=0.3, **kw)
     assert info["converged"]
+
+
+@pytest.mark.parametrize("name", ["maxwell16_sweep", "maxwell16_sweep_cslp"])
+def test_frequency_sweep_matches_oracle(name):
+    """jfnk_frequency_sweep against the oracle's sweep (Born start, continuation from each
+    converged field, the 20% run rule): the same converged flags, Newton counts and run
+    outcome, every frequency's field within FACTOR times the oracle's own summation-order
+    spread (order_spread.SWEEP_CASES), Krylov counts within the same multiple of theirs."""
+    import order_spread as OS
+    from oracle import frequency_sweep as oracle_sweep
+    from paper_2605_13378_amd import frequency_sweep
+
+    specs, srcs, opts, _, _ = OS.sweep_case(name)
+    tol_x, kslack = OS.sweep_gpu_bounds(name)
+    fields, infos, failed = frequency_sweep(specs, srcs, "f64", **opts)
+    probs = [Problem.from_spec(sp) for sp in specs]
+    ref, ri = oracle_sweep(probs, srcs, NewtonOptions.for_precision("f64", **opts))
+    assert failed == ri.failed
+    assert [i["converged"] for i in infos] == ri.converged
+    assert [i["newton_iters"] for i in infos] == [s.newton_iters for s in ri.steps]
+    for k, (f, r) in enumerate(zip(fields, ref)):
+        assert np.linalg.norm(f - r) <= tol_x * np.linalg.norm(r), (k, np.linalg.norm(f - r) / np.linalg.norm(r))
+    for i, s in zip(infos, ri.steps):
+        assert abs(i["krylov_iters"] - s.krylov_iters) <= kslack, (i["krylov_iters"], s.krylov_iters)
+
+
+def test_frequency_sweep_failure_hand_over():
+    """A Newton cap of 1 makes every frequency fail: each then starts from the Born guess, so
+    every field equals that frequency's own one-step solve from E = 0, and the run fails."""
+    from paper_2605_13378_amd import frequency_sweep
+
+    specs = [W.maxwell_spec(8, omega=om) for om in (2.5, 3.0, 3.5)]
+    srcs = [W.maxwell_source(8, omega=om) for om in (2.5, 3.0, 3.5)]
+    fields, infos, failed = frequency_sweep(specs, srcs, "f64", max_newton=1)
+    assert failed and not any(i["converged"] for i in infos)
+    for k in range(3):
+        alone, ia, _ = frequency_sweep(specs[k:k + 1], srcs[k:k + 1], "f64", max_newton=1)
+        assert np.array_equal(alone[0], fields[k]) and ia[0]["krylov_iters"] == infos[k]["krylov_iters"]
