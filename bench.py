@@ -39,8 +39,8 @@ CONFIG_NAME = "grayscott-1024x1024-backward-euler"
 # kernel sources and launch shapes they were taken with (hash of the device headers and
 # of the host file that sizes the grids).
 MEASURED_TRAFFIC = {
-    "jvp_ad": {"sources": "8e099e13502e9c76", "orth": "dcgs2", "ratio": 0.956},
-    "dcgs_update": {"sources": "8e099e13502e9c76", "orth": "dcgs2", "ratio": 0.892},
+    "jvp_ad": {"sources": "de14223660857823", "orth": "dcgs2", "ratio": 1.037},
+    "dcgs_update": {"sources": "de14223660857823", "orth": "dcgs2", "ratio": 0.956},
 }
 
 def kernel_sources_hash() -> str:
@@ -801,6 +801,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-budget-gib", type=float, default=16.0)
+    ap.add_argument("--cycle-trace", default="", metavar="SIZES",
+                    help="only run full GMRES(30) cycles (30 Arnoldi steps, no early stop) on Gray-Scott "
+                         "grids of these comma-separated sides, 6 per side, in --precision, for per-step "
+                         "kernel traces; prints one JSON line and exits")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run a plain device copy of MB megabytes 3 times first (HBM counter calibration)")
     args = ap.parse_args()
@@ -820,6 +824,27 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.cycle_trace:
+        from paper_2605_13378_amd import Solver
+
+        wd = torch.float64 if args.precision == "f64" else torch.float32
+        done = {}
+        for side in (int(v) for v in args.cycle_trace.split(",")):
+            spec_c, xp_c, _ = W.config("grayscott", n=side)
+            sc = Solver(spec_c, args.precision, m=30)
+            sc.set_previous(torch.tensor(xp_c, dtype=torch.float64, device="cuda"))
+            sc.set_orthogonalization(args.orth)
+            xc = torch.tensor(xp_c, dtype=wd, device="cuda")
+            rc = torch.tensor(W.random_vector(len(xp_c), 5), dtype=wd, device="cuda")
+            for _ in range(6):
+                _, info_c = sc.gmres(xc, rc, m=30, tol=1e-300, max_restarts=1)
+            torch.cuda.synchronize()
+            done[side] = info_c["krylov_iters"]
+            log(f"[bench] cycle trace {side}^2 {args.precision}: {done[side]} steps per cycle")
+            sc.close()
+        print(json.dumps({"cycle_trace": done, "precision": args.precision, "orth": args.orth}))
+        return
 
     copy_gbs = None
     if args.copy_calibration > 0:

@@ -1139,8 +1139,11 @@ jfnk_status malloc_dev(jfnk_solver* s, T** p, size_t bytes) {
     return JFNK_ERR_OOM;
   }
   *p = static_cast<T*>(q);
-  if (hipMemset(q, 0, bytes) != hipSuccess) {
-    s->err = "hipMemset failed";
+  // zeroed on the solver's stream (jfnk_create synchronizes it before
+  // returning): a synchronous memset would be a null-stream operation, which
+  // invalidates a graph another thread is capturing at the same time
+  if (hipMemsetAsync(q, 0, bytes, s->stream) != hipSuccess) {
+    s->err = "hipMemsetAsync failed";
     return JFNK_ERR_HIP;
   }
   return JFNK_OK;

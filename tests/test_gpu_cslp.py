@@ -9,8 +9,8 @@ Parity contract:
     paper's step: rounding-bound on this operator, see the test), 2e-4 (FP32
     AD, oracle in FP64 on the FP32-rounded inputs) of the oracle's; the GPU's true residual norm equals the oracle's;
   * the same at the full 512^2 grid in FP32 (the JVP-row shape);
-  * Newton from E = 0 with the preconditioner, per iterate, as the
-    unpreconditioned Maxwell tests (1e-6: Krylov-tolerance band);
+  * Newton from E = 0 with the preconditioner, per iterate, at FACTOR times
+    the oracle's own summation-order spread on the same case (order_spread);
   * the configurations the library rejects, and AUTO running the
     multi-kernel engine for a problem the single-workgroup engine would take.
 """
@@ -142,13 +142,13 @@ def test_newton_maxwell_cslp_from_born(orth):
 
 
 def test_newton_maxwell_cslp_auto_engine_runs_multi_kernel():
-    spec = W.maxwell_spec(12, omega=2.5, ny=10)
-    src = W.maxwell_source(12, omega=2.5, ny=10)
-    # (tolerances above the rounding-sensitive regime: at tol_krylov 1e-10 the
-    # oracle's own two Gram-Schmidt forms differ by 12% in the second solve)
-    info, ref = compare_newton(spec, np.zeros(4 * 12 * 10), src, "f64", "ad", 1e-6, engine="auto", orth="dcgs2",
-                               precond="cslp", krylov_slack=0.1, tol_newton=1e-6, tol_krylov=1e-8,
-                               max_restarts=20, max_newton=8)
+    # bounds: FACTOR times the oracle's summation-order spread (order_spread "maxwell12x10_cslp")
+    import order_spread as OS
+
+    spec, xp, src, opts, _, _, _ = OS.case("maxwell12x10_cslp")
+    tol, tol_x = OS.gpu_bounds("maxwell12x10_cslp")
+    info, ref = compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, engine="auto", orth="dcgs2",
+                               krylov_slack=0.1, **opts)
     assert info["converged"]
 
 

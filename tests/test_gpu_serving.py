@@ -239,3 +239,30 @@ def test_mixed_problem_kinds_and_methods_alone_equals_mix():
         assert ir.converged and ir.newton_iters == ia["newton_iters"], (spec["kind"], ir.newton_iters, ia)
         tol = 1e-6 if spec["kind"] == "maxwell" else 1e-10
         assert np.linalg.norm(xa - xr) <= tol * max(1.0, np.linalg.norm(xr)), spec["kind"]
+
+
+def test_graph_engine_in_a_mix_equals_multi_kernel_alone():
+    """Requests on the graph engine (each worker captures its cycles while the others run and
+    allocate workspaces) give bitwise the multi-kernel engine's results alone."""
+    from paper_2605_13378_amd import Batch
+
+    reqs = W.serving_stream(count=2000, seed=0, rate=1.0)[:40]
+    b1 = Batch("f32", m=30, max_slots=1)
+    alone = []
+    for req in reqs:
+        spec, xp = W.serving_request_inputs(req)
+        alone.append(b1.wait(b1.submit(spec, xp, engine="multi")))
+    b1.close()
+    b = Batch("f32", m=30, max_slots=8)
+    tickets = []
+    for req in reqs:
+        spec, xp = W.serving_request_inputs(req)
+        tickets.append(b.submit(spec, xp, engine="graph"))
+    mixed = [b.wait(t) for t in tickets]
+    st = b.stats()
+    b.close()
+    assert st["failed"] == 0 and st["max_running"] >= 2, st
+    for req, (xa, ia), (xm, im) in zip(reqs, alone, mixed):
+        assert ia["rc"] == 0 and im["rc"] == 0, (req, ia["status"], im["status"])
+        assert np.array_equal(xa, xm), req
+        assert ia["krylov_iters"] == im["krylov_iters"], req
