@@ -376,6 +376,47 @@ def kerr_newton(torch, max_newton=50):
     return out
 
 
+def kerr_c4_rows(torch):
+    """The Helmholtz-Kerr workload's physics (k0 = 2 pi / 64 cells, eps_L = 1) in the default run:
+    Newton to convergence on 64^2 (chi3 0.01 and 0.1, complex64 and complex128, AD; the grid the
+    parity tests compare per iterate), and the 1024^2 workload from E = 0 with a cap of 5 Newton
+    steps (AD and FD, chi3 0.1): the residual reduction unpreconditioned GMRES(30) reaches there."""
+    from paper_2605_13378_amd import Solver
+
+    import workloads as W
+
+    out = {"grid64": {}, "grid1024_cap5": {}}
+    for prec in ("f32", "f64"):
+        for chi3 in (0.01, 0.1):
+            spec = W.kerr_spec(64, chi3=chi3, cells_per_wavelength=64.0)
+            s = Solver(spec, prec, m=30)
+            s.set_previous(None, torch.tensor(W.kerr_gaussian_source(64), dtype=torch.float64, device="cuda"))
+            x0 = torch.zeros(2 * 64 * 64, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = s.newton_solve(x0, mode="ad", max_newton=50)
+            el = time.perf_counter() - t0
+            out["grid64"][f"{prec}-chi{chi3}"] = dict(
+                converged=info["converged"], newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                lin_iters=info["lin_iters"], final_rel_res=info["rel_res"][-1], seconds=round(el, 3))
+            log(f"[bench] C4 64^2 {prec} chi3 {chi3}: {out['grid64'][f'{prec}-chi{chi3}']}")
+            s.close()
+        s, _ = kerr_solver(torch, prec, chi3=0.1)
+        x0 = torch.zeros(2 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        for mode in ("ad", "fd"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = s.newton_solve(x0, mode=mode, eps_rule="paper", max_newton=5)
+            el = time.perf_counter() - t0
+            out["grid1024_cap5"][f"{prec}-{mode}"] = dict(
+                newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
+                rel_res=[round(r, 5) for r in info["rel_res"]], seconds=round(el, 3),
+                arnoldi_steps_per_s=round(info["krylov_iters"] / el, 1))
+            log(f"[bench] C4 1024^2 cap 5 {prec} {mode}: {out['grid1024_cap5'][f'{prec}-{mode}']}")
+        s.close()
+    return out
+
+
 def serving_pass(batch, reqs, inputs, rate_scale, saturate, opts=None):
     """Feed `reqs` to `batch` (Poisson arrivals scaled by 1/rate_scale, or all at
     once) and return solves/s and arrival-to-result latency percentiles."""
@@ -793,6 +834,8 @@ def main():
     ap.add_argument("--no-maxwell", action="store_true", help="skip the Maxwell-Kerr TE rows")
     ap.add_argument("--no-paper-burgers", action="store_true",
                     help="skip the 256^2 Burgers TGV/DSL rows (the paper's JVP-cost experiment)")
+    ap.add_argument("--no-kerr-c4", action="store_true",
+                    help="skip the Helmholtz-Kerr rows of the default run (64^2 Newton, 1024^2 capped)")
     ap.add_argument("--kerr-newton", action="store_true",
                     help="run the Helmholtz-Kerr 1024^2 Newton completion rows (minutes)")
     ap.add_argument("--completion-seeds", type=int, default=64,
@@ -1027,6 +1070,10 @@ def main():
     if args.kerr_newton:
         log("[bench] Helmholtz-Kerr 1024^2 Newton rows")
         c4 = kerr_newton(torch)
+    c4_short = None
+    if not args.no_kerr_c4:
+        log("[bench] Helmholtz-Kerr rows: 64^2 to convergence, 1024^2 capped at 5 Newton steps")
+        c4_short = kerr_c4_rows(torch)
 
     c1 = None
     if not args.no_latency:
@@ -1086,6 +1133,7 @@ def main():
         "latency_burgers1d_256": c1,
         "completion_burgers2d_2048": c3,
         "kerr_newton_1024": c4,
+        "kerr_c4": c4_short,
         "serving": serving,
         "cpu_baseline": cpu,
     }
