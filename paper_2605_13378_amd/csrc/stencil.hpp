@@ -332,61 +332,74 @@ __global__ void __launch_bounds__(256) cslp_apply_kernel(const T* __restrict__ x
 }
 
 // First CGS projection of an Arnoldi JVP's outputs on the stored basis:
-// acc[q] += V_q . o over the R rows `rows` (column cc) of this thread, for
-// q < a.K.  The rows of G basis vectors are loaded together before any is
-// used (G chosen for about 256 bytes in flight per lane; a load-use pair per
-// vector and row would leave the pass waiting on one memory round trip after
-// another).  Slots of the last group beyond K reload vector K-1 and their
-// products are discarded.
+// Loads the rows `rows` (column cc) of basis vectors q0 .. q0+G-1 into vq;
+// slots at or beyond K reload vector K-1 (their products are discarded).
+template <class P, class T, class VT, int VEC, int R, int G>
+__device__ __forceinline__ void project_load(const StencilArgs<T, VT>& a, int nx, int cc, const int (&rows)[R],
+                                             int q0, VT (&vq)[G][R][P::NF][VEC]) {
+  if (a.nt_basis) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+#pragma unroll
+      for (int tt = 0; tt < R; ++tt) load_nodes_nt<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+#pragma unroll
+      for (int tt = 0; tt < R; ++tt) load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
+    }
+  }
+}
+
+// acc[q0 + u] += V_{q0+u} . o for the G loaded vectors (u with q0 + u < K).
 template <class P, class T, class VT, int VEC, int R, int G, int KDOT>
-__device__ __forceinline__ void project_rows(const StencilArgs<T, VT>& a, int nx, int cc, const int (&rows)[R],
-                                             const T (&o)[R][P::NF][VEC], double (&acc)[KDOT + 1]) {
+__device__ __forceinline__ void project_accumulate(const StencilArgs<T, VT>& a, int q0,
+                                                   const VT (&vq)[G][R][P::NF][VEC], const T (&o)[R][P::NF][VEC],
+                                                   double (&acc)[KDOT + 1]) {
   constexpr int NF = P::NF;
 #pragma unroll
-  for (int q0 = 0; q0 < KDOT; q0 += G) {
-    if (q0 < a.K) {
-      VT vq[G][R][NF][VEC];
-      if (a.nt_basis) {
+  for (int u = 0; u < G; ++u) {
+    double sum;
+    if constexpr (sizeof(T) == 4) {
+      // FP32 sum over the thread's chunk, FP64 across chunks (as in the update pass)
+      T p = T(0);
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-          const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+      for (int tt = 0; tt < R; ++tt)
 #pragma unroll
-          for (int tt = 0; tt < R; ++tt)
-            load_nodes_nt<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
-        }
-      } else {
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-          const int q = q0 + u < a.K ? q0 + u : a.K - 1;
+          for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[u][tt][f][e]), o[tt][f][e], p);
+      sum = (double)p;
+    } else {
+      sum = 0.0;
 #pragma unroll
-          for (int tt = 0; tt < R; ++tt)
-            load_nodes<P, VT, VEC>(a.Vb + q * a.vstride, a.plane, nx, rows[tt], cc, vq[u][tt]);
-        }
-      }
+      for (int tt = 0; tt < R; ++tt)
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        double sum;
-        if constexpr (sizeof(T) == 4) {
-          // FP32 sum over the thread's chunk, FP64 across chunks (as in the update pass)
-          T p = T(0);
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-          for (int tt = 0; tt < R; ++tt)
+          for (int e = 0; e < VEC; ++e) sum += (double)to_c<T>(vq[u][tt][f][e]) * (double)o[tt][f][e];
+    }
+    if (q0 + u < KDOT) acc[q0 + u] += q0 + u < a.K ? sum : 0.0;
+  }
+}
+
+// acc[q] += V_q . o over the R rows `rows` (column cc) of this thread, for
+// q < a.K, starting at vector q0.  The rows of G basis vectors are loaded
+// together before any is used (G chosen for about 256 bytes in flight per
+// lane; a load-use pair per vector and row would leave the pass waiting on one
+// memory round trip after another).
+template <class P, class T, class VT, int VEC, int R, int G, int KDOT>
+__device__ __forceinline__ void project_rows(const StencilArgs<T, VT>& a, int nx, int cc, const int (&rows)[R],
+                                             const T (&o)[R][P::NF][VEC], double (&acc)[KDOT + 1], int q0 = 0) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) p = fmaf(to_c<T>(vq[u][tt][f][e]), o[tt][f][e], p);
-          sum = (double)p;
-        } else {
-          sum = 0.0;
-#pragma unroll
-          for (int tt = 0; tt < R; ++tt)
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) sum += (double)to_c<T>(vq[u][tt][f][e]) * (double)o[tt][f][e];
-        }
-        acc[q0 + u] += q0 + u < a.K ? sum : 0.0;
-      }
+  for (int qb = 0; qb < KDOT; qb += G) {
+    if (qb >= q0 && qb < a.K) {
+      VT vq[G][R][P::NF][VEC];
+      project_load<P, T, VT, VEC, R, G>(a, nx, cc, rows, qb, vq);
+      project_accumulate<P, T, VT, VEC, R, G, KDOT>(a, qb, vq, o, acc);
     }
   }
 }
@@ -434,6 +447,24 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   constexpr bool kEarlyB = RC * NF * VEC * (int)sizeof(T) <= 64;
   T bval[kEarlyB ? RC : 1][NF][VEC];
   const bool use_b = kNeedB && a.b != nullptr;
+  // Arnoldi JVP: the projection on the basis covers all of the thread's rows
+  // at once when their outputs fit 64 bytes per lane (kept in po), else it
+  // runs row by row; kProjGroup basis vectors' loads go out together
+  constexpr bool kProjAll = RC * NF * VEC * (int)sizeof(T) <= 64;
+  constexpr int PR = kProjAll ? RC : 1;
+  constexpr int kProjBytes = PR * NF * VEC * (int)sizeof(VT);
+  constexpr int kProjGroup0 = 256 / kProjBytes < 1 ? 1 : (256 / kProjBytes > 8 ? 8 : 256 / kProjBytes);
+  constexpr int kProjGroup = KDOT > 0 && kProjGroup0 > KDOT ? KDOT : kProjGroup0;
+  T po[KDOT > 0 ? PR : 1][NF][VEC];
+  int prow[KDOT > 0 ? PR : 1];
+  // the first tile's first group of basis rows is loaded right after the
+  // tile (it needs only the tile's position), so that its round trip
+  // overlaps the stencil arithmetic instead of following it; while all rows
+  // are projected at once and the group fits 64 registers per lane
+  constexpr int kPreRegs = kProjGroup * PR * NF * VEC * ((int)sizeof(VT) >= 4 ? (int)sizeof(VT) / 4 : 1);
+  constexpr bool kPre = OP != OP_RES && KDOT > 0 && kProjAll && kPreRegs <= 64;
+  constexpr int kPreGroup = kProjGroup;
+  VT vpre[kPre ? kPreGroup : 1][kPre ? PR : 1][NF][VEC];
   // Arnoldi JVP of the delayed form: the loads of the column completion in
   // the prologue go out first, then the first tile's (in-bounds either way;
   // unused if the cycle has stopped), so that the two sets of round trips
@@ -449,6 +480,17 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (kEarlyB) load_b_rows<P, T, VEC, RC>(a.b, a.plane, nx, ny, r0, cc, use_b, bval);
+    if constexpr (kPre) {
+      if (a.Vb != nullptr) {
+        int rows[PR];
+#pragma unroll
+        for (int tt = 0; tt < PR; ++tt) {
+          const int r = r0 + tt;
+          rows[tt] = P::kDim2 ? (r < ny ? r : 0) : 0;
+        }
+        project_load<P, T, VT, VEC, PR, kPreGroup>(a, nx, cc, rows, 0, vpre);
+      }
+    }
   }
 
   // Arnoldi mode (only instances with the fused projection, KDOT > 0): leave
@@ -524,19 +566,9 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
 
-  // Arnoldi JVP: the projection on the basis covers all of the thread's rows
-  // at once when their outputs fit 64 bytes per lane (kept in po), else it
-  // runs row by row; kProjGroup basis vectors' loads go out together
-  constexpr bool kProjAll = RC * NF * VEC * (int)sizeof(T) <= 64;
-  constexpr int PR = kProjAll ? RC : 1;
-  constexpr int kProjBytes = PR * NF * VEC * (int)sizeof(VT);
-  constexpr int kProjGroup0 = 256 / kProjBytes < 1 ? 1 : (256 / kProjBytes > 8 ? 8 : 256 / kProjBytes);
-  constexpr int kProjGroup = KDOT > 0 && kProjGroup0 > KDOT ? KDOT : kProjGroup0;
-  T po[KDOT > 0 ? PR : 1][NF][VEC];
-  int prow[KDOT > 0 ? PR : 1];
 
   // one tile whose loads have been issued (X, Vt at col0, r0)
-  auto process = [&]() {
+  auto process = [&](bool pre) {
     const bool colok = col0 < nx;
     const int cc = colok ? col0 : 0;
     const int pcc = cc;
@@ -645,18 +677,26 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         if constexpr (!kProjAll) project_rows<P, T, VT, VEC, 1, kProjGroup, KDOT>(a, nx, cc, prow, po, acc);
       }
     }
-    if constexpr (OP != OP_RES && KDOT > 0 && kProjAll)
+    if constexpr (OP != OP_RES && KDOT > 0 && kProjAll) {
+      if constexpr (kPre) {
+        if (pre) {
+          project_accumulate<P, T, VT, VEC, RC, kPreGroup, KDOT>(a, 0, vpre, po, acc);
+          project_rows<P, T, VT, VEC, RC, kProjGroup, KDOT>(a, nx, pcc, prow, po, acc, kPreGroup);
+          return;
+        }
+      }
       project_rows<P, T, VT, VEC, RC, kProjGroup, KDOT>(a, nx, pcc, prow, po, acc);
+    }
   };
 
-  if (t_begin < t_end) process();
+  if (t_begin < t_end) process(true);
   for (int t = t_begin + 1; t < t_end; ++t) {
     tile_origin(t, col0, r0);
     const int cc = col0 < nx ? col0 : 0;
     X.load(a.x, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (OP != OP_RES) Vt.load(a.v, a.plane, nx, ny, r0, col0, cc, lane);
     if constexpr (kEarlyB) load_b_rows<P, T, VEC, RC>(a.b, a.plane, nx, ny, r0, cc, use_b, bval);
-    process();
+    process(false);
   }
 
   if constexpr (OP == OP_RES) {
