@@ -173,8 +173,12 @@ __device__ inline GivensOut finish_column(Ctl* __restrict__ ctl, int j, const Pa
 struct LaggedPrefetch {
   PartialFetch pf;
   double h, cs, sn;
+  double gp, tol_abs, brk_tol, jvn2, sig;  // thread 0's scalars of the column update
 };
 
+// All of these are vector loads issued before the kernel's main loads: a
+// control-block read issued after them would wait for them to complete.
+template <bool HALF = false>
 __device__ __forceinline__ void lagged_prefetch(const Ctl* __restrict__ ctl, int c, const Partials& pd,
                                                 LaggedPrefetch& lp) {
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -183,6 +187,13 @@ __device__ __forceinline__ void lagged_prefetch(const Ctl* __restrict__ ctl, int
   lp.h = tid <= c ? ctl->Hp[c * ld + tid] : 0.0;
   lp.cs = tid < c ? ctl->cs[tid] : 0.0;
   lp.sn = tid < c ? ctl->sn[tid] : 0.0;
+  if (tid == 0) {
+    lp.gp = ctl->gp[c];
+    lp.tol_abs = ctl->tol_abs;
+    lp.brk_tol = ctl->brk_tol;
+    lp.jvn2 = ctl->jvn2c[c];
+    lp.sig = HALF ? ctl->vsig[c + 1] : 1.0;
+  }
 }
 
 // Delayed second pass (the alternative Arnoldi form): column c is completed
@@ -210,11 +221,11 @@ __device__ __forceinline__ GivensOut finish_column_lagged_from(Ctl* __restrict__
     in.sn[tid] = lp.sn;
   }
   if (tid == 0) {
-    in.gp = ctl->gp[c];
-    in.tol_abs = ctl->tol_abs;
-    in.brk_tol = ctl->brk_tol;
-    in.jvn2 = ctl->jvn2c[c];
-    in.sig = HALF ? ctl->vsig[c + 1] : 1.0;
+    in.gp = lp.gp;
+    in.tol_abs = lp.tol_abs;
+    in.brk_tol = lp.brk_tol;
+    in.jvn2 = lp.jvn2;
+    in.sig = lp.sig;
   }
   __shared__ double s_b2;
   __shared__ int s_bad;
@@ -256,7 +267,7 @@ template <bool HALF>
 __device__ inline GivensOut finish_column_lagged(Ctl* __restrict__ ctl, int c, const Partials& pd, int* host_flags,
                                                  double* col) {
   LaggedPrefetch lp;
-  lagged_prefetch(ctl, c, pd, lp);
+  lagged_prefetch<HALF>(ctl, c, pd, lp);
   return finish_column_lagged_from<HALF>(ctl, c, pd, host_flags, col, lp);
 }
 
@@ -538,21 +549,32 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   __shared__ double sh_sv, sh_su;  // FP16 storage scales of v_j and U_{j+1}
   const int tid = threadIdx.x;
   const int ld = kMaxM + 1;
-  // control-block inputs staged into LDS by all threads at once
-  for (int idx = tid; idx < j * (j + 1); idx += blockDim.x) {
-    const int l = idx / (j + 1), r = idx - l * (j + 1);
-    sh_hu[idx] = ctl->Hu[l * ld + r];
-  }
+  // control-block inputs loaded into registers by all threads at once (at
+  // most two completed-column entries each: j (j + 1) <= 992 < 2 * 512) and
+  // staged into LDS only after the basis loads have gone out: an LDS store
+  // waits for its load, and the basis loads would queue behind that wait
+  const int nhu = j * (j + 1);
+  const int i0 = tid, i1 = tid + blockDim.x;
+  double hu0 = 0.0, hu1 = 0.0, ah = 0.0, sc = 0.0, ts = 0.0;
+  if (i0 < nhu) hu0 = ctl->Hu[(i0 / (j + 1)) * ld + i0 % (j + 1)];
+  if (i1 < nhu) hu1 = ctl->Hu[(i1 / (j + 1)) * ld + i1 % (j + 1)];
   if (tid < j) {
-    sh_ah[tid] = ctl->ahat[tid];
-    sh_sc[tid] = ctl->scale[tid];
+    ah = ctl->ahat[tid];
+    sc = ctl->scale[tid];
   }
-  if (tid == 0) sh_ts = ctl->tscale[j];
+  if (tid == 0) ts = ctl->tscale[j];
   T w[VEC];
   Chunks<T, VT, KMAX, VEC> vv;
   vv.zero();
   if (i < a.n) cgs_load<T, VT, KMAX, VEC, NT>(a, i, K, w, vv);
   if (state != kRunning) return;
+  if (i0 < nhu) sh_hu[i0] = hu0;
+  if (i1 < nhu) sh_hu[i1] = hu1;
+  if (tid < j) {
+    sh_ah[tid] = ah;
+    sh_sc[tid] = sc;
+  }
+  if (tid == 0) sh_ts = ts;
   partials_reduce(a.in, K + 1, pf, tot);  // ends with a barrier
   if (tid < j) sh_b[tid] = tot[tid] * sh_sc[tid];
   if (tid <= j) {

@@ -462,7 +462,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   // overlaps the stencil arithmetic instead of following it; while all rows
   // are projected at once and the group fits 64 registers per lane
   constexpr int kPreRegs = kProjGroup * PR * NF * VEC * ((int)sizeof(VT) >= 4 ? (int)sizeof(VT) / 4 : 1);
-  constexpr bool kPre = OP != OP_RES && KDOT > 0 && kProjAll && kPreRegs <= 64;
+  constexpr bool kPre = OP != OP_RES && KDOT > 0 && KDOT <= 16 && kProjAll && kPreRegs <= 64;
   constexpr int kPreGroup = kProjGroup;
   VT vpre[kPre ? kPreGroup : 1][kPre ? PR : 1][NF][VEC];
   // Arnoldi JVP of the delayed form: the loads of the column completion in
@@ -470,9 +470,18 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   // unused if the cycle has stopped), so that the two sets of round trips
   // overlap (vector loads complete in order: issued after the tile, the
   // prologue's loads would wait for all of it).
+  // The stop state and the first step's tangent scale are read here too: a
+  // control-block read issued after the tile's loads would wait for them.
   LaggedPrefetch lpf;
+  [[maybe_unused]] int prev_state = kRunning;
+  [[maybe_unused]] double vscale0 = 1.0;
   if constexpr (OP != OP_RES && KDOT > 0) {
-    if (a.ctl != nullptr && a.lagged && a.arn_j > 0) lagged_prefetch(a.ctl, a.arn_j - 1, a.pc, lpf);
+    if (a.ctl != nullptr) {
+      const int j = a.arn_j;
+      prev_state = a.ctl->done_col[j > 0 ? j - 1 : 0];
+      if (j == 0) vscale0 = a.ctl->scale[0];
+      if (a.lagged && j > 0) lagged_prefetch<is_half<VT>()>(a.ctl, j - 1, a.pc, lpf);
+    }
   }
   if (t_begin < t_end) {
     tile_origin(t_begin, col0, r0);
@@ -498,7 +507,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   if constexpr (OP != OP_RES && KDOT > 0) {
     if (a.ctl != nullptr) {
       const int j = a.arn_j;
-      const int prev = a.ctl->done_col[j > 0 ? j - 1 : 0];
+      const int prev = prev_state;
       if (prev != kRunning) {
         // carry the state forward so that the flags stay monotone (later
         // kernels only look at the state after their own column)
@@ -530,7 +539,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
         arnoldi = true;
         const int j = a.arn_j;
         if (j == 0) {
-          vscale = a.ctl->scale[0];
+          vscale = vscale0;
         } else {
           __shared__ double gcol[kMaxM + 1];
           const GivensOut g = a.lagged ? finish_column_lagged_from<is_half<VT>()>(a.ctl, j - 1, a.pc, a.host_flags,
