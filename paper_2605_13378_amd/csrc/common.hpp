@@ -221,6 +221,87 @@ __device__ __forceinline__ double group_sum(double v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<kWave>(v); }
 
+// One halving step of a transposed wavefront sum: the lanes whose bit D of
+// the lane id is 0 keep the lower half of the M values (x = v[i], i < M/2),
+// the others the upper half (y = v[i + M/2]), each adding its partner's
+// copy of the half it keeps.  D = 32 and 16 use the permlane swaps, which
+// exchange x of one side for y of the other, so vdst + vsrc after the swap
+// is the kept half's pair sum on either side; smaller D use DPP moves of the
+// half the lane gives away.
+template <int D>
+__device__ __forceinline__ double halve_step(double x, double y, int lane) {
+  if constexpr (D == 32 || D == 16) {
+    const long long ux = __double_as_longlong(x), uy = __double_as_longlong(y);
+    const unsigned xl = (unsigned)(ux & 0xffffffffLL), xh = (unsigned)(ux >> 32);
+    const unsigned yl = (unsigned)(uy & 0xffffffffLL), yh = (unsigned)(uy >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (D == 32) {
+      const auto a = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+      const auto b = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+      l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    } else {
+      const auto a = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+      const auto b = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+      l0 = a[0]; l1 = a[1]; h0 = b[0]; h1 = b[1];
+    }
+    return __longlong_as_double(((long long)h0 << 32) | (long long)l0) +
+           __longlong_as_double(((long long)h1 << 32) | (long long)l1);
+  } else {
+    // partners: D = 8 row mirror (i <-> 15 - i), 4 half-row mirror (i <-> 7 - i),
+    // 2 and 1 lane xor within a quad; the partner's bit D is the opposite one
+    constexpr int CTRL = D == 8 ? 0x140 : (D == 4 ? 0x141 : (D == 2 ? 0x4E : 0xB1));
+    const bool low = (lane & D) == 0;
+    const double give = low ? y : x;
+    const double keep = low ? x : y;
+    return keep + dpp_f64<CTRL>(give);
+  }
+}
+
+// Sums of M values (a power of two, at most 32) over the 64 lanes of a
+// wavefront, transposed: lane l returns the sum of value l >> (6 - log2 M).
+// log2 M halving steps (M - 1 exchanges in all) and plain pair sums for the
+// remaining lane bits, where M separate wavefront sums would take 6 M.
+template <int M>
+__device__ __forceinline__ double wave_sum_transposed(const double (&v)[M], int lane) {
+  static_assert(M >= 1 && M <= 32 && (M & (M - 1)) == 0, "M: a power of two up to 32");
+  double a[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] = v[i];
+  int m = M;
+  // halving on lane bits 5, 4, 3, ... (D = 32, 16, 8, ...) while values remain
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int D = 32 >> s;
+    if (m > 1) {
+#pragma unroll
+      for (int i = 0; i < M / 2; ++i) {
+        if (i < m / 2) {
+          switch (D) {
+            case 32: a[i] = halve_step<32>(a[i], a[i + m / 2], lane); break;
+            case 16: a[i] = halve_step<16>(a[i], a[i + m / 2], lane); break;
+            case 8: a[i] = halve_step<8>(a[i], a[i + m / 2], lane); break;
+            case 4: a[i] = halve_step<4>(a[i], a[i + m / 2], lane); break;
+            case 2: a[i] = halve_step<2>(a[i], a[i + m / 2], lane); break;
+            default: a[i] = halve_step<1>(a[i], a[i + m / 2], lane); break;
+          }
+        }
+      }
+      m /= 2;
+    } else {
+      // one value left: a plain pair sum over this lane bit
+      switch (D) {
+        case 32: a[0] = swap_add_f64<32>(a[0]); break;
+        case 16: a[0] = swap_add_f64<16>(a[0]); break;
+        case 8: a[0] += dpp_f64<0x140>(a[0]); break;
+        case 4: a[0] += dpp_f64<0x141>(a[0]); break;
+        case 2: a[0] += dpp_f64<0x4E>(a[0]); break;
+        default: a[0] += dpp_f64<0xB1>(a[0]); break;
+      }
+    }
+  }
+  return a[0];
+}
+
 // group_sum for a group size known only at run time (uniform across the wavefront).
 __device__ __forceinline__ double group_sum_rt(double v, int G) {
   switch (G) {
@@ -267,8 +348,18 @@ __device__ __forceinline__ void block_partials(double (&acc)[NR], int nr, double
   const int wid = tid / kWave;
   const int nw = nthreads / kWave;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  // the first M values (M = NR rounded up to a power of two, at most 32) in
+  // one transposed wavefront sum, any further ones one by one
+  constexpr int M = NR <= 1 ? 1 : (NR <= 2 ? 2 : (NR <= 4 ? 4 : (NR <= 8 ? 8 : (NR <= 16 ? 16 : 32))));
+  constexpr int SH = M == 1 ? 6 : (M == 2 ? 5 : (M == 4 ? 4 : (M == 8 ? 3 : (M == 16 ? 2 : 1))));
+  double v[M];
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
+  for (int k = 0; k < M; ++k) v[k] = k < NR ? acc[k < NR ? k : 0] : 0.0;
+  const double t = wave_sum_transposed<M>(v, lane);
+  const int c = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && c < nr) lds[c * nw + wid] = t;
+#pragma unroll
+  for (int k = M; k < NR; ++k) {
     if (k < nr) {
       const double s = wave_sum(acc[k]);
       if (lane == 0) lds[k * nw + wid] = s;
