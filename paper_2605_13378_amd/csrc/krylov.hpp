@@ -577,11 +577,16 @@ __global__ void __launch_bounds__(512) dcgs_kernel(const KArgs<T, VT> a) {
   if (tid == 0) sh_ts = ts;
   partials_reduce(a.in, K + 1, pf, tot);  // ends with a barrier
   if (tid < j) sh_b[tid] = tot[tid] * sh_sc[tid];
-  if (tid <= j) {
-    // (H a^)_i over the completed columns 0..j-1 (row j only has column j-1)
+  {
+    // (H a^)_i over the completed columns 0..j-1 (row j only has column
+    // j-1): row i by 16 lanes (32 rows x 16 lanes = the 512 threads), each
+    // summing every 16th column, then a 16-lane sum
+    const int r = tid >> 4, g = tid & 15;
     double s = 0.0;
-    for (int l = 0; l < j; ++l) s += sh_hu[l * (j + 1) + tid] * sh_ah[l];
-    sh_ha[tid] = s;
+    if (r <= j)
+      for (int l = g; l < j; l += 16) s += sh_hu[l * (j + 1) + r] * sh_ah[l];
+    s = group_sum<16>(s);
+    if (r <= j && g == 0) sh_ha[r] = s;
   }
   __syncthreads();
   if (tid < kWave) {
