@@ -17,7 +17,8 @@ Newton-Krylov Solvers via Automatic Differentiation"):
 * ``bicgstab``: BiCGSTAB, the paper's short-recurrence nonsymmetric method.
 * ``cg``: conjugate gradients for the SPD reaction-diffusion linearization.
 * ``precond``: the block-diagonal CSLP preconditioner of the Maxwell-Kerr
-  problem (Appendix A.4), applied on the right of GMRES.
+  problem (Appendix A.4) and its scalar form for the Helmholtz-Kerr
+  workload, applied on the right of GMRES.
 * ``newton``: inexact Newton with backtracking line search and the
   failure classification of Section 3.4.
 * ``sweep``: the Maxwell frequency continuation (Section 3.1's outer loop,

@@ -16,6 +16,13 @@
 * right-preconditioned GMRES solves the unpreconditioned system: the update
   M^{-1} z equals the dense solve of J dx = rhs, with and without restarts;
 * Newton with the preconditioner converges to the same field as without.
+
+The scalar Helmholtz-Kerr form (M = 2/hx^2 + 2/hy^2 - k0^2 eps(E)(1 - 0.5 i)):
+the Born Jacobian diagonal and its complex structure; M(E) E equal to the
+source-free residual at a node whose neighbours are zero (fixes the |E|^2
+law, chi3, the loss sign and both 2/h^2 terms); damping, boundary identity
+and inverse; right-preconditioned GMRES against a dense solve; Newton to the
+same field with and without it.
 """
 
 import numpy as np
@@ -128,7 +135,7 @@ def test_boundary_nodes_are_identity():
     assert not np.allclose(mv[:, ~bnd], vv[:, ~bnd])
 
 
-def test_cslp_rejects_other_problems():
+def test_cslp_rejects_other_problems():  # Gray-Scott: no CSLP
     p = Problem.from_spec(W.grayscott_spec(8))
     with pytest.raises(ValueError):
         cslp_diagonal(p, np.zeros(p.n))
@@ -168,3 +175,112 @@ def test_newton_with_cslp_reaches_the_same_field():
     assert np.linalg.norm(residual(p, outs["cslp"], x0, src)) <= 1e-10 * np.linalg.norm(residual(p, x0, x0, src))
     with pytest.raises(ValueError):
         newton_solve(p, x0, NewtonOptions(krylov="bicgstab", precond="cslp"), source=src)
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz-Kerr: the same construction on the scalar operator
+# -Lap E - k0^2 (eps_L + chi3 |E|^2) E (one complex component per node)
+# ---------------------------------------------------------------------------
+
+
+def kerr_grid(nx, ny, chi=0.3, eps_im=-0.05, cpw=8.0):
+    """hx != hy and a lossy eps_L, so that a swapped 2/h^2 term or a dropped loss sign fails."""
+    return Problem(kind="kerr", nx=nx, ny=ny, hx=1.0, hy=0.8, k0=2.0 * np.pi / cpw, eps_re=1.0, eps_im=eps_im,
+                   chi3=chi)
+
+
+def kerr_unit(p, j, i, f):
+    e = np.zeros(p.n)
+    e[2 * (j * p.nx + i) + f] = 1.0
+    return e
+
+
+@pytest.mark.parametrize("nx,ny", [(9, 7), (6, 11)])
+def test_kerr_undamped_cslp_is_the_born_jacobian_diagonal(nx, ny):
+    p = kerr_grid(nx, ny)
+    x = np.zeros(p.n)
+    (m,) = cslp_diagonal(p, x, damping=0.0)
+    for j in range(1, ny - 1):
+        for i in range(1, nx - 1):
+            k = j * nx + i
+            col = jvp_ad(p, x, kerr_unit(p, j, i, 0), x, None)[1]
+            d = col[2 * k] + 1j * col[2 * k + 1]
+            assert abs(m[j, i] - d) <= 1e-12 * abs(d), (j, i, m[j, i], d)
+            # the Im unit column holds i d: the Jacobian at E = 0 is complex-linear
+            col_im = jvp_ad(p, x, kerr_unit(p, j, i, 1), x, None)[1]
+            assert abs(col_im[2 * k] + d.imag) <= 1e-12 * abs(d) and abs(col_im[2 * k + 1] - d.real) <= 1e-12 * abs(d)
+
+
+def test_kerr_undamped_cslp_times_an_isolated_field_is_the_residual():
+    """Where E vanishes at every neighbour of a node, the source-free residual there is M(E) E
+    (complex product): a route through the residual itself that fixes the |E|^2 law, chi3, the
+    loss sign and both 2/h^2 terms of the field-dependent diagonal, node by node."""
+    p = kerr_grid(8, 7, chi=0.7)
+    rng = np.random.default_rng(21)
+    checked = 0
+    for j in range(1, p.ny - 1):
+        for i in range(1, p.nx - 1):
+            x = np.zeros(p.n)
+            k = j * p.nx + i
+            e = complex(*rng.standard_normal(2))
+            x[2 * k], x[2 * k + 1] = e.real, e.imag
+            (m,) = cslp_diagonal(p, x, damping=0.0)
+            F = residual(p, x, None, None)
+            f = F[2 * k] + 1j * F[2 * k + 1]
+            assert abs(m[j, i] * e - f) <= 1e-12 * abs(f), (j, i, m[j, i] * e, f)
+            checked += 1
+    assert checked == 6 * 5
+    # and the field matters: |E|^2 enters with chi3
+    x = W.random_vector(p.n, 4)
+    (m,) = cslp_diagonal(p, x, damping=0.0)
+    (mb,) = cslp_diagonal(p, np.zeros(p.n), damping=0.0)
+    re, im = x[0::2].reshape(p.ny, p.nx), x[1::2].reshape(p.ny, p.nx)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose((mb - m)[inner], (p.k0 ** 2 * p.chi3 * (re * re + im * im))[inner], rtol=1e-13, atol=0)
+
+
+def test_kerr_damping_boundary_and_inverse():
+    p = kerr_grid(7, 9)
+    rng = np.random.default_rng(5)
+    x, v = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    (m0,) = cslp_diagonal(p, x, damping=0.0)
+    (md,) = cslp_diagonal(p, x)
+    diag = 2.0 / p.hx ** 2 + 2.0 / p.hy ** 2
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose((md - diag)[inner], ((1 - 0.5j) * (m0 - diag))[inner], rtol=1e-14)
+    # boundary nodes: identity
+    mv = cslp_solve(p, x, v).reshape(p.ny, p.nx, 2)
+    vv = v.reshape(p.ny, p.nx, 2)
+    bnd = np.ones((p.ny, p.nx), bool)
+    bnd[1:-1, 1:-1] = False
+    assert np.array_equal(mv[bnd], vv[bnd]) and not np.allclose(mv[~bnd], vv[~bnd])
+    # M acts as a complex multiplication: M^{-1} (M v) = v
+    c = v[0::2] + 1j * v[1::2]
+    mc = md.ravel() * c
+    back = cslp_solve(p, x, np.stack([mc.real, mc.imag], axis=-1).ravel())
+    assert np.allclose(back, v, rtol=0, atol=1e-13)
+
+
+def test_kerr_right_preconditioned_gmres_and_newton():
+    p = kerr_grid(7, 6, chi=0.3)
+    rng = np.random.default_rng(7)
+    x = 0.5 * rng.standard_normal(p.n)
+    rhs = rng.standard_normal(p.n)
+    ref = np.linalg.solve(dense_jacobian(p, x), rhs)
+    mv = lambda v: jvp_ad(p, x, v, x, None)[1]  # noqa: E731
+    z, info = gmres_solve(lambda v: mv(cslp_solve(p, x, v)), rhs, m=100, tol=1e-12, max_restarts=3)
+    assert info.converged, info
+    dx = cslp_solve(p, x, z)
+    assert np.linalg.norm(dx - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert np.linalg.norm(z - ref) > 1e-3 * np.linalg.norm(ref)
+    # Newton with and without the preconditioner: the same field
+    src = np.zeros(p.n)
+    src.reshape(p.ny, p.nx, 2)[1:-1, 1:-1, 0] = 0.3 * rng.standard_normal((p.ny - 2, p.nx - 2))
+    x0 = np.zeros(p.n)
+    outs = {}
+    for pc in ("none", "cslp"):
+        o = NewtonOptions(m=30, tol_newton=1e-10, tol_krylov=1e-11, max_newton=10, max_restarts=20, precond=pc)
+        xs, ni = newton_solve(p, x0, o, source=src)
+        assert ni.converged, (pc, ni.rel_res)
+        outs[pc] = xs
+    assert np.linalg.norm(outs["cslp"] - outs["none"]) <= 1e-9 * np.linalg.norm(outs["none"])
