@@ -380,7 +380,8 @@ def kerr_c4_rows(torch):
     """The Helmholtz-Kerr workload's physics (k0 = 2 pi / 64 cells, eps_L = 1) in the default run:
     Newton to convergence on 64^2 (chi3 0.01 and 0.1, complex64 and complex128, AD; the grid the
     parity tests compare per iterate), and the 1024^2 workload from E = 0 with a cap of 5 Newton
-    steps (AD and FD, chi3 0.1): the residual reduction unpreconditioned GMRES(30) reaches there."""
+    steps (AD and FD, chi3 0.1): the residual reduction unpreconditioned GMRES(30) reaches there.
+    Rows with a "-cslp" suffix: the same with the CSLP right preconditioner (AD)."""
     from paper_2605_13378_amd import Solver
 
     import workloads as W
@@ -392,22 +393,26 @@ def kerr_c4_rows(torch):
             s = Solver(spec, prec, m=30)
             s.set_previous(None, torch.tensor(W.kerr_gaussian_source(64), dtype=torch.float64, device="cuda"))
             x0 = torch.zeros(2 * 64 * 64, dtype=torch.float64, device="cuda")
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info = s.newton_solve(x0, mode="ad", max_newton=50)
-            el = time.perf_counter() - t0
-            out["grid64"][f"{prec}-chi{chi3}"] = dict(
-                converged=info["converged"], newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
-                lin_iters=info["lin_iters"], final_rel_res=info["rel_res"][-1], seconds=round(el, 3))
-            log(f"[bench] C4 64^2 {prec} chi3 {chi3}: {out['grid64'][f'{prec}-chi{chi3}']}")
+            for pre in ("none", "cslp"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = s.newton_solve(x0, mode="ad", max_newton=50, precond=pre)
+                el = time.perf_counter() - t0
+                key = f"{prec}-chi{chi3}" + ("-cslp" if pre == "cslp" else "")
+                out["grid64"][key] = dict(
+                    converged=info["converged"], newton_iters=info["newton_iters"],
+                    krylov_iters=info["krylov_iters"], lin_iters=info["lin_iters"],
+                    final_rel_res=info["rel_res"][-1], seconds=round(el, 3))
+                log(f"[bench] C4 64^2 {key}: {out['grid64'][key]}")
             s.close()
         s, _ = kerr_solver(torch, prec, chi3=0.1)
         x0 = torch.zeros(2 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        for mode in ("ad", "fd"):
+        for mode, pre in (("ad", "none"), ("fd", "none"), ("ad", "cslp")):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, info = s.newton_solve(x0, mode=mode, eps_rule="paper", max_newton=5)
+            _, info = s.newton_solve(x0, mode=mode, eps_rule="paper", max_newton=5, precond=pre)
             el = time.perf_counter() - t0
+            mode = mode + ("-cslp" if pre == "cslp" else "")
             out["grid1024_cap5"][f"{prec}-{mode}"] = dict(
                 newton_iters=info["newton_iters"], krylov_iters=info["krylov_iters"],
                 rel_res=[round(r, 5) for r in info["rel_res"]], seconds=round(el, 3),

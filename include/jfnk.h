@@ -141,8 +141,12 @@ typedef struct {
  * (frozen for the linear solve); boundary nodes are left as they are.  GMRES
  * runs on J M^{-1} and returns dx = M^{-1} z, so its residual, tolerance and
  * reported norms are those of J dx = rhs.  Applied inside the JVP kernel (no
- * extra pass over memory) and once to the final update.  Only for
- * JFNK_MAXWELL2D, with GMRES on the MULTI_KERNEL engine (AUTO picks it), and
+ * extra pass over memory) and once to the final update.  On the scalar
+ * Helmholtz-Kerr workload (JFNK_KERR2D) the same construction: each interior
+ * pair divided by M = 2/hx^2 + 2/hy^2 - k0^2 (eps_L + chi3 |E|^2)(1 - 0.5 i),
+ * the diagonal of -Lap and the damped permittivity (the paper defines the
+ * preconditioner for the TE problem only).  Only for JFNK_MAXWELL2D and
+ * JFNK_KERR2D, with GMRES on the MULTI_KERNEL engine (AUTO picks it), and
  * with the FD JVP only under the paper's step rule or a fixed step; other
  * combinations return JFNK_ERR_ARG. */
 typedef enum { JFNK_PRECOND_NONE = 0, JFNK_PRECOND_CSLP = 1 } jfnk_precond;
@@ -358,9 +362,9 @@ jfnk_status jfnk_set_orthogonalization(jfnk_solver* s, int orth);
 
 /* Preconditioner (jfnk_precond) of later jfnk_gmres calls on this solver
  * (default NONE); jfnk_newton_solve takes it from its options instead.
- * CSLP on a problem other than JFNK_MAXWELL2D returns JFNK_ERR_ARG, and a
- * later jfnk_gmres call with the FD JVP under the normalized step rule does
- * too. */
+ * CSLP on a problem other than JFNK_MAXWELL2D or JFNK_KERR2D returns
+ * JFNK_ERR_ARG, and a later jfnk_gmres call with the FD JVP under the
+ * normalized step rule does too. */
 jfnk_status jfnk_set_preconditioner(jfnk_solver* s, int precond);
 
 /* Move a solver to another stream (a hipStream_t; NULL = the default stream)

@@ -31,10 +31,10 @@ ARCH = os.environ.get("JFNK_OFFLOAD_ARCH", "gfx950")
 UNITS = [(os.path.splitext(s)[0], s, []) for s in
          ["solver.hip", "serving.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_f16.hip"]]
 OPS = ["Burgers1DOp", "Burgers2DOp", "GrayScottOp", "KerrOp", "RD2DOp", "SuOlsonOp", "SuOlsonPYOp", "MaxwellTEOp",
-       "MaxwellTECslpOp"]
+       "MaxwellTECslpOp", "KerrCslpOp"]
 for _t, _vt, _tag in (("double", "double", "f64"), ("float", "float", "f32"), ("float", "__half", "f16")):
     for _op in OPS:
-        _fused = 1 if (_t == _vt and _op != "MaxwellTECslpOp") else 0
+        _fused = 1 if (_t == _vt and not _op.endswith("CslpOp")) else 0
         UNITS.append((f"stencil_{_tag}_{_op}", "stencil_inst.hip",
                       [f"-DJFNK_OP={_op}", f"-DJFNK_T={_t}", f"-DJFNK_VT={_vt}", f"-DJFNK_FUSED={_fused}"]))
 

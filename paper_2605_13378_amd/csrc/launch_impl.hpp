@@ -17,6 +17,8 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
     case kGrayScott:
       return launch_stencil_p<GrayScottOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kKerr:
+      if (a.precond && op != OP_RES)
+        return launch_stencil_p<KerrCslpOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
       return launch_stencil_p<KerrOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
     case kRD2D:
       return launch_stencil_p<RD2DOp, T, VT>(pid, op, withf, vectorized, a, c, cap, s, nblocks);
@@ -35,9 +37,14 @@ hipError_t launch_stencil(int pid, int op, bool withf, bool vectorized, const St
 
 template <class T>
 hipError_t launch_cslp_apply(int pid, const T* x, T* z, int nx, int ny, const Coefs& c, int grid, hipStream_t s) {
-  if (pid != kMaxwell) return hipErrorInvalidValue;
-  JFNK_LAUNCH((cslp_apply_kernel<MaxwellTEOp, T>), dim3(grid), dim3(kStreamThreads), s, x, z, nx, ny,
-              (long long)nx * ny, c);
+  if (pid == kMaxwell)
+    JFNK_LAUNCH((cslp_apply_kernel<MaxwellTEOp, T>), dim3(grid), dim3(kStreamThreads), s, x, z, nx, ny,
+                (long long)nx * ny, c);
+  else if (pid == kKerr)
+    JFNK_LAUNCH((cslp_apply_kernel<KerrOp, T>), dim3(grid), dim3(kStreamThreads), s, x, z, nx, ny,
+                (long long)nx * ny, c);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -192,6 +192,28 @@ struct KerrOp {
   __device__ __forceinline__ static bool boundary(int i, int j, int nx, int ny) {
     return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
   }
+  // The complex shifted-Laplacian preconditioner of Appendix A.4 on this
+  // scalar operator, frozen at the state x of an interior node: v's pair
+  // (Re, Im) is divided, as a complex number, by
+  // M = 2/hx^2 + 2/hy^2 - k0^2 eps(E) (1 - 0.5 i), eps(E) = eps_L + chi3 |E|^2
+  // (the diagonal of -Lap and the damped permittivity of the TE form).
+  template <class T>
+  __device__ __forceinline__ static void cslp_inv(const K<T>& k, const T (&x)[2], T (&v)[2]) {
+    const T a = k.er + k.chi * (x[0] * x[0] + x[1] * x[1]);
+    // k0^2 eps (1 - 0.5 i) = k2 ((a + ei/2) + (ei - a/2) i)
+    const T mr = T(2) * (k.ihx2 + k.ihy2) - k.k2 * (a + T(0.5) * k.ei);
+    const T mi = -(k.k2 * (k.ei - T(0.5) * a));
+    const T d = T(1) / (mr * mr + mi * mi);
+    const T v0 = v[0], v1 = v[1];
+    v[0] = (v0 * mr + v1 * mi) * d;
+    v[1] = (v1 * mr - v0 * mi) * d;
+  }
+};
+
+// The Helmholtz-Kerr operator with the CSLP preconditioner applied to every
+// JVP tangent (right preconditioning), as MaxwellTECslpOp.
+struct KerrCslpOp : KerrOp {
+  static constexpr bool kPrecondTangent = true;
 };
 
 struct RD2DOp {

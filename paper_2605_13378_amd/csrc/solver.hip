@@ -1265,7 +1265,8 @@ jfnk_status short_recurrence_api(jfnk_solver* s, int krylov, const T* x, const T
   return st;
 }
 
-// The CSLP preconditioner: the Maxwell-Kerr problem only, with GMRES on the
+// The CSLP preconditioner: the Maxwell-Kerr problem and the Helmholtz-Kerr
+// workload (the same construction on the scalar operator), with GMRES on the
 // multi-kernel engine; the FD JVP takes the paper's step rule (the
 // normalized rule would need the norm of M^{-1} v).
 bool precond_ok(const jfnk_solver* s, int precond, int krylov, int engine, int mode, int eps_rule, double fd_eps,
@@ -1275,8 +1276,8 @@ bool precond_ok(const jfnk_solver* s, int precond, int krylov, int engine, int m
     *why = "unknown preconditioner";
     return false;
   }
-  if (s->pid != kMaxwell) {
-    *why = "the CSLP preconditioner is defined for the Maxwell-Kerr problem only";
+  if (s->pid != kMaxwell && s->pid != kKerr) {
+    *why = "the CSLP preconditioner is defined for the Maxwell-Kerr and Helmholtz-Kerr problems only";
     return false;
   }
   if (krylov != JFNK_KRYLOV_GMRES || engine == JFNK_ENGINE_SINGLE_WORKGROUP) {

@@ -309,7 +309,8 @@ __device__ __forceinline__ void precondition_tile(const KT& k, const Tile<P, T, 
 }
 
 // dx = M^{-1} z in place (the update of right-preconditioned GMRES), one
-// node per thread, grid-stride; SoA planes.
+// node per thread, grid-stride; SoA planes or interleaved pairs, as the
+// operator stores them.
 template <class P, class T>
 __global__ void __launch_bounds__(256) cslp_apply_kernel(const T* __restrict__ x, T* __restrict__ z, int nx, int ny,
                                                           long long plane, const Coefs coefs) {
@@ -322,12 +323,13 @@ __global__ void __launch_bounds__(256) cslp_apply_kernel(const T* __restrict__ x
     T xv[P::NF], vv[P::NF];
 #pragma unroll
     for (int f = 0; f < P::NF; ++f) {
-      xv[f] = x[f * plane + i];
-      vv[f] = z[f * plane + i];
+      const long long o = P::kInterleaved ? P::NF * i + f : f * plane + i;
+      xv[f] = x[o];
+      vv[f] = z[o];
     }
     P::template cslp_inv<T>(k, xv, vv);
 #pragma unroll
-    for (int f = 0; f < P::NF; ++f) z[f * plane + i] = vv[f];
+    for (int f = 0; f < P::NF; ++f) z[P::kInterleaved ? P::NF * i + f : f * plane + i] = vv[f];
   }
 }
 

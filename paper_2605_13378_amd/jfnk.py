@@ -297,7 +297,7 @@ class Solver:
         self._check(lib().jfnk_set_orthogonalization(self._h, ORTH[orth]))
 
     def set_preconditioner(self, precond: str):
-        """Right preconditioner of later gmres() calls: 'none' (default) or 'cslp' (Maxwell-Kerr)."""
+        """Right preconditioner of later gmres() calls: 'none' (default) or 'cslp' (Maxwell-Kerr, Helmholtz-Kerr)."""
         self._check(lib().jfnk_set_preconditioner(self._h, PRECOND[precond]))
 
     def gmres(self, x, rhs, m=None, tol=1e-8, max_restarts=100, mode="ad", eps=0.0, eps_rule="paper"):

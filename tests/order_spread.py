@@ -52,6 +52,10 @@ CASES = {
                                                   max_restarts=20, max_newton=8), 8e-12, 3e-10, 8),
     "kerr64_chi0.01": (_kerr_c4, (64, 0.01), dict(max_newton=50), 3e-9, 6e-9, 120),
     "kerr64_chi0.1": (_kerr_c4, (64, 0.1), dict(max_newton=50), 6e-9, 6e-9, 160),
+    # with the CSLP preconditioner; measured (three permutations, both Gram-Schmidt forms):
+    # 1.2e-11 / 4.8e-11 / 12 on 12 x 10, 5.3e-9 / 4.8e-9 / 62 on 64 x 64
+    "kerr12x10_cpw32_chi1.0_cslp": (_kerr12, (32.0, 1.0), dict(max_newton=20, precond="cslp"), 2.5e-11, 1e-10, 24),
+    "kerr64_chi0.1_cslp": (_kerr_c4, (64, 0.1), dict(max_newton=50, precond="cslp"), 1.2e-8, 1e-8, 130),
 }
 
 

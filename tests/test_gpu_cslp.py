@@ -13,6 +13,14 @@ Parity contract:
     the oracle's own summation-order spread on the same case (order_spread);
   * the configurations the library rejects, and AUTO running the
     multi-kernel engine for a problem the single-workgroup engine would take.
+
+The same for the preconditioner's scalar form on the Helmholtz-Kerr workload
+(M = 2/hx^2 + 2/hy^2 - k0^2 eps(E)(1 - 0.5 i), interleaved (Re, Im) storage):
+GMRES on a lossy non-square-cell grid with |E| > 0 (FP64 AD 1e-9 with both
+Gram-Schmidt forms, FP32 AD 1e-5 including the 1024^2 workload, FP64 FD under
+the paper's step at ten times the oracle's own one-ulp sensitivity), odd and
+tiny grids, and Newton per iterate on 12 x 10 and on the workload's physics
+at 64 x 64 at FACTOR times the oracle's summation-order spread.
 """
 
 import numpy as np
@@ -150,6 +158,93 @@ def test_newton_maxwell_cslp_auto_engine_runs_multi_kernel():
     info, ref = compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, engine="auto", orth="dcgs2",
                                krylov_slack=0.1, **opts)
     assert info["converged"]
+
+
+def kerr_case(nx, ny, prec, chi=0.3, eps_im=-0.05, cpw=16.0, seed=9, amp=0.4):
+    """Helmholtz-Kerr, hx != hy, lossy eps_L, a seeded source zero on the boundary and a state
+    with |E| > 0, so that M varies from node to node."""
+    spec = dict(kind="kerr", nx=nx, ny=ny, hx=1.0, hy=0.8, dt=0.0, theta=1.0, k0=2 * np.pi / cpw, eps_re=1.0,
+                eps_im=eps_im, chi3=chi)
+    p = Problem.from_spec(spec)
+    src = 0.5 * W.random_vector(p.n, seed + 1)
+    src.reshape(ny, nx, 2)[[0, -1], :, :] = 0.0
+    src.reshape(ny, nx, 2)[:, [0, -1], :] = 0.0
+    x = amp * W.random_vector(p.n, seed)
+    xw = x if prec == "f64" else x.astype(np.float32).astype(np.float64)
+    rhs = -residual(p, xw, None, src)
+    if prec == "f32":
+        rhs = rhs.astype(np.float32).astype(np.float64)
+    return spec, src, p, xw, rhs
+
+
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+@pytest.mark.parametrize("m,cycles", [(8, 1), (6, 3)])
+def test_kerr_cslp_gmres_f64_ad(orth, m, cycles):
+    spec, src, p, xw, rhs = kerr_case(40, 36, "f64")
+    ref, rinfo, mv = oracle_gmres(p, xw, rhs, src, m, cycles, orth=orth)
+    dx, info = run_gpu(spec, src, "f64", xw, rhs, m, cycles, orth=orth)
+    assert info["krylov_iters"] == rinfo.iters == m * cycles and not info["converged"]
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 1e-9 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+    true_res = np.linalg.norm(rhs - mv(d))
+    assert abs(true_res - np.linalg.norm(rhs - mv(ref))) <= 1e-8 * np.linalg.norm(rhs)
+    plain, _ = gmres_solve(mv, rhs, m=m, tol=1e-30, max_restarts=cycles)
+    assert np.linalg.norm(plain - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_kerr_cslp_gmres_f64_fd_paper_step():
+    # the oracle's own 16-step FD iterate moves by 5.9e-7 when F(x) changes by one ulp
+    # (measured); the bound is ten times that, the unpreconditioned iterate is 3.7e-2 away
+    spec, src, p, xw, rhs = kerr_case(40, 36, "f64")
+    ref, rinfo, mv = oracle_gmres(p, xw, rhs, src, 8, 2, mode="fd")
+    dx, info = run_gpu(spec, src, "f64", xw, rhs, 8, 2, mode="fd")
+    assert info["krylov_iters"] == rinfo.iters == 16
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 6e-6 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+    plain, _ = gmres_solve(mv, rhs, m=8, tol=1e-30, max_restarts=2)
+    assert np.linalg.norm(plain - ref) > 1e-2 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,chi,cpw", [(40, 0.3, 16.0), (1024, 0.1, 64.0)])
+def test_kerr_cslp_gmres_f32_ad(n, chi, cpw):
+    """FP32 at the contract bound, on a small grid and on the Helmholtz-Kerr workload's own
+    shape and physics (1024^2, k0 = 2 pi / 64, eps_L = 1, chi3 = 0.1), one GMRES(30) cycle."""
+    eps_im = -0.05 if n == 40 else 0.0
+    spec, src, p, xw, rhs = kerr_case(n, n - 4 if n == 40 else n, "f32", chi=chi, eps_im=eps_im, cpw=cpw)
+    m = 8 if n == 40 else 30
+    ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, m, 1, orth="dcgs2")
+    dx, info = run_gpu(spec, src, "f32", xw, rhs, m, 1)
+    assert info["krylov_iters"] == rinfo.iters == m
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= 1e-5 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("nx,ny,prec,m,tol", [(37, 29, "f64", 8, 1e-9), (37, 29, "f32", 8, 1e-5),
+                                              (3, 3, "f64", 2, 1e-12), (4, 3, "f32", 4, 1e-5)])
+def test_kerr_cslp_gmres_sizes(nx, ny, prec, m, tol):
+    """An odd width (the one-column-per-thread path); the smallest grids (one or two interior
+    nodes: 2 and 4 real interior unknowns)."""
+    spec, src, p, xw, rhs = kerr_case(nx, ny, prec)
+    ref, rinfo, _ = oracle_gmres(p, xw, rhs, src, m, 1)
+    dx, info = run_gpu(spec, src, prec, xw, rhs, m, 1, orth="dcgs2" if nx > 4 else "cgs2")
+    assert info["krylov_iters"] == rinfo.iters, (info["krylov_iters"], rinfo.iters)
+    d = host(dx)
+    assert np.linalg.norm(d - ref) <= tol * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,slack", [("kerr12x10_cpw32_chi1.0_cslp", 0.3), ("kerr64_chi0.1_cslp", 0.15)])
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_newton_kerr_cslp(name, slack, orth):
+    """Newton from E = 0 with the preconditioner, per iterate, at FACTOR times the oracle's
+    own summation-order spread (order_spread); 64 x 64 is the Helmholtz-Kerr workload's
+    physics (k0 = 2 pi / 64 cells, eps_L = 1, chi3 = 0.1)."""
+    import order_spread as OS
+
+    spec, xp, src, opts, _, _, _ = OS.case(name)
+    tol, tol_x = OS.gpu_bounds(name)
+    info, ref = compare_newton(spec, xp, src, "f64", "ad", tol, tol_x=tol_x, orth=orth, krylov_slack=slack,
+                               **opts)
+    assert info["converged"] and ref.converged
 
 
 def test_cslp_rejected_configurations():
