@@ -389,16 +389,16 @@ __device__ __forceinline__ void project_accumulate(const StencilArgs<T, VT>& a, 
 }
 
 // acc[q] += V_q . o over the R rows `rows` (column cc) of this thread, for
-// q < a.K, starting at vector q0.  The rows of G basis vectors are loaded
+// q < a.K, starting at vector Q0.  The rows of G basis vectors are loaded
 // together before any is used (G chosen for about 256 bytes in flight per
 // lane; a load-use pair per vector and row would leave the pass waiting on one
 // memory round trip after another).
-template <class P, class T, class VT, int VEC, int R, int G, int KDOT>
+template <class P, class T, class VT, int VEC, int R, int G, int KDOT, int Q0 = 0>
 __device__ __forceinline__ void project_rows(const StencilArgs<T, VT>& a, int nx, int cc, const int (&rows)[R],
-                                             const T (&o)[R][P::NF][VEC], double (&acc)[KDOT + 1], int q0 = 0) {
+                                             const T (&o)[R][P::NF][VEC], double (&acc)[KDOT + 1]) {
 #pragma unroll
-  for (int qb = 0; qb < KDOT; qb += G) {
-    if (qb >= q0 && qb < a.K) {
+  for (int qb = Q0; qb < KDOT; qb += G) {
+    if (qb < a.K) {
       VT vq[G][R][P::NF][VEC];
       project_load<P, T, VT, VEC, R, G>(a, nx, cc, rows, qb, vq);
       project_accumulate<P, T, VT, VEC, R, G, KDOT>(a, qb, vq, o, acc);
@@ -463,9 +463,10 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
   // tile (it needs only the tile's position), so that its round trip
   // overlaps the stencil arithmetic instead of following it; while all rows
   // are projected at once and the group fits 64 registers per lane
-  constexpr int kPreRegs = kProjGroup * PR * NF * VEC * ((int)sizeof(VT) >= 4 ? (int)sizeof(VT) / 4 : 1);
-  constexpr bool kPre = OP != OP_RES && KDOT > 0 && KDOT <= 16 && kProjAll && kPreRegs <= 64;
-  constexpr int kPreGroup = kProjGroup;
+  // (FP16 basis values take a register each: the group is cut to fit)
+  constexpr int kPreVecRegs = PR * NF * VEC * ((int)sizeof(VT) >= 4 ? (int)sizeof(VT) / 4 : 1);
+  constexpr int kPreGroup = 64 / kPreVecRegs < kProjGroup ? 64 / kPreVecRegs : kProjGroup;
+  constexpr bool kPre = OP != OP_RES && KDOT > 0 && KDOT <= 16 && kProjAll && kPreGroup >= 1;
   VT vpre[kPre ? kPreGroup : 1][kPre ? PR : 1][NF][VEC];
   // Arnoldi JVP of the delayed form: the loads of the column completion in
   // the prologue go out first, then the first tile's (in-bounds either way;
@@ -692,7 +693,7 @@ stencil_kernel(const StencilArgs<T, VT> a, const Coefs coefs) {
       if constexpr (kPre) {
         if (pre) {
           project_accumulate<P, T, VT, VEC, RC, kPreGroup, KDOT>(a, 0, vpre, po, acc);
-          project_rows<P, T, VT, VEC, RC, kProjGroup, KDOT>(a, nx, pcc, prow, po, acc, kPreGroup);
+          project_rows<P, T, VT, VEC, RC, kProjGroup, KDOT, kPreGroup>(a, nx, pcc, prow, po, acc);
           return;
         }
       }
