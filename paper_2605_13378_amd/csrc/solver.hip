@@ -542,35 +542,43 @@ struct Impl {
       constexpr bool fp16 = !std::is_same<T, VT>::value;
       JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->n, fp16 ? 1 : 0, s->stream));
       if (fp16) JFNK_HIP(s, launch_store_basis0<T, VT>(s->npad, w, basis(s, 0), s->ctl, sgrid, s->stream));
-      JFNK_TRY(sync_read_ctl(s));
-      if (pending_vy) {
-        pending_vy = false;
-        const int k = s->hctl->k_last;
-        if (s->prof) {
-          for (ProfRec& r : s->recs)
-            if (r.kid == PK_VY) r.bytes = (double)s->n * (k * sizeof(VT) + (cycle == 1 ? 1.0 : 2.0) * sizeof(T));
-          prof_harvest(s, k);
+      // The first cycle's start is not read back: its Arnoldi steps are
+      // queued at once, and if the start already stopped the cycle (a zero
+      // or non-finite right-hand side) they leave at once on the device and
+      // the V y update writes dx = 0 with k = 0; the next cycle's start
+      // reads both back (one synchronization fewer per solve).
+      if (cycle > 0 || max_restarts == 0) {
+        JFNK_TRY(sync_read_ctl(s));
+        if (pending_vy) {
+          pending_vy = false;
+          const int k = s->hctl->k_last;
+          if (s->prof) {
+            for (ProfRec& r : s->recs)
+              if (r.kid == PK_VY) r.bytes = (double)s->n * (k * sizeof(VT) + (cycle == 1 ? 1.0 : 2.0) * sizeof(T));
+            prof_harvest(s, k);
+          }
+          go.iters += k;
+          if (k == 0) go.cycles -= 1;  // the cycle stopped at its start: not a cycle run
+          if (k > 0 && s->hctl->k_last_state == kNonfinite) {
+            go.nonfinite = true;
+            break;
+          }
+        } else if (s->prof) {
+          prof_harvest(s, 0);
         }
-        go.iters += k;
-        if (k > 0 && s->hctl->k_last_state == kNonfinite) {
+        if (cycle <= 1) go.bnorm = s->hctl->bnorm;  // written by the first cycle's start only
+        go.true_res = s->hctl->beta;
+        const int d0 = s->hctl->done_col[0];
+        if (d0 == kNonfinite) {
           go.nonfinite = true;
           break;
         }
-      } else if (s->prof) {
-        prof_harvest(s, 0);
+        if (d0 == kConverged) {
+          go.converged = true;
+          break;
+        }
+        if (cycle == max_restarts) break;
       }
-      if (cycle == 0) go.bnorm = s->hctl->bnorm;
-      go.true_res = s->hctl->beta;
-      const int d0 = s->hctl->done_col[0];
-      if (d0 == kNonfinite) {
-        go.nonfinite = true;
-        break;
-      }
-      if (d0 == kConverged) {
-        go.converged = true;
-        break;
-      }
-      if (cycle == max_restarts) break;
       go.cycles += 1;
       // Arnoldi steps back to back; the Givens update of column j runs in the
       // prologue of step j+1's JVP and reports its stop flag to mapped host
