@@ -248,6 +248,12 @@ def test_gmres_restart_cap_and_zero_rhs():
     assert np.linalg.norm(host(dx) - ref) <= 1e-12 * np.linalg.norm(ref)
     dx0, info0 = s.gmres(dev(xp, wdtype("f64")), dev(np.zeros(p.n), wdtype("f64")), tol=1e-8)
     assert info0["converged"] and info0["krylov_iters"] == 0 and not host(dx0).any()
+    # the first cycle's start is not read back: its steps leave on the device and are not
+    # counted as a cycle run
+    assert info0["restarts"] == 0
+    # no cycle allowed: no iterations, dx = 0
+    dxn, infn = s.gmres(dev(xp, wdtype("f64")), dev(rhs, wdtype("f64")), m=4, tol=1e-14, max_restarts=0)
+    assert not infn["converged"] and infn["krylov_iters"] == 0 and infn["restarts"] == 0 and not host(dxn).any()
 
 
 def test_nonfinite_and_not_converged_statuses():
