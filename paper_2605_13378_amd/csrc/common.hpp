@@ -257,6 +257,15 @@ __device__ __forceinline__ double halve_step(double x, double y, int lane) {
   }
 }
 
+// Lane i's copy of a 64-bit value (i uniform across the wavefront; every
+// lane active).
+__device__ __forceinline__ double lane_f64(double v, int i) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffLL), i);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), i);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Sums of M values (a power of two, at most 32) over the 64 lanes of a
 // wavefront, transposed: lane l returns the sum of value l >> (6 - log2 M).
 // log2 M halving steps (M - 1 exchanges in all) and plain pair sums for the

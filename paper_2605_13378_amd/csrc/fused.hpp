@@ -375,24 +375,38 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           double wn2 = 0.0;
           block_sum2(sw, 0.0, sc, wn2, dummy);
           const double wn = sqrt(wn2);
-          // Givens rotations of column j (one thread), stop tests published in LDS
-          if (tid == 0) {
+          // Givens rotations of column j (wavefront 0: the finiteness test
+          // one entry per lane, the rotation chain on lane 0), stop tests
+          // published in LDS
+          if (tid < kWave) {
             double* __restrict__ col = H + (size_t)j * (m + 1);
             const double* __restrict__ csr = cs;
             const double* __restrict__ snr = sn;
-            col[K] = wn;
-            bool ok = isfinite(wn);
-            for (int i = 0; i < K; ++i) ok = ok && isfinite(col[i]);
-            if (ok) {
+            const bool bad = tid < K && !isfinite(col[tid]);
+            const bool ok = isfinite(wn) && __any(bad) == 0;
+            if (tid == 0) col[K] = wn;
+            if (tid == 0 && ok) {
               // previous rotations; the entry being rotated down the column
-              // stays in a register (cur), the untouched entries are loads
-              // off the dependency chain
+              // stays in a register (cur), the untouched entries are read
+              // four at a time, off the dependency chain
               double cur = col[0];
-              for (int i = 0; i < j; ++i) {
-                const double nxt = col[i + 1];
-                const double ci = csr[i], si = snr[i];
-                col[i] = ci * cur + si * nxt;
-                cur = -si * cur + ci * nxt;
+              for (int i0 = 0; i0 < j; i0 += 4) {
+                double hb[4], cb[4], sb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const int i = i0 + u < j ? i0 + u : j - 1;  // in bounds; slots past j unused
+                  hb[u] = col[i + 1];
+                  cb[u] = csr[i];
+                  sb[u] = snr[i];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  if (i0 + u < j) {
+                    const double nxt = hb[u];
+                    col[i0 + u] = cb[u] * cur + sb[u] * nxt;
+                    cur = -sb[u] * cur + cb[u] * nxt;
+                  }
+                }
               }
               const double ha = cur, hb = col[j + 1];
               double c = 1.0, s = 0.0;
@@ -409,7 +423,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
               g[j] = c * g[j];
               sc[S_EST] = fabs(g[j + 1]);
             }
-            sc[S_FLAG] = ok ? 0.0 : 1.0;
+            if (tid == 0) sc[S_FLAG] = ok ? 0.0 : 1.0;
           }
           __syncthreads();
           if (sc[S_FLAG] != 0.0) {
@@ -424,12 +438,15 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           __syncthreads();
         }
         if (nonfinite) break;
-        // y = R^{-1} g (back substitution), dx += V y
-        if (tid == 0) {
+        // y = R^{-1} g (back substitution by columns on wavefront 0: lane l
+        // keeps row l's partial sum; each y_i, once divided out, is removed
+        // from the rows above it in one step), dx += V y
+        if (tid < kWave) {
+          double t = tid < kk ? g[tid] : 0.0;
           for (int i = kk - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int l = i + 1; l < kk; ++l) t -= H[i + (size_t)l * (m + 1)] * yv[l];
-            yv[i] = t / H[i + (size_t)i * (m + 1)];
+            const double yi = lane_f64(t, i) / H[i + (size_t)i * (m + 1)];
+            if (tid == i) yv[i] = yi;
+            if (tid < i) t -= H[tid + (size_t)i * (m + 1)] * yi;
           }
         }
         __syncthreads();
