@@ -102,8 +102,8 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* sc, doubl
 }
 
 // out[i] = V_i . w for i < K (FP64 accumulation): G lanes of one wavefront
-// per vector (G a power of two, G * K <= threads), then a reduction inside
-// each lane group (group_sum).  Vector i starts at V + i * ldv; the padded stride puts
+// per vector (G a power of two, G * K <= threads), each with four partial
+// sums, then a reduction inside each lane group (group_sum).  Vector i starts at V + i * ldv; the padded stride puts
 // the lane groups of one wavefront on different LDS banks.  Barriers on
 // entry (earlier readers of `out`) and exit.
 template <class T>
@@ -114,13 +114,37 @@ __device__ __forceinline__ void block_dots(const T* V, int n, int ldv, int K, co
   const int g = threadIdx.x % G;
   double s = 0.0;
   if (i < K) {
+    // four partial sums: a dependency chain a quarter as long
     const T* v = V + (size_t)i * ldv;
-    for (int e = g; e < n; e += G) s += (double)v[e] * (double)w[e];
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int e = g;
+    for (; e + 3 * G < n; e += 4 * G) {
+      s += (double)v[e] * (double)w[e];
+      s1 += (double)v[e + G] * (double)w[e + G];
+      s2 += (double)v[e + 2 * G] * (double)w[e + 2 * G];
+      s3 += (double)v[e + 3 * G] * (double)w[e + 3 * G];
+    }
+    for (; e < n; e += G) s += (double)v[e] * (double)w[e];
+    s = (s + s1) + (s2 + s3);
   }
   s = group_sum_rt(s, G);
   __syncthreads();
   if (i < K && g == 0) out[i] = s;
   __syncthreads();
+}
+
+// w_e - sum_i h_i V_i[e] over i < K, as two interleaved chains of
+// products (half the dependency length), subtracted at the end.
+template <class T>
+__device__ __forceinline__ T cgs_update(T we, const double* hv, const T* V, int ldv, int K, int e) {
+  T a = we, b = T(0);
+  int i = 0;
+  for (; i + 1 < K; i += 2) {
+    a = a - T(hv[i]) * V[(size_t)i * ldv + e];
+    b = b + T(hv[i + 1]) * V[(size_t)(i + 1) * ldv + e];
+  }
+  if (i < K) a = a - T(hv[i]) * V[(size_t)i * ldv + e];
+  return a - b;
 }
 
 template <class P, class T>
@@ -355,19 +379,14 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           jvp(V + (size_t)j * ldv, 1.0, jn2);
           // classical Gram-Schmidt, first pass: h = V^T w, w -= V h
           block_dots<T>(V, n, ldv, K, w, hv);
-          for (int e = tid; e < n; e += kFusedThreads) {
-            T acc = w[e];
-            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * ldv + e];
-            w[e] = acc;
-          }
+          for (int e = tid; e < n; e += kFusedThreads) w[e] = cgs_update<T>(w[e], hv, V, ldv, K, e);
           if (tid < K) H[tid + (size_t)j * (m + 1)] = hv[tid];
           __syncthreads();
           // second pass: h2 = V^T w, w -= V h2, ||w||^2
           block_dots<T>(V, n, ldv, K, w, hv);
           double sw = 0.0;
           for (int e = tid; e < n; e += kFusedThreads) {
-            T acc = w[e];
-            for (int i = 0; i < K; ++i) acc = acc - T(hv[i]) * V[(size_t)i * ldv + e];
+            const T acc = cgs_update<T>(w[e], hv, V, ldv, K, e);
             w[e] = acc;
             sw += (double)acc * (double)acc;
           }
@@ -375,53 +394,45 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           double wn2 = 0.0;
           block_sum2(sw, 0.0, sc, wn2, dummy);
           const double wn = sqrt(wn2);
-          // Givens rotations of column j (wavefront 0: the finiteness test
-          // one entry per lane, the rotation chain on lane 0), stop tests
-          // published in LDS
+          // Givens rotations of column j on wavefront 0: lane i holds entry i
+          // of the column and rotation i (all read at once); the chain runs
+          // on every lane alike, taking rotation i and entry i + 1 from lane
+          // i, and lane i keeps its rotated entry; stop tests published in LDS
           if (tid < kWave) {
             double* __restrict__ col = H + (size_t)j * (m + 1);
-            const double* __restrict__ csr = cs;
-            const double* __restrict__ snr = sn;
-            const bool bad = tid < K && !isfinite(col[tid]);
-            const bool ok = isfinite(wn) && __any(bad) == 0;
-            if (tid == 0) col[K] = wn;
-            if (tid == 0 && ok) {
-              // previous rotations; the entry being rotated down the column
-              // stays in a register (cur), the untouched entries are read
-              // four at a time, off the dependency chain
-              double cur = col[0];
-              for (int i0 = 0; i0 < j; i0 += 4) {
-                double hb[4], cb[4], sb[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  const int i = i0 + u < j ? i0 + u : j - 1;  // in bounds; slots past j unused
-                  hb[u] = col[i + 1];
-                  cb[u] = csr[i];
-                  sb[u] = snr[i];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  if (i0 + u < j) {
-                    const double nxt = hb[u];
-                    col[i0 + u] = cb[u] * cur + sb[u] * nxt;
-                    cur = -sb[u] * cur + cb[u] * nxt;
-                  }
-                }
+            const double hl = tid < K ? col[tid] : 0.0;
+            const double cl = tid < j ? cs[tid] : 0.0;
+            const double sl = tid < j ? sn[tid] : 0.0;
+            const bool ok = isfinite(wn) && __any(tid < K && !isfinite(hl)) == 0;
+            if (ok) {
+              double cur = lane_f64(hl, 0);
+              double mine = hl;
+              for (int i = 0; i < j; ++i) {
+                const double nxt = lane_f64(hl, i + 1);
+                const double ci = lane_f64(cl, i), si = lane_f64(sl, i);
+                const double v = ci * cur + si * nxt;
+                cur = -si * cur + ci * nxt;
+                if (tid == i) mine = v;
               }
-              const double ha = cur, hb = col[j + 1];
-              double c = 1.0, s = 0.0;
-              if (hb != 0.0) {
-                const double r = hypot(ha, hb);
-                c = ha / r;
-                s = hb / r;
+              if (tid < j) col[tid] = mine;
+              if (tid == 0) {
+                const double ha = cur, hb = wn;
+                double c = 1.0, s = 0.0;
+                if (hb != 0.0) {
+                  const double r = hypot(ha, hb);
+                  c = ha / r;
+                  s = hb / r;
+                }
+                cs[j] = c;
+                sn[j] = s;
+                col[j] = c * ha + s * hb;
+                col[j + 1] = 0.0;
+                g[j + 1] = -s * g[j];
+                g[j] = c * g[j];
+                sc[S_EST] = fabs(g[j + 1]);
               }
-              cs[j] = c;
-              sn[j] = s;
-              col[j] = c * ha + s * hb;
-              col[j + 1] = 0.0;
-              g[j + 1] = -s * g[j];
-              g[j] = c * g[j];
-              sc[S_EST] = fabs(g[j + 1]);
+            } else if (tid == 0) {
+              col[K] = wn;
             }
             if (tid == 0) sc[S_FLAG] = ok ? 0.0 : 1.0;
           }
