@@ -395,9 +395,12 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           block_sum2(sw, 0.0, sc, wn2, dummy);
           const double wn = sqrt(wn2);
           // Givens rotations of column j on wavefront 0: lane i holds entry i
-          // of the column and rotation i (all read at once); the chain runs
-          // on every lane alike, taking rotation i and entry i + 1 from lane
-          // i, and lane i keeps its rotated entry; stop tests published in LDS
+          // of the column and rotation i (all read at once).  Rotation i maps
+          // the entry carried down the column, cur_i, to
+          // cur_{i+1} = -s_i cur_i + c_i h_{i+1}, an affine map; a scan of
+          // their compositions across the lanes (log2 j steps) gives every
+          // lane its cur_i at once, and lane i forms its rotated entry
+          // c_i cur_i + s_i h_{i+1}.  Stop tests published in LDS.
           if (tid < kWave) {
             double* __restrict__ col = H + (size_t)j * (m + 1);
             const double hl = tid < K ? col[tid] : 0.0;
@@ -405,16 +408,23 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
             const double sl = tid < j ? sn[tid] : 0.0;
             const bool ok = isfinite(wn) && __any(tid < K && !isfinite(hl)) == 0;
             if (ok) {
-              double cur = lane_f64(hl, 0);
-              double mine = hl;
-              for (int i = 0; i < j; ++i) {
-                const double nxt = lane_f64(hl, i + 1);
-                const double ci = lane_f64(cl, i), si = lane_f64(sl, i);
-                const double v = ci * cur + si * nxt;
-                cur = -si * cur + ci * nxt;
-                if (tid == i) mine = v;
+              const double h0 = lane_f64(hl, 0);
+              const double hnext = __shfl_down(hl, 1);  // h_{i+1} on lane i
+              // f_i(x) = A x + B on lanes i < j, the identity above
+              double A = tid < j ? -sl : 1.0;
+              double B = tid < j ? cl * hnext : 0.0;
+              for (int d = 1; d < j; d <<= 1) {
+                const double Ap = __shfl_up(A, d), Bp = __shfl_up(B, d);
+                if (tid >= d) {
+                  B = A * Bp + B;
+                  A = A * Ap;
+                }
               }
-              if (tid < j) col[tid] = mine;
+              // lane i: f_i o ... o f_0; cur_i from lane i - 1's composition
+              const double Ap = __shfl_up(A, 1), Bp = __shfl_up(B, 1);
+              const double cur_i = tid == 0 ? h0 : Ap * h0 + Bp;
+              if (tid < j) col[tid] = cl * cur_i + sl * hnext;
+              const double cur = j == 0 ? h0 : lane_f64(A, j - 1) * h0 + lane_f64(B, j - 1);
               if (tid == 0) {
                 const double ha = cur, hb = wn;
                 double c = 1.0, s = 0.0;
