@@ -409,9 +409,26 @@ struct Impl {
 
   struct GOut {
     bool converged = false, nonfinite = false;
+    // the Newton trial point x + dx and its residual norms were queued
+    // before the solve's last synchronization and read back with it
+    bool trial_done = false;
     int iters = 0, cycles = 0;
     double bnorm = 0.0, true_res = 0.0;
   };
+
+  // Newton trial point x64t = x64 + alpha dx (and its working copy), then its
+  // residual Ft with the norms ||Ft||^2, ||xt||^2 into the control block.
+  static jfnk_status queue_trial(jfnk_solver* s, double alpha, int sgrid) {
+    constexpr bool f64 = std::is_same<T, double>::value;
+    {
+      ProfScope ps(s, PK_TRIAL, (double)s->n * (16.0 + sizeof(T) + (f64 ? 0.0 : sizeof(T))));
+      JFNK_HIP(s, launch_trial<T>(s->npad, s->x64, static_cast<const T*>(s->dx), alpha, s->x64t,
+                                  f64 ? nullptr : static_cast<T*>(s->xwt), sgrid, s->stream));
+    }
+    const T* xt = f64 ? reinterpret_cast<const T*>(s->x64t) : static_cast<const T*>(s->xwt);
+    JFNK_TRY(residual(s, xt, static_cast<T*>(s->Ft), true));
+    return JFNK_OK;
+  }
 
   static VT* basis(jfnk_solver* s, int i) { return static_cast<VT*>(s->V) + (long long)i * s->vstride; }
 
@@ -506,9 +523,15 @@ struct Impl {
   // iterate z and the basis live in the preconditioned space and the
   // residual, its norm and the stopping tests are those of J dx = sign * R;
   // dx = M^{-1} z at the end.
+  // spec_trial (Newton, AD JVP, no preconditioner): the second cycle's start,
+  // where a solve that converged in one cycle ends, also queues the Newton
+  // trial point with alpha = 1 and its residual, so that one synchronization
+  // reads back both (go.trial_done); if the solve goes on they are discarded
+  // (scratch vectors and residual norms only: no kernel of the solve reads
+  // them, which is why the FD JVP, whose step reads ||x||, is left out).
   static jfnk_status gmres(jfnk_solver* s, const T* x, const T* R, double sign, int m, double tol, int max_restarts,
                            int mode, double fixed_eps, int eps_rule, double brk, GOut& go, bool lagged = false,
-                           bool pre = false) {
+                           bool pre = false, bool spec_trial = false) {
     go = GOut{};
     T* dxi = static_cast<T*>(s->dx);
     T* w = static_cast<T*>(s->w);
@@ -527,7 +550,9 @@ struct Impl {
     // cycle's start (one synchronization per cycle): its k and stop state sit
     // in fields the cycle start leaves alone.
     bool pending_vy = false;
+    int spec_cycle = -1, last_cycle = 0;
     for (int cycle = 0;; ++cycle) {
+      last_cycle = cycle;
       const T* wr = nullptr;
       s->cur_step = -1;
       if (cycle > 0) {
@@ -542,6 +567,10 @@ struct Impl {
       constexpr bool fp16 = !std::is_same<T, VT>::value;
       JFNK_HIP(s, launch_cycle_begin(s->ctl, parts(s, 3, sgrid), m, s->n, fp16 ? 1 : 0, s->stream));
       if (fp16) JFNK_HIP(s, launch_store_basis0<T, VT>(s->npad, w, basis(s, 0), s->ctl, sgrid, s->stream));
+      if (spec_trial && !pre && cycle == 1) {
+        JFNK_TRY(queue_trial(s, 1.0, sgrid));
+        spec_cycle = cycle;
+      }
       // The first cycle's start is not read back: its Arnoldi steps are
       // queued at once, and if the start already stopped the cycle (a zero
       // or non-finite right-hand side) they leave at once on the device and
@@ -617,6 +646,7 @@ struct Impl {
       updated = true;
       pending_vy = true;
     }
+    go.trial_done = spec_cycle >= 0 && spec_cycle == last_cycle;
     if (!updated) JFNK_HIP(s, launch_fill_zero<T>(s->npad, dxi, sgrid, s->stream));
     if (pre && updated)
       JFNK_HIP(s, launch_cslp_apply<T>(s->pid, x, dxi, s->prob.nx, s->prob.ny, s->coefs, sgrid, s->stream));
@@ -967,7 +997,7 @@ struct Impl {
       } else {
         JFNK_TRY(gmres(s, cur_x(), static_cast<const T*>(s->F), -1.0, o.m, o.tol_krylov, o.max_restarts, o.mode,
                        o.fd_eps, o.eps_rule, o.breakdown_tol, go, o.orth == JFNK_ORTH_DCGS2,
-                       o.precond == JFNK_PRECOND_CSLP));
+                       o.precond == JFNK_PRECOND_CSLP, o.mode == JFNK_JVP_AD));
       }
       info->krylov_iters += go.iters;
       info->restarts += go.cycles;
@@ -980,15 +1010,12 @@ struct Impl {
       double ft = 0.0;
       bool accepted = false;
       for (int t = 0; t <= o.ls_max_backtracks; ++t) {
-        {
-          ProfScope ps(s, PK_TRIAL, (double)n * (16.0 + sizeof(T) + (f64 ? 0.0 : sizeof(T))));
-          JFNK_HIP(s, launch_trial<T>(s->npad, s->x64, static_cast<const T*>(s->dx), alpha, s->x64t,
-                                      f64 ? nullptr : static_cast<T*>(s->xwt), sgrid, s->stream));
+        // the full step's trial may have been read back with the linear solve
+        if (t > 0 || !go.trial_done) {
+          JFNK_TRY(queue_trial(s, alpha, sgrid));
+          JFNK_TRY(sync_read_ctl(s));
+          if (s->prof) prof_harvest(s, 0);
         }
-        const T* xt = f64 ? reinterpret_cast<const T*>(s->x64t) : static_cast<const T*>(s->xwt);
-        JFNK_TRY(residual(s, xt, static_cast<T*>(s->Ft), true));
-        JFNK_TRY(sync_read_ctl(s));
-        if (s->prof) prof_harvest(s, 0);
         ft = std::sqrt(s->hctl->fnorm2);
         if (std::isfinite(ft) && ft <= (1.0 - o.ls_c * alpha) * fk) {
           accepted = true;
