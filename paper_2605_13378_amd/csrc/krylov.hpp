@@ -896,17 +896,18 @@ __global__ void __launch_bounds__(512) vy_kernel(const VyArgs<T, VT> a) {
   }
   if (tid < k) gr[tid] = (pending && tid == k - 1) ? 0.0 : ctl->gr[tid];
   __syncthreads();
-  if (tid == 0) {
-    for (int i = k - 1; i >= 0; --i) {
-      double s = (pending && i == k - 1) ? lastgr : gr[i];
-      for (int l = i + 1; l < k; ++l) {
-        const double r = (pending && l == k - 1) ? lastcol[i] : R[l * kMaxM + i];
-        s -= r * y[l];
-      }
-      const double d = (pending && i == k - 1) ? lastcol[i] : R[i * kMaxM + i];
-      y[i] = s / d;
+  // y = R^{-1} g by columns on the first wavefront: lane i keeps row i's
+  // partial sum, and each y_l, once divided out, is taken out of the rows
+  // above it in one step (k dependent steps, not k^2 / 2)
+  if (tid < kWave) {
+    double t = tid < k ? ((pending && tid == k - 1) ? lastgr : gr[tid]) : 0.0;
+    for (int l = k - 1; l >= 0; --l) {
+      const bool last = pending && l == k - 1;  // the column this kernel completed itself
+      const double yl = lane_f64(t, l) / (last ? lastcol[l] : R[l * kMaxM + l]);
+      if (tid == l) y[l] = yl;
+      if (tid < l) t -= (last ? lastcol[tid] : R[l * kMaxM + tid]) * yl;
     }
-    if (blockIdx.x == 0) {
+    if (tid == 0 && blockIdx.x == 0) {
       ctl->k = k;
       ctl->k_last = k;
       ctl->k_last_state = k == 0 ? kRunning : (pending ? lastdone : flags[k]);
