@@ -97,7 +97,9 @@ def test_newton_burgers1d_config_f64_ad(engine):
 
 # Single-workgroup engine (the whole solve in one launch, vectors in LDS) on
 # problems small enough for it, at the same per-iterate bounds as the
-# multi-kernel path.
+# multi-kernel path.  The last three are the largest 1D sizes whose LDS
+# footprint fits one workgroup's 160 KB (n = 480 in FP64, 896 in FP32) and a
+# ragged 2D grid, each with more unknowns than the workgroup has threads.
 @pytest.mark.parametrize("kind,nx,ny,prec,mode,rule,tol", [
     ("burgers1d", 256, None, "f32", "ad", "paper", 1e-5),
     ("burgers1d", 256, None, "f64", "fd", "paper", 1e-7),
@@ -106,6 +108,9 @@ def test_newton_burgers1d_config_f64_ad(engine):
     ("grayscott", 16, 16, "f32", "ad", "paper", 1e-5),
     ("burgers2d", 12, 10, "f64", "ad", "paper", 1e-12),
     ("burgers2d", 12, 10, "f64", "fd", "paper", 1e-7),
+    ("burgers1d", 480, None, "f64", "ad", "paper", 1e-12),
+    ("burgers1d", 896, None, "f32", "ad", "paper", 1e-5),
+    ("grayscott", 21, 19, "f32", "ad", "paper", 1e-5),
 ])
 def test_newton_single_workgroup(kind, nx, ny, prec, mode, rule, tol):
     if kind == "burgers1d":
