@@ -397,6 +397,11 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           double wn2 = 0.0;
           block_sum2(sw, 0.0, sc, wn2, dummy);
           const double wn = sqrt(wn2);
+          // the next basis vector, written by the other wavefronts while
+          // wavefront 0 rotates the column (left unused if the cycle stops
+          // at this step)
+          if (tid >= kWave)
+            for (int e = tid - kWave; e < n; e += kFusedThreads - kWave) V[(size_t)K * ldv + e] = T((double)w[e] / wn);
           // Givens rotations of column j on wavefront 0: lane i holds entry i
           // of the column and rotation i (all read at once).  Rotation i maps
           // the entry carried down the column, cur_i, to
@@ -458,8 +463,6 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
           iters += 1;
           if (sc[S_EST] <= target) break;
           if (wn <= a.o.brk * sqrt(jn2)) break;
-          for (int e = tid; e < n; e += kFusedThreads) V[(size_t)K * ldv + e] = T((double)w[e] / wn);
-          __syncthreads();
         }
         if (nonfinite) break;
         // y = R^{-1} g (back substitution by columns on wavefront 0: lane l
