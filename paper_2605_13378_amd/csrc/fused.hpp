@@ -150,6 +150,18 @@ __device__ __forceinline__ T cgs_update(T we, const double* hv, const T* V, int 
   return a - b;
 }
 
+// One Hillis-Steele step of the Givens scan inside rows of 16 lanes: lane l
+// composes its map with that of lane l - D (DPP row shift, no LDS round
+// trip) when take is set, the composition order being the scan's.
+template <int D>
+__device__ __forceinline__ void affine_scan_step(double& A, double& B, bool take) {
+  const double Ap = dpp_f64<0x110 + D>(A), Bp = dpp_f64<0x110 + D>(B);  // row_shr:D
+  if (take) {
+    B = A * Bp + B;
+    A = A * Ap;
+  }
+}
+
 template <class P, class T>
 __device__ __forceinline__ int at(int f, int c, int cells) {
   return P::kInterleaved ? 2 * c + f : f * cells + c;
@@ -417,19 +429,28 @@ __global__ void __launch_bounds__(kFusedThreads) fused_solve_kernel(const FusedA
             const bool ok = isfinite(wn) && __any(tid < K && !isfinite(hl)) == 0;
             if (ok) {
               const double h0 = lane_f64(hl, 0);
-              const double hnext = __shfl_down(hl, 1);  // h_{i+1} on lane i
-              // f_i(x) = A x + B on lanes i < j, the identity above
+              const double hnext = dpp_f64<0x130>(hl);  // wave_shl:1: h_{i+1} on lane i
+              // f_i(x) = A x + B on lanes i < j, the identity above; the
+              // scan runs within rows of 16 lanes (shifts 1, 2, 4, 8), then
+              // row 1 composes with row 0's total, lane 15's (row_bcast:15):
+              // j <= 31, so lanes 32-63 are never read
               double A = tid < j ? -sl : 1.0;
               double B = tid < j ? cl * hnext : 0.0;
-              for (int d = 1; d < j; d <<= 1) {
-                const double Ap = __shfl_up(A, d), Bp = __shfl_up(B, d);
-                if (tid >= d) {
+              const int r = tid & 15;
+              if (j > 1) affine_scan_step<1>(A, B, r >= 1);
+              if (j > 2) affine_scan_step<2>(A, B, r >= 2);
+              if (j > 4) affine_scan_step<4>(A, B, r >= 4);
+              if (j > 8) affine_scan_step<8>(A, B, r >= 8);
+              if (j > 16) {
+                const double Ap = dpp_f64<0x142>(A), Bp = dpp_f64<0x142>(B);
+                if (tid >= 16 && tid < 32) {
                   B = A * Bp + B;
                   A = A * Ap;
                 }
               }
               // lane i: f_i o ... o f_0; cur_i from lane i - 1's composition
-              const double Ap = __shfl_up(A, 1), Bp = __shfl_up(B, 1);
+              // (wave_shr:1)
+              const double Ap = dpp_f64<0x138>(A), Bp = dpp_f64<0x138>(B);
               const double cur_i = tid == 0 ? h0 : Ap * h0 + Bp;
               if (tid < j) col[tid] = cl * cur_i + sl * hnext;
               const double cur = j == 0 ? h0 : lane_f64(A, j - 1) * h0 + lane_f64(B, j - 1);
